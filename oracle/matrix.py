@@ -1,0 +1,156 @@
+"""Matrix side of the method (paper Sec. 3, eqs. equ:ExpoMatRat and equ:expAx).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The library approximates exp(tA)V for Hermitian A by R_d(tA)V, where
+R_d(z) = 1/exp_d(-z).  The method reaches R_d(tA)V exactly up to rounding, and
+that result has a plain definition as a matrix function of a Hermitian matrix
+(the paper extends any scalar approximation to diagonalizable matrices through
+the eigendecomposition, Sec. 1):
+
+    R_d(tA) V = U diag(1/exp_d(-t w_i)) U^H V,     A = U diag(w) U^H.
+
+``expm_R`` writes that definition out; it never uses the partial fractions, so
+the partial-fraction path is checked against an independent computation.
+``expm_exact`` is the same with e^{t w_i}: it measures the approximation error,
+it is not the parity target.
+
+Conventions shared with the library's statement of the problem (not its code):
+* A is given by its lower triangle (the strictly upper part is ignored and the
+  imaginary part of the diagonal is dropped), so the operand is Hermitian by
+  construction;
+* V = None means V = I (the full matrix R_d(tA));
+* arrays are numpy complex128; shapes (n, n) and (n, m).
+
+The remaining functions are other routes to R_d(tA)V used only to pin this
+oracle: exact partial-fraction sum and product form at 50 digits (n <= 8), and
+matrix polynomial evaluation followed by a linear solve.
+"""
+
+from __future__ import annotations
+
+import mpmath
+import numpy as np
+
+from . import scalar
+
+
+def hermitian_from_lower(A: np.ndarray) -> np.ndarray:
+    """The Hermitian matrix whose lower triangle is that of A (diagonal made real)."""
+    A = np.asarray(A, dtype=np.complex128)
+    L = np.tril(A, -1)
+    return L + L.conj().T + np.diag(A.diagonal().real).astype(np.complex128)
+
+
+def _eig(A: np.ndarray):
+    # LAPACK zheevd through numpy, reading the lower triangle only.
+    w, U = np.linalg.eigh(np.asarray(A, dtype=np.complex128), UPLO="L")
+    return w, U
+
+
+def _apply_spectral(U, f, V):
+    """U diag(f) U^H V, with V = None meaning the identity."""
+    if V is None:
+        return (U * f[None, :]) @ U.conj().T
+    V = np.asarray(V, dtype=np.complex128)
+    return U @ (f[:, None] * (U.conj().T @ V))
+
+
+def expm_R(A, V, t: float, d: int, eig=None):
+    """R_d(tA) V by eigendecomposition (the oracle's definition of the result).
+
+    r_i = 1/exp_d(-t w_i) is evaluated directly by Horner (Sec. 2.2).  For
+    t w_i <= 0 every term is positive; eigenvalues with t w_i > 0 lie outside
+    the domain the paper's bounds cover (Sec. 3, Theorem) but are still mapped.
+    ``eig`` may pass a precomputed (w, U) of the same A.
+    """
+    scalar.check_degree(d)
+    w, U = eig if eig is not None else _eig(A)
+    r = scalar.R_direct(t * w, d)
+    return _apply_spectral(U, r, V)
+
+
+def expm_exact(A, V, t: float, eig=None):
+    """exp(tA) V = U diag(e^{t w_i}) U^H V (reported beside parity, never gated)."""
+    w, U = eig if eig is not None else _eig(A)
+    return _apply_spectral(U, np.exp(t * w), V)
+
+
+def rel_fro(X, Y) -> float:
+    """||X - Y||_F / ||Y||_F."""
+    X = np.asarray(X)
+    Y = np.asarray(Y)
+    return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+
+# --------------------------------------------------------------------------
+# routes used only to pin the oracle
+# --------------------------------------------------------------------------
+
+def _mp_matrix(M):
+    return mpmath.matrix([[mpmath.mpc(complex(x)) for x in row] for row in np.asarray(M)])
+
+
+def _solve_cols(M, B):
+    """M^{-1} B column by column (mpmath's LU solve takes one right-hand side)."""
+    out = mpmath.zeros(B.rows, B.cols)
+    for j in range(B.cols):
+        x = mpmath.lu_solve(M, B.column(j))
+        for i in range(B.rows):
+            out[i, j] = x[i]
+    return out
+
+
+def _to_numpy(M) -> np.ndarray:
+    return np.array([[complex(M[i, j]) for j in range(M.cols)] for i in range(M.rows)], dtype=np.complex128)
+
+
+def expm_R_pfd_mp(A, V, t: float, d: int, dps: int = 50):
+    """sum_k a_k (tA + theta_k I)^{-1} V over all d poles at ``dps`` digits (eq. equ:ExpoMatRat / equ:expAx).
+
+    Exact inversion by mpmath LU; for tiny n only (n <= 8).
+    """
+    Ah = hermitian_from_lower(A)
+    n = Ah.shape[0]
+    theta, a = scalar.pfd_full_mp(d)
+    with mpmath.workdps(dps):
+        tA = _mp_matrix(Ah) * mpmath.mpf(t)
+        Vm = mpmath.eye(n) if V is None else _mp_matrix(V)
+        S = mpmath.zeros(n, Vm.cols)
+        for th, ak in zip(theta, a):
+            S += ak * _solve_cols(tA + th * mpmath.eye(n), Vm)
+        return _to_numpy(S)
+
+
+def expm_R_product_mp(A, V, t: float, d: int, dps: int = 50):
+    """d! prod_k (tA + theta_k I)^{-1} V at ``dps`` digits.
+
+    exp_d(-z) = (1/d!) prod_k (z + theta_k) for even d, so R_d(z) = d!/prod_k (z + theta_k):
+    this route uses the roots but no residue, hence no cancellation between residues.
+    """
+    Ah = hermitian_from_lower(A)
+    n = Ah.shape[0]
+    theta, _ = scalar.pfd_full_mp(d)
+    with mpmath.workdps(dps):
+        tA = _mp_matrix(Ah) * mpmath.mpf(t)
+        Y = mpmath.eye(n) if V is None else _mp_matrix(V)
+        for th in theta:
+            Y = _solve_cols(tA + th * mpmath.eye(n), Y)
+        return _to_numpy(Y * mpmath.factorial(d))
+
+
+def expm_R_polysolve(A, V, t: float, d: int):
+    """exp_d(-tA)^{-1} V: matrix Horner in FP64, then one LU solve.
+
+    Uses neither eigenvectors, roots nor residues.  Accuracy degrades with
+    cond(exp_d(-tA)) = exp_d(t rho) for tA <= 0, so pins use small t rho.
+    """
+    Ah = hermitian_from_lower(A)
+    n = Ah.shape[0]
+    Z = -t * Ah
+    I = np.eye(n, dtype=np.complex128)
+    S = I.copy()
+    for k in range(d, 0, -1):
+        S = I + (S @ Z) / k
+    rhs = I if V is None else np.asarray(V, dtype=np.complex128)
+    return np.linalg.solve(S, rhs)
