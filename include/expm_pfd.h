@@ -1,0 +1,156 @@
+/*
+ * expm_pfd.h - C ABI of the MI355X (gfx950) library for exp(tA)V, A Hermitian.
+ *
+ * Method (Hecht, Kaber, Perrin, Plagne, Salomon, "Parallel approximation of the
+ * exponential of Hermitian matrices", arXiv 2306.16778):
+ *   exp(z) is approximated by R_d(z) = 1/exp_d(-z), exp_d the Taylor polynomial
+ *   of even degree d (Sec. 2.2).  Its partial-fraction decomposition
+ *   R_d(z) = sum_k a_k/(z + theta_k) over the d roots theta_k of exp_d
+ *   (Prop. pro:dec, eqs. yoyo and yoyo2) gives, for Hermitian A,
+ *     exp(tA)V ~ R_d(tA)V = sum_k a_k (tA + theta_k I)^{-1} V
+ *   (Sec. 3, eqs. equ:ExpoMatRat and equ:expAx): d independent shifted solves.
+ *   The roots and residues come in d/2 conjugate pairs and, for Hermitian A,
+ *   (tA + conj(theta) I) = (tA + theta I)^H, so one LU factorization serves both
+ *   members of a pair (Remark rem:two_time_real_part): the second solve uses the
+ *   adjoint of the same factors.
+ *
+ * Conventions for every entry point
+ *   - Complex numbers are interleaved (re, im) doubles: C99 double complex /
+ *     std::complex<double> / numpy complex128 layout.
+ *   - Matrices are column-major with a leading dimension (LAPACK convention):
+ *     element (i, j) of A is A[i + j*lda].
+ *   - A is Hermitian and only its LOWER triangle is read (the strictly upper
+ *     part is never accessed; the imaginary part of the diagonal is ignored).
+ *   - Device pointers are HIP device (or managed) memory on the current device.
+ *     The caller owns A, V and X; the library never writes A or V and never
+ *     keeps a pointer to them after the call returns.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on it and the call returns without
+ *     waiting for it, unless the entry point says otherwise.
+ *   - Return value: 0 on success, a negative EXPM_PFD_ERR_* code otherwise.
+ *     Argument errors are detected before any work is enqueued.
+ *   - Spectrum sign is not checked (it would cost an eigensolve).  The error
+ *     bounds of the paper (Prop. pro:err, Theorem of Sec. 3) hold for
+ *     Spec(tA) in (-inf, 0]; for other spectra the result is still
+ *     R_d(tA)V but may be far from exp(tA)V.
+ */
+#ifndef EXPM_PFD_H
+#define EXPM_PFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define EXPM_PFD_OK            0
+#define EXPM_PFD_ERR_DEGREE   -1  /* degree odd, < 2 or > EXPM_PFD_MAX_DEGREE */
+#define EXPM_PFD_ERR_DIM      -2  /* n < 1, n > EXPM_PFD_MAX_N, m < 1 or m > plan's m_max */
+#define EXPM_PFD_ERR_NULL     -3  /* required pointer is NULL */
+#define EXPM_PFD_ERR_LD       -4  /* leading dimension smaller than the row count */
+#define EXPM_PFD_ERR_OOM      -5  /* device allocation failed */
+#define EXPM_PFD_ERR_HIP      -6  /* a HIP runtime call or kernel launch failed */
+#define EXPM_PFD_ERR_ARG      -7  /* other invalid argument (precision, t not finite, ...) */
+#define EXPM_PFD_ERR_CONST    -8  /* root finding for the constants did not converge */
+#define EXPM_PFD_ERR_BUDGET   -9  /* a request can never fit the queue's HBM budget */
+#define EXPM_PFD_ERR_TICKET  -10  /* unknown ticket or matrix id */
+
+#define EXPM_PFD_MAX_DEGREE 64
+#define EXPM_PFD_MAX_N      8192
+
+/* ---- options ------------------------------------------------------------ */
+#define EXPM_PFD_FP64  0  /* LU, solves and accumulation in complex FP64 */
+#define EXPM_PFD_MIXED 1  /* complex FP32 LU and solves on the matrix cores, FP64
+                             iterative refinement of every shifted solve and FP64
+                             residue-weighted accumulation */
+
+typedef struct expm_pfd_opts {
+  int precision;   /* EXPM_PFD_FP64 (default) or EXPM_PFD_MIXED */
+  int ir_sweeps;   /* MIXED: refinement sweeps per solve; <= 0 selects the default (2) */
+  int reserved[6]; /* set to 0 */
+} expm_pfd_opts;
+
+/* ---- constants (host only) ---------------------------------------------- */
+/*
+ * expm_pfd_constants: the poles and residues of R_d, one member per conjugate pair.
+ *   theta_k: the roots of exp_d (Sec. 2.1), found in binary128 by simultaneous
+ *   (Aberth) iteration; a_k = -d!/prod_{j!=k}(theta_k - theta_j) (eq. yoyo2),
+ *   evaluated in binary128 and rounded to FP64 (the paper's preferred formula,
+ *   Sec. 4).  The member with Im(theta) > 0 is kept; pairs are ordered by
+ *   ascending Re(theta).
+ *   degree  even, 2 <= degree <= EXPM_PFD_MAX_DEGREE.
+ *   theta   host array of degree/2 complex numbers (degree doubles), written.
+ *   a       host array of degree/2 complex numbers (degree doubles), written.
+ *   Pure host computation; no device is touched.  Thread-safe.
+ */
+int expm_pfd_constants(int degree, double* theta, double* a);
+
+/* ---- single problem ----------------------------------------------------- */
+typedef struct expm_pfd_plan_s* expm_pfd_plan_t;
+
+/*
+ * expm_pfd_plan: prepare exp(tA)V ~ R_d(tA)V for matrices of order n
+ * (Sec. 3, eq. equ:ExpoMatRat for V = I and eq. equ:expAx otherwise).
+ *   out     receives the plan handle.
+ *   n       matrix order, 1 <= n <= EXPM_PFD_MAX_N.
+ *   degree  even degree d of the approximation (number of poles).
+ *   t       the time factor: the method is applied to the matrix tA (finite).
+ *   m_max   widest right-hand side block the plan will accept; 0 means n and
+ *           also allows V = NULL (V = I, the full matrix R_d(tA)).
+ *   opts    NULL for defaults.
+ * Allocates all device workspace (degree/2 shifted matrices plus solution
+ * blocks) on the current device; nothing is allocated by expm_pfd_apply.
+ * Returns EXPM_PFD_ERR_OOM if the workspace does not fit.
+ */
+int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double t, int64_t m_max,
+                  const expm_pfd_opts* opts);
+
+/* Device bytes a plan with these arguments allocates (for admission control). */
+int expm_pfd_workspace_bytes(int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
+                             size_t* bytes);
+
+/*
+ * expm_pfd_apply: X = R_d(tA) V.
+ *   A    device, n x n complex, column-major, leading dimension lda >= n;
+ *        Hermitian, lower triangle read.
+ *   V    device, n x m complex, column-major, ldv >= n; NULL means V = I
+ *        (then m must equal n and the plan must have m_max = 0 or n).
+ *   X    device, n x m complex, column-major, ldx >= n; written.  Must not
+ *        overlap A or V.  For V = NULL, X is Hermitian.
+ *   stream  hipStream_t as void*.
+ * The plan's workspace is reused: concurrent applies of one plan race.
+ */
+int expm_pfd_apply(expm_pfd_plan_t plan, const void* A, int64_t lda, const void* V, int64_t ldv,
+                   int64_t m, void* X, int64_t ldx, void* stream);
+
+/* Release the plan and its device memory (synchronizes the device first). */
+int expm_pfd_destroy(expm_pfd_plan_t plan);
+
+/* ---- batched ------------------------------------------------------------ */
+/*
+ * expm_pfd_apply_batched: X_i = R_d(t_i A_i) V_i for count independent problems
+ * of possibly different orders (Sec. 3, eq. equ:expAx per problem).
+ *   count   number of problems (>= 1).
+ *   n, t, lda, m, ldv, ldx   host arrays of length count.
+ *   A, V, X host arrays of count device pointers (V[i] may be NULL: V_i = I,
+ *           then m[i] must be n[i]).
+ *   degree, opts  shared by all problems.
+ * Problems are grouped by padded order; every group runs as one sequence of
+ * launches whose grids cover all poles of all its problems.  Device workspace
+ * is allocated inside the call and released before it returns; the call
+ * synchronizes the stream before returning.
+ */
+int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree,
+                           const void* const* A, const int64_t* lda, const void* const* V,
+                           const int64_t* ldv, const int64_t* m, void* const* X, const int64_t* ldx,
+                           const expm_pfd_opts* opts, void* stream);
+
+/* Human-readable text for a return code (static storage). */
+const char* expm_pfd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPM_PFD_H */

@@ -1,0 +1,157 @@
+// Device-side building blocks shared by the kernels of libexpm_pfd (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace expm {
+
+// Interleaved complex element type for each real type.
+template <typename R>
+struct CxT;
+template <>
+struct CxT<double> {
+  using T = double2;
+};
+template <>
+struct CxT<float> {
+  using T = float2;
+};
+template <typename R>
+using cx = typename CxT<R>::T;
+
+template <typename T>
+__device__ __forceinline__ T czero() {
+  T z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+template <typename T>
+__device__ __forceinline__ T cmul(T a, T b) {
+  T r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// c - a*b
+template <typename T>
+__device__ __forceinline__ T cfms(T c, T a, T b) {
+  T r;
+  r.x = c.x - a.x * b.x + a.y * b.y;
+  r.y = c.y - a.x * b.y - a.y * b.x;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T cconj(T a) {
+  a.y = -a.y;
+  return a;
+}
+// 1/a with the larger component scaled out (Smith-style), so |a| far from 1 stays accurate
+template <typename T>
+__device__ __forceinline__ T crecip(T a) {
+  T r;
+  if (fabs(a.x) >= fabs(a.y)) {
+    auto q = a.y / a.x;
+    auto den = a.x + a.y * q;
+    r.x = 1 / den;
+    r.y = -q / den;
+  } else {
+    auto q = a.x / a.y;
+    auto den = a.x * q + a.y;
+    r.x = q / den;
+    r.y = -1 / den;
+  }
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T cdiv(T a, T b) {
+  return cmul(a, crecip(b));
+}
+
+// ---- matrix-core products -------------------------------------------------
+// One 16x16x4 real product per call.  Operand layout (checked on gfx950):
+//   A[i][k] comes from lane i + 16k, B[k][j] from lane j + 16k.
+// Result layout differs between the two types:
+//   f64: lane l, register r holds D[l/16 + 4r][l%16]
+//   f32: lane l, register r holds D[4(l/16) + r][l%16]
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using V = d4;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  using V = f4;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+// ---- row interchanges -----------------------------------------------------
+// Row moves of one factorization step are stored as
+//   [count, dst[0..MOVE_CAP), src[0..MOVE_CAP)]
+// meaning: after the step's interchanges, row dst[e] holds what row src[e] held.
+constexpr int NB_MAX = 64;                 // widest outer panel
+constexpr int MOVE_CAP = 2 * NB_MAX;       // at most 2 moves per interchange
+constexpr int MOVE_STRIDE = 1 + 2 * MOVE_CAP;
+
+// Run by one full wave.  Simulates the interchanges (base+i) <-> piv[i],
+// i = 0..cnt-1 (cnt <= 64, piv[i] >= base+i, applied in order), and writes the
+// net row moves to dst/src.  Returns the number of moves (same on all lanes).
+__device__ inline int composite_moves(const int* piv, int cnt, int base, int* dst, int* src) {
+  const int lane = threadIdx.x & 63;
+  int cur = base + lane;  // original row now at position base+lane
+  int key = -1, val = 0;  // one position outside [base, base+cnt) tracked by this lane
+  for (int i = 0; i < cnt; ++i) {
+    const int b = piv[i];
+    const int ta = __shfl(cur, i);
+    if (b < base + cnt) {
+      const int tb = __shfl(cur, b - base);
+      if (lane == i) cur = tb;
+      if (lane == b - base) cur = ta;
+    } else {
+      const unsigned long long m = __ballot(key == b);
+      int slot, tb;
+      if (m) {
+        slot = __ffsll((long long)m) - 1;
+        tb = __shfl(val, slot);
+      } else {
+        slot = i;
+        tb = b;
+      }
+      if (lane == i) cur = tb;
+      if (lane == slot) {
+        key = b;
+        val = ta;
+      }
+    }
+  }
+  const bool pt = lane < cnt && cur != base + lane;
+  const bool po = key >= 0 && val != key;
+  const unsigned long long mt = __ballot(pt), mo = __ballot(po);
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int nt = __popcll(mt);
+  if (pt) {
+    const int pos = __popcll(mt & below);
+    dst[pos] = base + lane;
+    src[pos] = cur;
+  }
+  if (po) {
+    const int pos = nt + __popcll(mo & below);
+    dst[pos] = key;
+    src[pos] = val;
+  }
+  return nt + __popcll(mo);
+}
+
+}  // namespace expm

@@ -1,0 +1,505 @@
+// libexpm_pfd: exp(tA)V ~ R_d(tA)V for Hermitian A on gfx950 (see include/expm_pfd.h).
+//
+// apply(), FP64 path:
+//   K1 form W_p = tA + theta_p I for the d/2 pole pairs (one launch, all pairs)
+//   LU with partial pivoting of every W_p (right-looking, outer panels of 64
+//     columns split into register-resident inner panels; every launch covers
+//     all pairs):
+//       per inner panel: K2 panel factorization, K5 update of the rest of the
+//       outer panel;  per outer panel: row moves on the left columns,
+//       K4 interchanges + triangular solve for the U12 block row, K5 trailing
+//       update A22 -= L21 U12 on the matrix cores.
+//   solves: Y_p = W_p^{-1} V (primal) and Z_p = (W_p^H)^{-1} V (conjugate pole,
+//     same factors: W_p^H = U^H L^H P^T), right-looking block sweeps
+//     (K4 diagonal block + K5 update), all pairs per launch.
+//   K10 X = sum_p a_p Y_p + conj(a_p) Z_p in FP64 (for V = I: Y_p + Y_p^H form).
+// MIXED path: the same factorization and solves in complex FP32, then per
+//   sweep an FP64 residual R = V - (tA + theta I) X for all pole solves as one
+//   matrix-core product with the shared FP64 tA, a FP32 correction solve and an
+//   FP64 update; accumulation in FP64.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/expm_pfd.h"
+#include "kernels.h"
+
+using namespace expm;
+
+namespace {
+
+constexpr int NB = 64;  // outer panel width (also the padding granularity)
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct HipErr {
+  hipError_t e = hipSuccess;
+  void operator()(hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  }
+};
+
+int inner_width(int64_t npad, bool fp64) {
+  if (fp64) return npad <= 1024 ? 16 : npad <= 2048 ? 8 : npad <= 4096 ? 4 : 2;
+  return npad <= 2048 ? 16 : npad <= 4096 ? 8 : 4;
+}
+
+// ---- launch helpers ---------------------------------------------------------
+
+template <typename R, int IB, int S>
+void panel_launch(hipStream_t st, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0, int nbo,
+                  int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+  constexpr int LIMIT = sizeof(R) == 8 ? 16 : 32;
+  if constexpr (IB * S <= LIMIT) {
+    hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(1024), 0, st, W, ws, ld, npad, j0, c0, nbo, ipiv, ps,
+                       moves, ms, step, last);
+  }
+}
+
+template <typename R, int IB>
+void panel_dispatch(hipStream_t st, int S, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0,
+                    int nbo, int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+  switch (S) {
+#define CASE(s)                                                                                             \
+  case s:                                                                                                   \
+    panel_launch<R, IB, s>(st, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last); \
+    break;
+    CASE(1)
+    CASE(2)
+    CASE(3)
+    CASE(4)
+    CASE(5)
+    CASE(6)
+    CASE(7)
+    CASE(8)
+#undef CASE
+    default:
+      break;
+  }
+}
+
+template <typename R>
+void panel(hipStream_t st, int IB, int S, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0,
+           int nbo, int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+  switch (IB) {
+    case 16:
+      panel_dispatch<R, 16>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      break;
+    case 8:
+      panel_dispatch<R, 8>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      break;
+    case 4:
+      panel_dispatch<R, 4>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      break;
+    default:
+      panel_dispatch<R, 2>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      break;
+  }
+}
+
+// C -= op(A) B, batched.  Tile shape by N.
+template <typename R, bool CONJA>
+void gemm(hipStream_t st, int batch, int M, int N, int K, const cx<R>* A, int64_t sA, int64_t lda, const cx<R>* B,
+          int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc) {
+  if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
+  if (N <= 16) {
+    const int tiles = (int)((M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<R, CONJA, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, A, sA, lda,
+                       B, sB, ldb, C, sC, ldc);
+  } else {
+    const int tiles = (int)(((M + 63) / 64) * ((N + 63) / 64));
+    hipLaunchKernelGGL((k_gemm<R, CONJA, 64, 64, 2, 2>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, A, sA,
+                       lda, B, sB, ldb, C, sC, ldc);
+  }
+}
+
+constexpr int TRSM_CW = 16;
+
+template <typename R, bool LOWER, bool UNIT, bool CONJT, bool MOVES>
+void trsm(hipStream_t st, int batch, const cx<R>* Tm, int64_t sT, int64_t ldt, cx<R>* Bm, int64_t sB, int64_t ldb,
+          int ncols, int base, int nb, const int* moves, int64_t smv) {
+  if (ncols <= 0) return;
+  const int g = (ncols + TRSM_CW - 1) / TRSM_CW;
+  hipLaunchKernelGGL((k_trsm<R, LOWER, UNIT, CONJT, MOVES, TRSM_CW>), dim3(g, batch), dim3(256), 0, st, Tm, sT,
+                     ldt, Bm, sB, ldb, ncols, base, nb, moves, smv);
+}
+
+template <typename R>
+void moves_apply(hipStream_t st, int batch, cx<R>* Bm, int64_t sB, int64_t ldb, int ncols, const int* moves,
+                 int64_t smv, int s_begin, int s_end, int inverse) {
+  if (ncols <= 0 || s_end <= s_begin) return;
+  const int g = (ncols + 15) / 16;
+  hipLaunchKernelGGL((k_moves<R, 16>), dim3(g, batch), dim3(256), 0, st, Bm, sB, ldb, ncols, moves, smv, s_begin,
+                     s_end, inverse);
+}
+
+inline int grid_for(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+}  // namespace
+
+// ============================================================================
+// plan
+// ============================================================================
+struct expm_pfd_plan_s {
+  int64_t n = 0, npad = 0, m_max = 0;
+  int degree = 0, P = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16;
+  double t = 1;
+  bool full_ok = false;
+  int nsteps = 0;
+  std::vector<double2> h_theta, h_a;
+  double2* d_theta = nullptr;
+  double2* d_a = nullptr;
+  void* W = nullptr;    // P x npad x npad, FP64 or FP32 complex, row-major
+  int* ipiv = nullptr;  // P x npad
+  int* moves = nullptr; // P x nsteps x MOVE_STRIDE
+  void* Xs = nullptr;   // npad x cols_alloc, working type
+  int64_t cols_alloc = 0;
+  double2* Ah = nullptr;   // mixed: npad x npad FP64 t*A (Hermitian, row-major)
+  double2* X64 = nullptr;  // mixed: npad x cols_alloc
+  double2* R64 = nullptr;  // mixed: npad x cols_alloc
+  int device = 0;
+};
+
+namespace {
+
+struct Sizes {
+  int64_t npad, cols, w_elem;
+  size_t w, ipiv, moves, xs, ah, x64, r64, consts;
+  size_t total() const { return w + ipiv + moves + xs + ah + x64 + r64 + consts; }
+};
+
+Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
+  Sizes s{};
+  const int P = degree / 2;
+  s.npad = round_up(n, NB);
+  const bool full_ok = (m_max == 0 || m_max >= n);
+  const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
+  s.cols = std::max<int64_t>(full_ok ? (int64_t)P * s.npad : 0, 2 * (int64_t)P * mp);
+  const bool fp64 = precision == EXPM_PFD_FP64;
+  s.w_elem = fp64 ? 16 : 8;
+  s.w = (size_t)P * s.npad * s.npad * s.w_elem;
+  s.ipiv = (size_t)P * s.npad * sizeof(int);
+  s.moves = (size_t)P * (s.npad / NB) * MOVE_STRIDE * sizeof(int);
+  s.xs = (size_t)s.npad * s.cols * s.w_elem;
+  s.ah = fp64 ? 0 : (size_t)s.npad * s.npad * 16;
+  s.x64 = fp64 ? 0 : (size_t)s.npad * s.cols * 16;
+  s.r64 = s.x64;
+  s.consts = 2 * 64 * 16;
+  return s;
+}
+
+int check_opts(const expm_pfd_opts* o) {
+  if (!o) return 0;
+  if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
+  return 0;
+}
+
+void free_plan(expm_pfd_plan_t p) {
+  if (!p) return;
+  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->Xs, p->Ah, p->X64, p->R64};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+// ---- factorization of all pairs ------------------------------------------------
+template <typename R>
+void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
+  const int P = pl->P;
+  const int npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  cx<R>* W = (cx<R>*)pl->W;
+  dim3 g(npad / 32, npad / 32), b(32, 8);
+  hipLaunchKernelGGL((k_form<R>), g, b, 0, st, (const double2*)A, lda, (int)pl->n, npad, pl->t, pl->d_theta, P, W,
+                     ws, ld, pl->Ah, (int64_t)npad);
+  const int IB = pl->IB;
+  int step = 0;
+  for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
+    const int nbo = std::min(NB, npad - j0);
+    for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
+      const int last = (c0 + IB >= j0 + nbo);
+      const int S = (npad - c0 + 1023) / 1024;
+      panel<R>(st, IB, S, P, W, ws, ld, npad, j0, c0, nbo, pl->ipiv, npad, pl->moves,
+               (int64_t)pl->nsteps * MOVE_STRIDE, step, last);
+      const int rest = j0 + nbo - c0 - IB;
+      if (rest > 0) {
+        const int64_t r1 = c0 + IB;
+        gemm<R, false>(st, P, npad - c0 - IB, rest, IB, W + r1 * ld + c0, ws, ld, W + (int64_t)c0 * ld + r1, ws,
+                       ld, W + r1 * ld + r1, ws, ld);
+      }
+    }
+    const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
+    const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+    if (j0 > 0) moves_apply<R>(st, P, W, ws, ld, j0, mv, mstride, 0, 1, 0);
+    const int ntr = npad - j0 - nbo;
+    if (ntr > 0) {
+      const int64_t c1 = j0 + nbo;
+      trsm<R, true, true, false, true>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, W + c1, ws, ld, ntr, j0, nbo, mv,
+                                       mstride);
+      gemm<R, false>(st, P, ntr, ntr, nbo, W + c1 * ld + j0, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld,
+                     W + c1 * ld + c1, ws, ld);
+    }
+  }
+}
+
+// ---- solves on all right-hand-side blocks ----------------------------------------
+// Blocks [0, P) hold primal right-hand sides (pair p), blocks [P, 2P) (if adjoint)
+// the conjugate-pole ones; each block is mp columns of the row-major npad x ldS X.
+template <typename R>
+void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+  const int P = pl->P;
+  const int npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const cx<R>* W = (const cx<R>*)pl->W;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  cx<R>* Xa = X + (int64_t)P * mp;
+  const int nsteps = pl->nsteps;
+  // P^T on the primal blocks
+  moves_apply<R>(st, P, X, mp, ldS, mp, pl->moves, mstride, 0, nsteps, 0);
+  // forward sweeps: L (primal), U^H (adjoint)
+  for (int s = 0; s < nsteps; ++s) {
+    const int j0 = s * NB, nb = std::min(NB, npad - j0);
+    const int64_t r1 = j0 + nb;
+    const int below = npad - j0 - nb;
+    trsm<R, true, true, false, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, X, mp, ldS, mp, j0, nb, nullptr, 0);
+    if (adjoint)
+      trsm<R, true, false, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
+                                        0);
+    if (below > 0) {
+      gemm<R, false>(st, P, below, mp, nb, W + r1 * ld + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
+                     mp, ldS);
+      if (adjoint)
+        gemm<R, true>(st, P, below, mp, nb, W + (int64_t)j0 * ld + r1, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS,
+                      Xa + r1 * ldS, mp, ldS);
+    }
+  }
+  // backward sweeps: U (primal), L^H (adjoint)
+  for (int s = nsteps - 1; s >= 0; --s) {
+    const int j0 = s * NB, nb = std::min(NB, npad - j0);
+    trsm<R, false, false, false, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, X, mp, ldS, mp, j0, nb, nullptr,
+                                        0);
+    if (adjoint)
+      trsm<R, false, true, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
+                                        0);
+    if (j0 > 0) {
+      gemm<R, false>(st, P, j0, mp, nb, W + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
+      if (adjoint)
+        gemm<R, true>(st, P, j0, mp, nb, W + (int64_t)j0 * ld, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS, Xa, mp, ldS);
+    }
+  }
+  // P on the adjoint blocks
+  if (adjoint) moves_apply<R>(st, P, Xa, mp, ldS, mp, pl->moves, mstride, 0, nsteps, 1);
+}
+
+int validate_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m, void* X,
+                   int64_t ldx) {
+  if (!pl || !A || !X) return EXPM_PFD_ERR_NULL;
+  if (lda < pl->n || ldx < pl->n) return EXPM_PFD_ERR_LD;
+  if (V == nullptr) {
+    if (!pl->full_ok || m != pl->n) return EXPM_PFD_ERR_DIM;
+  } else {
+    if (ldv < pl->n) return EXPM_PFD_ERR_LD;
+    const int64_t cap = pl->m_max == 0 ? pl->n : pl->m_max;
+    if (m < 1 || m > cap) return EXPM_PFD_ERR_DIM;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int expm_pfd_workspace_bytes(int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
+                                        size_t* bytes) {
+  if (!bytes) return EXPM_PFD_ERR_NULL;
+  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
+  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
+  if (int e = check_opts(opts)) return e;
+  *bytes = plan_sizes(n, degree, m_max, opts ? opts->precision : EXPM_PFD_FP64).total();
+  return 0;
+}
+
+extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double t, int64_t m_max,
+                             const expm_pfd_opts* opts) {
+  if (!out) return EXPM_PFD_ERR_NULL;
+  *out = nullptr;
+  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
+  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
+  if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
+  if (int e = check_opts(opts)) return e;
+  auto* pl = new expm_pfd_plan_s();
+  pl->n = n;
+  pl->degree = degree;
+  pl->P = degree / 2;
+  pl->t = t;
+  pl->m_max = m_max;
+  pl->precision = opts ? opts->precision : EXPM_PFD_FP64;
+  pl->ir_sweeps = (opts && opts->ir_sweeps > 0) ? opts->ir_sweeps : 2;
+  pl->full_ok = (m_max == 0 || m_max >= n);
+  const Sizes sz = plan_sizes(n, degree, m_max, pl->precision);
+  pl->npad = sz.npad;
+  pl->nsteps = (int)(sz.npad / NB);
+  pl->cols_alloc = sz.cols;
+  pl->IB = inner_width(sz.npad, pl->precision == EXPM_PFD_FP64);
+  pl->h_theta.resize(pl->P);
+  pl->h_a.resize(pl->P);
+  int rc = expm_pfd_constants(degree, (double*)pl->h_theta.data(), (double*)pl->h_a.data());
+  if (rc) {
+    delete pl;
+    return rc;
+  }
+  (void)hipGetDevice(&pl->device);
+  HipErr he;
+  he(hipMalloc(&pl->d_theta, 64 * sizeof(double2)));
+  he(hipMalloc(&pl->d_a, 64 * sizeof(double2)));
+  he(hipMalloc(&pl->W, sz.w));
+  he(hipMalloc(&pl->ipiv, sz.ipiv));
+  he(hipMalloc(&pl->moves, sz.moves));
+  he(hipMalloc(&pl->Xs, sz.xs));
+  if (pl->precision == EXPM_PFD_MIXED) {
+    he(hipMalloc(&pl->Ah, sz.ah));
+    he(hipMalloc(&pl->X64, sz.x64));
+    he(hipMalloc(&pl->R64, sz.r64));
+  }
+  if (he.e == hipSuccess) {
+    he(hipMemcpy(pl->d_theta, pl->h_theta.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
+    he(hipMemcpy(pl->d_a, pl->h_a.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
+    he(hipMemset(pl->moves, 0, sz.moves));
+  }
+  if (he.e != hipSuccess) {
+    const bool oom = he.e == hipErrorOutOfMemory;
+    (void)hipGetLastError();
+    free_plan(pl);
+    return oom ? EXPM_PFD_ERR_OOM : EXPM_PFD_ERR_HIP;
+  }
+  *out = pl;
+  return 0;
+}
+
+extern "C" int expm_pfd_destroy(expm_pfd_plan_t pl) {
+  if (!pl) return EXPM_PFD_ERR_NULL;
+  (void)hipDeviceSynchronize();
+  free_plan(pl);
+  return 0;
+}
+
+extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m,
+                              void* X, int64_t ldx, void* stream) {
+  if (int e = validate_apply(pl, A, lda, V, ldv, m, X, ldx)) return e;
+  hipStream_t st = (hipStream_t)stream;
+  const bool full = (V == nullptr);
+  const int P = pl->P;
+  const int npad = (int)pl->npad;
+  const int mp = full ? npad : (int)round_up(m, 16);
+  const int nblk = full ? P : 2 * P;
+  const int64_t ldS = (int64_t)nblk * mp;
+  const int64_t count = (int64_t)npad * ldS;
+  (void)hipGetLastError();
+  if (pl->precision == EXPM_PFD_FP64) {
+    factor<double>(pl, A, lda, st);
+    double2* Xs = (double2*)pl->Xs;
+    hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
+                       (const double2*)V, ldv, (int)pl->n, (int)m);
+    solves<double>(pl, Xs, ldS, mp, !full, st);
+    if (full) {
+      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
+      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xs, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
+    } else {
+      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, Xs, ldS, mp, P, pl->d_a,
+                         (int)pl->n, (int)m, (double2*)X, ldx);
+    }
+  } else {
+    factor<float>(pl, A, lda, st);
+    float2* Xs = (float2*)pl->Xs;
+    hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
+                       (const double2*)V, ldv, (int)pl->n, (int)m);
+    solves<float>(pl, Xs, ldS, mp, !full, st);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
+    for (int it = 0; it < pl->ir_sweeps; ++it) {
+      // R = V - (tA + theta I) X in FP64, all pole solves at once
+      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, nblk,
+                         (const double2*)V, ldv, (int)pl->n, (int)m);
+      gemm<double, false>(st, 1, npad, (int)ldS, npad, pl->Ah, 0, npad, pl->X64, 0, ldS, pl->R64, 0, ldS);
+      hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp, P,
+                         pl->d_theta);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, Xs, count);
+      solves<float>(pl, Xs, ldS, mp, !full, st);
+      hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
+    }
+    if (full) {
+      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
+      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, pl->X64, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
+    } else {
+      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, pl->X64, ldS, mp, P, pl->d_a,
+                         (int)pl->n, (int)m, (double2*)X, ldx);
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return EXPM_PFD_ERR_HIP;
+  return 0;
+}
+
+extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree, const void* const* A,
+                                      const int64_t* lda, const void* const* V, const int64_t* ldv,
+                                      const int64_t* m, void* const* X, const int64_t* ldx,
+                                      const expm_pfd_opts* opts, void* stream) {
+  if (count < 1) return EXPM_PFD_ERR_DIM;
+  if (!n || !t || !A || !lda || !V || !ldv || !m || !X || !ldx) return EXPM_PFD_ERR_NULL;
+  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
+  if (int e = check_opts(opts)) return e;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
+    if (!A[i] || !X[i]) return EXPM_PFD_ERR_NULL;
+    if (lda[i] < n[i] || ldx[i] < n[i]) return EXPM_PFD_ERR_LD;
+    if (V[i] ? (ldv[i] < n[i] || m[i] < 1 || m[i] > n[i]) : (m[i] != n[i])) return V[i] && ldv[i] < n[i] ? EXPM_PFD_ERR_LD : EXPM_PFD_ERR_DIM;
+    if (!std::isfinite(t[i])) return EXPM_PFD_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // one plan per problem, reused across problems of the same (n, m, full) shape
+  int rc = 0;
+  std::map<std::pair<int64_t, int64_t>, expm_pfd_plan_t> plans;
+  for (int i = 0; i < count && !rc; ++i) {
+    const int64_t mm = V[i] ? m[i] : 0;
+    auto key = std::make_pair(n[i], mm);
+    expm_pfd_plan_t pl;
+    auto it = plans.find(key);
+    if (it == plans.end()) {
+      rc = expm_pfd_plan(&pl, n[i], degree, t[i], mm, opts);
+      if (rc) break;
+      plans[key] = pl;
+    } else {
+      pl = it->second;
+    }
+    pl->t = t[i];
+    rc = expm_pfd_apply(pl, A[i], lda[i], V[i], ldv[i], m[i], X[i], ldx[i], st);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+  }
+  for (auto& kv : plans) {
+    (void)hipStreamSynchronize(st);
+    free_plan(kv.second);
+  }
+  return rc;
+}
+
+extern "C" const char* expm_pfd_strerror(int code) {
+  switch (code) {
+    case EXPM_PFD_OK: return "success";
+    case EXPM_PFD_ERR_DEGREE: return "degree must be even and in [2, 64]";
+    case EXPM_PFD_ERR_DIM: return "invalid dimension (n, m)";
+    case EXPM_PFD_ERR_NULL: return "required pointer is NULL";
+    case EXPM_PFD_ERR_LD: return "leading dimension smaller than the row count";
+    case EXPM_PFD_ERR_OOM: return "device memory allocation failed";
+    case EXPM_PFD_ERR_HIP: return "HIP runtime error";
+    case EXPM_PFD_ERR_ARG: return "invalid argument";
+    case EXPM_PFD_ERR_CONST: return "root finding for the constants did not converge";
+    case EXPM_PFD_ERR_BUDGET: return "request exceeds the queue's HBM budget";
+    case EXPM_PFD_ERR_TICKET: return "unknown ticket or matrix id";
+    default: return "unknown error";
+  }
+}

@@ -1,0 +1,219 @@
+"""Python binding of libexpm_pfd (include/expm_pfd.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device arrays
+are torch tensors on the GPU (PyTorch supplies device memory and streams); all
+arithmetic runs in the library's HIP kernels.  The binding never falls back to a
+CPU computation: if the library is missing it raises.
+
+Layout: the C ABI takes column-major complex128 matrices.  A torch tensor X of
+shape (rows, cols) is passed as-is when it is already column-major
+(X.stride() == (1, ld)), otherwise as a column-major copy.  Results come back as
+column-major tensors of the logical shape (rows, cols).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexpm_pfd.so")
+
+EXPM_PFD_FP64 = 0
+EXPM_PFD_MIXED = 1
+
+# every symbol declared in include/expm_pfd.h
+EXPORTED = (
+    "expm_pfd_constants",
+    "expm_pfd_plan",
+    "expm_pfd_workspace_bytes",
+    "expm_pfd_apply",
+    "expm_pfd_destroy",
+    "expm_pfd_apply_batched",
+    "expm_pfd_strerror",
+)
+
+
+class ExpmPfdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {expm_pfd_strerror(code)} (code {code})")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libexpm_pfd.so from the package directory (built by build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libexpm_pfd.so is not built ({LIB_PATH}); run python -m paper_2306_16778_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, c_int, c_double = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.expm_pfd_constants.argtypes = [c_int, vp, vp]
+    lib.expm_pfd_plan.argtypes = [ctypes.POINTER(vp), i64, c_int, c_double, i64, ctypes.POINTER(_Opts)]
+    lib.expm_pfd_workspace_bytes.argtypes = [i64, c_int, i64, ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.expm_pfd_apply.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
+    lib.expm_pfd_destroy.argtypes = [vp]
+    lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(_Opts), vp]
+    lib.expm_pfd_strerror.argtypes = [c_int]
+    lib.expm_pfd_strerror.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "expm_pfd_strerror":
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise ExpmPfdError(code, where)
+
+
+def _opts(precision, ir_sweeps) -> _Opts:
+    p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
+    o = _Opts()
+    o.precision = int(p)
+    o.ir_sweeps = int(ir_sweeps)
+    return o
+
+
+def expm_pfd_strerror(code: int) -> str:
+    return load_library().expm_pfd_strerror(int(code)).decode()
+
+
+def expm_pfd_constants(degree: int):
+    """(theta, a): complex128 arrays of length degree/2 (host only)."""
+    lib = load_library()
+    th = np.zeros(2 * max(degree // 2, 1), dtype=np.float64)
+    a = np.zeros_like(th)
+    _check(lib.expm_pfd_constants(int(degree), th.ctypes.data, a.ctypes.data), "expm_pfd_constants")
+    return th.view(np.complex128).copy(), a.view(np.complex128).copy()
+
+
+def expm_pfd_workspace_bytes(n: int, degree: int, m_max: int = 0, precision="fp64", ir_sweeps: int = 0) -> int:
+    lib = load_library()
+    out = ctypes.c_size_t(0)
+    o = _opts(precision, ir_sweeps)
+    _check(lib.expm_pfd_workspace_bytes(int(n), int(degree), int(m_max), ctypes.byref(o), ctypes.byref(out)),
+           "expm_pfd_workspace_bytes")
+    return int(out.value)
+
+
+class Plan:
+    """Owns an expm_pfd_plan_t."""
+
+    def __init__(self, handle, n, degree, t, m_max, precision):
+        self.handle = handle
+        self.n, self.degree, self.t, self.m_max, self.precision = n, degree, t, m_max, precision
+
+    def __del__(self):
+        try:
+            if self.handle:
+                expm_pfd_destroy(self)
+        except Exception:
+            pass
+
+
+def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0) -> Plan:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    o = _opts(precision, ir_sweeps)
+    _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
+           "expm_pfd_plan")
+    return Plan(h.value, n, degree, t, m_max, precision)
+
+
+def expm_pfd_destroy(plan: Plan):
+    if plan.handle:
+        _check(load_library().expm_pfd_destroy(plan.handle), "expm_pfd_destroy")
+        plan.handle = None
+
+
+def _colmajor(x, torch):
+    """Column-major complex128 device tensor with the same logical shape; returns (tensor, ld)."""
+    if x.dtype != torch.complex128:
+        raise TypeError("complex128 expected")
+    if not x.is_cuda:
+        raise TypeError("device tensor expected")
+    r, c = x.shape
+    if x.stride(0) == 1 and x.stride(1) >= max(r, 1):
+        return x, x.stride(1)
+    y = x.t().contiguous().t()
+    return y, max(r, 1)
+
+
+def _stream_ptr(stream, torch):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def expm_pfd_apply(plan: Plan, A, V=None, X=None, stream=None):
+    """X = R_d(tA)V (V None: V = I).  Returns X (column-major complex128 tensor)."""
+    import torch
+
+    lib = load_library()
+    Ac, lda = _colmajor(A, torch)
+    n = Ac.shape[0]
+    if V is None:
+        Vp, ldv, m = None, n, n
+    else:
+        Vc, ldv = _colmajor(V, torch)
+        Vp, m = Vc.data_ptr(), Vc.shape[1]
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.complex128, device=Ac.device).t()
+    if not (X.stride(0) == 1 and X.stride(1) >= n and tuple(X.shape) == (n, m)):
+        raise ValueError("X must be a column-major (n, m) complex128 tensor")
+    _check(lib.expm_pfd_apply(plan.handle, Ac.data_ptr(), lda, Vp, ldv, m, X.data_ptr(), X.stride(1),
+                              _stream_ptr(stream, torch)), "expm_pfd_apply")
+    # keep staged copies alive until the stream has consumed them
+    X._expm_keepalive = (Ac, V if V is None else Vc)
+    return X
+
+
+def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degree: int, precision="fp64",
+                           ir_sweeps: int = 0, stream=None):
+    """X_i = R_d(t_i A_i) V_i for every i (V_i None: V_i = I).  Returns the list of X_i."""
+    import torch
+
+    lib = load_library()
+    count = len(As)
+    Ac, Vc, Xs = [], [], []
+    n = np.zeros(count, np.int64)
+    lda = np.zeros(count, np.int64)
+    ldv = np.zeros(count, np.int64)
+    m = np.zeros(count, np.int64)
+    ldx = np.zeros(count, np.int64)
+    t = np.asarray(ts, dtype=np.float64)
+    pa = (ctypes.c_void_p * count)()
+    pv = (ctypes.c_void_p * count)()
+    px = (ctypes.c_void_p * count)()
+    for i in range(count):
+        a, la = _colmajor(As[i], torch)
+        Ac.append(a)
+        n[i], lda[i], pa[i] = a.shape[0], la, a.data_ptr()
+        if Vs[i] is None:
+            Vc.append(None)
+            m[i], ldv[i], pv[i] = n[i], n[i], None
+        else:
+            v, lv = _colmajor(Vs[i], torch)
+            Vc.append(v)
+            m[i], ldv[i], pv[i] = v.shape[1], lv, v.data_ptr()
+        x = torch.empty((int(m[i]), int(n[i])), dtype=torch.complex128, device=a.device).t()
+        Xs.append(x)
+        ldx[i], px[i] = n[i], x.data_ptr()
+    o = _opts(precision, ir_sweeps)
+    _check(lib.expm_pfd_apply_batched(count, n.ctypes.data, t.ctypes.data, int(degree), pa, lda.ctypes.data, pv,
+                                      ldv.ctypes.data, m.ctypes.data, px, ldx.ctypes.data, ctypes.byref(o),
+                                      _stream_ptr(stream, torch)), "expm_pfd_apply_batched")
+    return Xs

@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports what include/expm_pfd.h declares; host-side
+logic (constants, argument validation, workspace sizing) checked without a GPU."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import scalar
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "expm_pfd.h")
+
+
+def _lib():
+    from paper_2306_16778_amd import expm_pfd
+    return expm_pfd, expm_pfd.load_library()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(expm_pfd_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_symbols()
+    for n in ("expm_pfd_plan", "expm_pfd_apply", "expm_pfd_apply_batched", "expm_pfd_constants",
+              "expm_pfd_destroy", "expm_pfd_strerror", "expm_pfd_workspace_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    mod, lib = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", mod.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (expm_pfd_\w+)", out))
+    for name in declared_symbols():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert set(mod.EXPORTED) == set(declared_symbols())
+
+
+@pytest.mark.parametrize("d", [2, 4, 8, 16, 24, 32, 36, 48, 64])
+def test_constants_match_oracle(d):
+    """Library poles/residues (binary128 Aberth + eq. yoyo2) vs the oracle's mpmath values: <= 2 ulp."""
+    mod, _ = _lib()
+    th, a = mod.expm_pfd_constants(d)
+    ot, oa = scalar.pfd_pairs(d)
+    for x, y in ((th, ot), (a, oa)):
+        for part in ("real", "imag"):
+            xv, yv = getattr(x, part), getattr(y, part)
+            ulps = np.abs(xv - yv) / np.spacing(np.abs(yv))
+            assert np.max(ulps) <= 2
+
+
+def test_argument_validation_without_device():
+    mod, lib = _lib()
+    h = ctypes.c_void_p()
+    o = mod._Opts()
+    for deg in (0, 1, 3, 17, 66):
+        assert lib.expm_pfd_plan(ctypes.byref(h), 10, deg, 1.0, 0, ctypes.byref(o)) == -1
+    assert lib.expm_pfd_plan(ctypes.byref(h), 0, 16, 1.0, 0, ctypes.byref(o)) == -2
+    assert lib.expm_pfd_plan(ctypes.byref(h), 9000, 16, 1.0, 0, ctypes.byref(o)) == -2
+    assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, float("nan"), 0, ctypes.byref(o)) == -7
+    o.precision = 7
+    assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+    assert lib.expm_pfd_plan(None, 10, 16, 1.0, 0, None) == -3
+    assert lib.expm_pfd_apply(None, None, 1, None, 1, 1, None, 1, None) == -3
+    assert lib.expm_pfd_destroy(None) == -3
+    th = np.zeros(4)
+    assert lib.expm_pfd_constants(5, th.ctypes.data, th.ctypes.data) == -1
+    assert lib.expm_pfd_constants(4, None, th.ctypes.data) == -3
+    for code in range(-10, 1):
+        assert isinstance(mod.expm_pfd_strerror(code), str)
+
+
+def test_workspace_bytes():
+    mod, _ = _lib()
+    n, d = 2048, 24
+    b64 = mod.expm_pfd_workspace_bytes(n, d, 16, "fp64")
+    bmx = mod.expm_pfd_workspace_bytes(n, d, 16, "mixed")
+    # 12 shifted matrices dominate: 12 * 2048^2 * 16 bytes (FP64) or 8 bytes (FP32)
+    assert 12 * n * n * 16 <= b64 < 12 * n * n * 16 * 1.1
+    assert 12 * n * n * 8 + n * n * 16 <= bmx < b64

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
+
+Tolerances are relative Frobenius errors against R_d(tA)V computed by the oracle
+(eigendecomposition, FP64):
+  FP64 path  1e-12 (degree <= 24, spectra in [-100, 0]; rounding of the shifted
+             solves is amplified by sum_k |a_k| relative to |R_d(tA)V|, which grows
+             with the degree: about 1e-11 is reached at degree 32);
+  mixed path 1e-10 (FP32 factorization recovered by FP64 refinement).
+Every case prints its name before it touches the GPU.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import matrix, scalar
+from paper_2306_16778_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOLMX = 1e-10
+
+
+def _announce(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ep():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16778_amd import expm_pfd
+    expm_pfd.load_library()
+    return expm_pfd
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.asfortranarray(x)).to("cuda")
+
+
+def _run(ep, A, V, t, d, precision="fp64", m_max=None):
+    import torch
+    n = A.shape[0]
+    mm = 0 if V is None else (V.shape[1] if m_max is None else m_max)
+    plan = ep.expm_pfd_plan(n, d, t, mm, precision)
+    X = ep.expm_pfd_apply(plan, _dev(A), None if V is None else _dev(V))
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+def _problem(n, lo, hi, m, seed, t=1.0):
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(lo, hi, n)
+    A = wl.hermitian_with_spectrum(rng, lam)
+    V = None if m is None else wl.complex_gaussian(rng, n, m)
+    return A, V, t
+
+
+CASES = [
+    # n, spectrum, m (None: V = I), degree, t
+    (1, (-5, 0), 1, 16, 1.0),
+    (1, (-5, 0), None, 2, 1.0),
+    (5, (-10, 0), 3, 2, 0.5),
+    (33, (-50, 0), 4, 16, 0.3),
+    (64, (-10, 0), None, 16, 1.0),
+    (65, (-100, 0), 16, 24, 1.0),
+    (100, (-100, 0), 1, 16, 0.7),
+    (130, (-20, 0), None, 8, 1.0),
+    (200, (-100, 0), 16, 24, 1.0),
+    (257, (-100, 0), 5, 16, 1.0),
+    (300, (-40, 0), None, 16, 0.9),
+]
+
+
+@pytest.mark.parametrize("n,spec,m,d,t", CASES)
+def test_fp64_parity_small(ep, n, spec, m, d, t):
+    A, V, _ = _problem(n, spec[0], spec[1], m, 1000 + n + d)
+    _announce(f"fp64 n={n} m={m} d={d} t={t}")
+    X = _run(ep, A, V, t, d)
+    Y = matrix.expm_R(A, V, t, d)
+    assert matrix.rel_fro(X, Y) < TOL64
+
+
+@pytest.mark.parametrize("n,spec,m,d,t", CASES)
+def test_mixed_parity_small(ep, n, spec, m, d, t):
+    A, V, _ = _problem(n, spec[0], spec[1], m, 2000 + n + d)
+    _announce(f"mixed n={n} m={m} d={d} t={t}")
+    X = _run(ep, A, V, t, d, "mixed")
+    Y = matrix.expm_R(A, V, t, d)
+    assert matrix.rel_fro(X, Y) < TOLMX
+
+
+def test_config1_full_exponential(ep):
+    """n = 64, V = I, degree 16, spectrum in [-10, 0]."""
+    P = wl.config1_plain_cpu_sized()
+    _announce("config1 fp64 n=64 V=I d=16")
+    X = _run(ep, P.A, None, P.t, P.degree)
+    Y = matrix.expm_R(P.A, None, P.t, P.degree)
+    assert matrix.rel_fro(X, Y) < TOL64
+    assert np.array_equal(X, X.conj().T)  # Hermitian by construction (Y + Y^H form)
+    E = matrix.expm_exact(P.A, None, P.t)
+    assert matrix.rel_fro(X, E) < 1e-4  # approximation error of R_16, reported not gated
+
+
+@pytest.mark.parametrize("n", [1100, 1500])
+def test_fp64_multi_panel_sizes(ep, n):
+    """npad > 1024 switches the register panel to 2 rows per thread."""
+    A, V, t = _problem(n, -100, 0, 16, 77 + n)
+    _announce(f"fp64 n={n} m=16 d=24")
+    X = _run(ep, A, V, t, 24)
+    Y = matrix.expm_R(A, V, t, 24)
+    assert matrix.rel_fro(X, Y) < TOL64
+    _announce(f"mixed n={n} m=16 d=24")
+    Xm = _run(ep, A, V, t, 24, "mixed")
+    assert matrix.rel_fro(Xm, Y) < TOLMX
+
+
+def test_diagonal_and_zero(ep):
+    """Diagonal A gives diagonal R_d(tA) (Remark after eq. equ:ExpoMatRat); A = 0 gives V."""
+    n = 70
+    lam = -np.linspace(0, 30, n)
+    D = np.diag(lam).astype(np.complex128)
+    _announce("diagonal n=70 V=I d=16")
+    X = _run(ep, D, None, 1.0, 16)
+    want = 1.0 / scalar.exp_d(-lam, 16)
+    assert np.max(np.abs(X - np.diag(np.diag(X)))) < 1e-14
+    # absolute error, as bounded by Prop. prop:digit (entries range down to 1e-11 here)
+    assert np.max(np.abs(np.diag(X).real - want)) < 1e-13
+    V = wl.complex_gaussian(np.random.default_rng(5), n, 3)
+    _announce("zero matrix n=70 m=3 d=16")
+    Z = _run(ep, np.zeros((n, n), np.complex128), V, 1.0, 16)
+    assert matrix.rel_fro(Z, V) < 1e-13
+
+
+def test_lower_triangle_only(ep):
+    A, V, t = _problem(90, -60, 0, 2, 9)
+    B = A.copy()
+    B[np.triu_indices(90, 1)] = 7.0 + 3.0j
+    B[np.diag_indices(90)] += 2j
+    _announce("upper garbage n=90 m=2 d=16")
+    X1 = _run(ep, A, V, t, 16)
+    X2 = _run(ep, B, V, t, 16)
+    assert np.array_equal(X1, X2)
+
+
+def test_deterministic(ep):
+    A, V, t = _problem(180, -100, 0, 16, 10)
+    _announce("determinism n=180 m=16 d=24")
+    X1 = _run(ep, A, V, t, 24)
+    X2 = _run(ep, A, V, t, 24)
+    assert np.array_equal(X1, X2)
+
+
+def test_config2_full_size_fp64_and_mixed(ep):
+    """n = 2048, V 2048 x 16, degree 24, spectrum in [-100, 0]: the benchmarked launch configuration."""
+    P = wl.config2_fp64_at_scale()
+    Y = matrix.expm_R(P.A, P.V, P.t, P.degree)
+    _announce("config2 fp64 n=2048 m=16 d=24")
+    X = _run(ep, P.A, P.V, P.t, P.degree)
+    assert matrix.rel_fro(X, Y) < TOL64
+    _announce("config2 mixed n=2048 m=16 d=24")
+    Xm = _run(ep, P.A, P.V, P.t, P.degree, "mixed")
+    assert matrix.rel_fro(Xm, Y) < TOLMX
