@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""exp(tA)V throughput on one MI355X.
+
+Workload: dense Hermitian A, n = 2048, spectrum uniform in [-100, 0], V 2048 x 16
+complex Gaussian, t = 1, degree 24 (12 conjugate pole pairs).  One step = one
+complete exp(tA)V ~ R_24(tA)V through the C ABI: shifted-matrix formation, 12
+pivoted complex LU factorizations, 24 shifted solves (primal + adjoint per pair),
+FP64 residue-weighted accumulation; the mixed path adds FP64 refinement.
+Inputs are resident on the GPU before timing starts.
+
+Both paths are timed: the mixed path (complex FP32 factorization + FP64
+refinement, the reported value) and the plain FP64 path.  The oracle
+(eigendecomposition, FP64, host CPU) is timed once on the same input as the CPU
+baseline and provides the error check of both GPU results.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "exp(tA)V solves/s at rel err<=1e-10, mixed vs FP64 GPU path; p50/p99 latency"
+PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
+
+
+def algorithmic_flops(n, m, degree):
+    """LAPACK counts (complex multiply-add = 8 flops): degree/2 LU factorizations
+    (8/3 n^3 each) and degree solves with an n x m block (8 n^2 m each)."""
+    P = degree // 2
+    return P * (8.0 / 3.0) * n ** 3 + 2 * P * 8.0 * n * n * m
+
+
+def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
+    n, m, d = prob.A.shape[0], prob.V.shape[1], prob.degree
+    plan = ep.expm_pfd_plan(n, d, prob.t, m, precision)
+    X = torch.empty((m, n), dtype=torch.complex128, device="cuda").t()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ep.expm_pfd_apply(plan, Ad, Vd, X)
+    torch.cuda.synchronize()
+    # timed region: K steps; the dominant kernel's launches carry HIP event pairs
+    ep.expm_pfd_trace(["lu_gemm"])
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        evs[k][0].record(stream)
+        ep.expm_pfd_apply(plan, Ad, Vd, X)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom = ep.expm_pfd_trace_summary("lu_gemm")
+    lat = sorted(a.elapsed_time(b) for a, b in evs)
+    # one more traced step for the per-class breakdown (not part of the timed region)
+    ep.expm_pfd_trace(list(ep.KERNEL_CLASSES))
+    ep.expm_pfd_apply(plan, Ad, Vd, X)
+    torch.cuda.synchronize()
+    breakdown = {c: ep.expm_pfd_trace_summary(c) for c in ep.KERNEL_CLASSES}
+    ep.expm_pfd_trace([])
+    Xh = X.cpu().numpy()
+
+    def pct(q):
+        i = min(len(lat) - 1, max(0, int(round(q * (len(lat) - 1)))))
+        return lat[i]
+
+    ms = wall * 1e3 / steps
+    flops = algorithmic_flops(n, m, d)
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
+    return {
+        "X": Xh,
+        "ms_per_step": ms,
+        "solves_per_s": 1e3 / ms,
+        "gflops": flops / (ms * 1e-3) / 1e9,
+        "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
+        "roofline": {
+            "kernel": "k_gemm<%s,64x64> (LU trailing and in-panel updates)" % ("double" if precision == "fp64" else "float"),
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK[precision],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK[precision],
+            "traffic": None,
+            "launches_per_step": dom["launches"] / steps,
+            "avg_launch_us": dom["ms"] * 1e3 / max(dom["launches"], 1),
+            "flops_per_launch": dom["flops"] / max(dom["launches"], 1),
+        },
+        "breakdown_ms_per_step": {c: round(v["ms"], 4) for c, v in breakdown.items() if v["launches"]},
+    }
+
+
+def cpu_baseline(prob):
+    """The oracle as it stands on the host cores: one full R_d(tA)V of the workload."""
+    from oracle import matrix
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    Y = matrix.expm_R(prob.A, prob.V, prob.t, prob.degree)
+    dt = time.perf_counter() - t0
+    return Y, {"value": 1.0 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+               "sample": "one full exp(tA)V of the workload (n=2048 Hermitian eigendecomposition + 2 products), %.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the poles or the requests "
+              "would be sharded across GPUs with one final reduction; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2306_16778_amd import expm_pfd as ep
+    from paper_2306_16778_amd import workloads
+
+    ep.load_library()
+    prob = workloads.config2_fp64_at_scale()
+    n, m = prob.V.shape
+    Ad = torch.from_numpy(np.asfortranarray(prob.A)).to("cuda")
+    Vd = torch.from_numpy(np.asfortranarray(prob.V)).to("cuda")
+    torch.cuda.synchronize()
+    print(f"[bench] workload n={n} m={m} degree={prob.degree}; timing mixed then fp64 "
+          f"({args.warmup} warmup + {args.steps} steps each)", file=sys.stderr, flush=True)
+    res = {p: run_path(ep, torch, prob, Ad, Vd, p, args.steps, args.warmup) for p in ("mixed", "fp64")}
+    print("[bench] GPU timing done", file=sys.stderr, flush=True)
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle import matrix
+        Y, cpu = cpu_baseline(prob)
+        errs = {p: matrix.rel_fro(r["X"], Y) for p, r in res.items()}
+        print(f"[bench] oracle done: rel errs {errs}", file=sys.stderr, flush=True)
+
+    mx, f64 = res["mixed"], res["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": mx["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mx["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": "Hermitian n=2048, spectrum U[-100,0], V 2048x16 Gaussian, t=1, degree 24",
+                   "n": n, "m": m, "degree": prob.degree, "t": prob.t, "path": "mixed (FP32 LU + FP64 refinement)"},
+        "latency_ms": mx["latency_ms"],
+        "gflops": mx["gflops"],
+        "rel_err_vs_oracle": errs.get("mixed"),
+        "meets_1e-10": (errs["mixed"] <= 1e-10) if errs else None,
+        "speedup_vs_fp64_path": f64["ms_per_step"] / mx["ms_per_step"],
+        "fp64_path": {"value": f64["solves_per_s"], "ms_per_step": f64["ms_per_step"],
+                      "latency_ms": f64["latency_ms"], "gflops": f64["gflops"],
+                      "rel_err_vs_oracle": errs.get("fp64"), "roofline": f64["roofline"],
+                      "breakdown_ms_per_step": f64["breakdown_ms_per_step"]},
+        "breakdown_ms_per_step": mx["breakdown_ms_per_step"],
+        "roofline": mx["roofline"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

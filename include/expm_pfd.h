@@ -147,6 +147,41 @@ int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int deg
                            const int64_t* ldv, const int64_t* m, void* const* X, const int64_t* ldx,
                            const expm_pfd_opts* opts, void* stream);
 
+/* ---- tracing ------------------------------------------------------------ */
+/* Kernel classes timed by the tracer (one HIP event pair per launch, recorded on
+ * the stream the kernel is launched on). */
+#define EXPM_PFD_K_FORM        0  /* shifted-matrix formation */
+#define EXPM_PFD_K_PANEL       1  /* register-resident panel factorization */
+#define EXPM_PFD_K_LU_GEMM     2  /* LU updates, 64x64 complex tiles on the matrix cores */
+#define EXPM_PFD_K_LU_TRSM     3  /* LU interchanges + U12 triangular solve */
+#define EXPM_PFD_K_MOVES       4  /* row moves (left columns, right-hand sides) */
+#define EXPM_PFD_K_SOLVE_TRSM  5  /* diagonal-block solves of the sweeps */
+#define EXPM_PFD_K_SOLVE_GEMM  6  /* block updates of the sweeps */
+#define EXPM_PFD_K_ACCUM       7  /* residue-weighted accumulation */
+#define EXPM_PFD_K_IR_GEMM     8  /* refinement residual product (FP64) */
+#define EXPM_PFD_K_ELEMENTWISE 9  /* staging, conversions, shift, correction */
+#define EXPM_PFD_K_COUNT      10
+
+/*
+ * expm_pfd_trace: time every later launch of the kernel classes whose bit is set
+ * in class_mask (bit EXPM_PFD_K_x; 0 disables tracing), discarding what was
+ * recorded before.  Host-side process-wide state; not thread-safe.  Adds two
+ * event records per timed launch.
+ */
+int expm_pfd_trace(int class_mask);
+
+/*
+ * expm_pfd_trace_summary: totals for one kernel class over the launches
+ * recorded since tracing was enabled.  Waits for the recorded events.
+ *   ms        summed kernel durations (milliseconds)
+ *   launches  number of launches
+ *   flops     algorithmic floating-point operations of those launches
+ *             (complex multiply-add = 8)
+ *   bytes     algorithmic HBM bytes (reads of the operands once, writes once)
+ * Any output pointer may be NULL.
+ */
+int expm_pfd_trace_summary(int kernel_class, double* ms, int64_t* launches, double* flops, double* bytes);
+
 /* Human-readable text for a return code (static storage). */
 const char* expm_pfd_strerror(int code);
 

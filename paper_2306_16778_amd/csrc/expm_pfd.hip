@@ -38,6 +38,53 @@ constexpr int NB = 64;  // outer panel width (also the padding granularity)
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// ---- per-launch event tracing (expm_pfd_trace) ---------------------------------
+namespace trace {
+struct Rec {
+  hipEvent_t a, b;
+  int cls;
+  double flops, bytes;
+};
+unsigned mask = 0;  // bit c set: launches of kernel class c are timed
+std::vector<Rec> recs;
+std::vector<hipEvent_t> pool;
+hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+void clear() {
+  for (auto& r : recs) {
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+// Brackets one kernel launch with an event pair on its stream.
+struct Scope {
+  bool active;
+  hipStream_t s;
+  Rec r{};
+  Scope(hipStream_t st, int cls, double flops, double bytes) : active((mask >> cls) & 1u), s(st) {
+    if (active) {
+      r = {get_event(), get_event(), cls, flops, bytes};
+      (void)hipEventRecord(r.a, s);
+    }
+  }
+  ~Scope() {
+    if (active) {
+      (void)hipEventRecord(r.b, s);
+      recs.push_back(r);
+    }
+  }
+};
+}  // namespace trace
+
 struct HipErr {
   hipError_t e = hipSuccess;
   void operator()(hipError_t x) {
@@ -57,6 +104,9 @@ void panel_launch(hipStream_t st, int P, cx<R>* W, int64_t ws, int64_t ld, int n
                   int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
   constexpr int LIMIT = sizeof(R) == 8 ? 16 : 32;
   if constexpr (IB * S <= LIMIT) {
+    const double rows = npad - c0;
+    trace::Scope ts(st, EXPM_PFD_K_PANEL, (double)P * 4.0 * rows * IB * IB,
+                    (double)P * 2.0 * rows * IB * sizeof(cx<R>));
     hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(1024), 0, st, W, ws, ld, npad, j0, c0, nbo, ipiv, ps,
                        moves, ms, step, last);
   }
@@ -105,10 +155,13 @@ void panel(hipStream_t st, int IB, int S, int P, cx<R>* W, int64_t ws, int64_t l
 
 // C -= op(A) B, batched.  Tile shape by N.
 template <typename R, bool CONJA>
-void gemm(hipStream_t st, int batch, int M, int N, int K, const cx<R>* A, int64_t sA, int64_t lda, const cx<R>* B,
-          int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc) {
+void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, const cx<R>* A, int64_t sA, int64_t lda,
+          const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
-  if (N <= 16) {
+  const double e = sizeof(cx<R>);
+  trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * K,
+                  e * batch * ((double)M * K + (double)K * N + 2.0 * M * N));
+  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM) {
     const int tiles = (int)((M + 63) / 64);
     hipLaunchKernelGGL((k_gemm<R, CONJA, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, A, sA, lda,
                        B, sB, ldb, C, sC, ldc);
@@ -125,6 +178,9 @@ template <typename R, bool LOWER, bool UNIT, bool CONJT, bool MOVES>
 void trsm(hipStream_t st, int batch, const cx<R>* Tm, int64_t sT, int64_t ldt, cx<R>* Bm, int64_t sB, int64_t ldb,
           int ncols, int base, int nb, const int* moves, int64_t smv) {
   if (ncols <= 0) return;
+  const double e = sizeof(cx<R>);
+  trace::Scope ts(st, MOVES ? EXPM_PFD_K_LU_TRSM : EXPM_PFD_K_SOLVE_TRSM, 4.0 * batch * (double)nb * nb * ncols,
+                  e * batch * ((double)nb * nb + 2.0 * nb * ncols));
   const int g = (ncols + TRSM_CW - 1) / TRSM_CW;
   hipLaunchKernelGGL((k_trsm<R, LOWER, UNIT, CONJT, MOVES, TRSM_CW>), dim3(g, batch), dim3(256), 0, st, Tm, sT,
                      ldt, Bm, sB, ldb, ncols, base, nb, moves, smv);
@@ -134,6 +190,7 @@ template <typename R>
 void moves_apply(hipStream_t st, int batch, cx<R>* Bm, int64_t sB, int64_t ldb, int ncols, const int* moves,
                  int64_t smv, int s_begin, int s_end, int inverse) {
   if (ncols <= 0 || s_end <= s_begin) return;
+  trace::Scope ts(st, EXPM_PFD_K_MOVES, 0.0, 0.0);
   const int g = (ncols + 15) / 16;
   hipLaunchKernelGGL((k_moves<R, 16>), dim3(g, batch), dim3(256), 0, st, Bm, sB, ldb, ncols, moves, smv, s_begin,
                      s_end, inverse);
@@ -219,8 +276,13 @@ void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
   const int64_t ld = npad, ws = (int64_t)npad * npad;
   cx<R>* W = (cx<R>*)pl->W;
   dim3 g(npad / 32, npad / 32), b(32, 8);
-  hipLaunchKernelGGL((k_form<R>), g, b, 0, st, (const double2*)A, lda, (int)pl->n, npad, pl->t, pl->d_theta, P, W,
+  {
+    trace::Scope ts(st, EXPM_PFD_K_FORM, 0.0,
+                    (double)pl->n * pl->n * 16 + (double)P * npad * npad * sizeof(cx<R>) +
+                        (pl->Ah ? (double)npad * npad * 16 : 0.0));
+    hipLaunchKernelGGL((k_form<R>), g, b, 0, st, (const double2*)A, lda, (int)pl->n, npad, pl->t, pl->d_theta, P, W,
                      ws, ld, pl->Ah, (int64_t)npad);
+  }
   const int IB = pl->IB;
   int step = 0;
   for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
@@ -233,7 +295,7 @@ void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
       const int rest = j0 + nbo - c0 - IB;
       if (rest > 0) {
         const int64_t r1 = c0 + IB;
-        gemm<R, false>(st, P, npad - c0 - IB, rest, IB, W + r1 * ld + c0, ws, ld, W + (int64_t)c0 * ld + r1, ws,
+        gemm<R, false>(st, EXPM_PFD_K_LU_GEMM, P, npad - c0 - IB, rest, IB, W + r1 * ld + c0, ws, ld, W + (int64_t)c0 * ld + r1, ws,
                        ld, W + r1 * ld + r1, ws, ld);
       }
     }
@@ -245,7 +307,7 @@ void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
       const int64_t c1 = j0 + nbo;
       trsm<R, true, true, false, true>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, W + c1, ws, ld, ntr, j0, nbo, mv,
                                        mstride);
-      gemm<R, false>(st, P, ntr, ntr, nbo, W + c1 * ld + j0, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld,
+      gemm<R, false>(st, EXPM_PFD_K_LU_GEMM, P, ntr, ntr, nbo, W + c1 * ld + j0, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld,
                      W + c1 * ld + c1, ws, ld);
     }
   }
@@ -275,10 +337,10 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
       trsm<R, true, false, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
                                         0);
     if (below > 0) {
-      gemm<R, false>(st, P, below, mp, nb, W + r1 * ld + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
+      gemm<R, false>(st, EXPM_PFD_K_SOLVE_GEMM, P, below, mp, nb, W + r1 * ld + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
                      mp, ldS);
       if (adjoint)
-        gemm<R, true>(st, P, below, mp, nb, W + (int64_t)j0 * ld + r1, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS,
+        gemm<R, true>(st, EXPM_PFD_K_SOLVE_GEMM, P, below, mp, nb, W + (int64_t)j0 * ld + r1, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS,
                       Xa + r1 * ldS, mp, ldS);
     }
   }
@@ -291,9 +353,9 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
       trsm<R, false, true, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
                                         0);
     if (j0 > 0) {
-      gemm<R, false>(st, P, j0, mp, nb, W + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
+      gemm<R, false>(st, EXPM_PFD_K_SOLVE_GEMM, P, j0, mp, nb, W + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
       if (adjoint)
-        gemm<R, true>(st, P, j0, mp, nb, W + (int64_t)j0 * ld, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS, Xa, mp, ldS);
+        gemm<R, true>(st, EXPM_PFD_K_SOLVE_GEMM, P, j0, mp, nb, W + (int64_t)j0 * ld, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS, Xa, mp, ldS);
     }
   }
   // P on the adjoint blocks
@@ -402,44 +464,67 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   const int64_t ldS = (int64_t)nblk * mp;
   const int64_t count = (int64_t)npad * ldS;
   (void)hipGetLastError();
+  const double e64 = 16.0;
+  // residue-weighted accumulation of the solution blocks into X
+  auto accumulate = [&](const double2* Xsrc) {
+    trace::Scope ts(st, EXPM_PFD_K_ACCUM, 8.0 * nblk * (double)pl->n * m,
+                    e64 * ((double)nblk * pl->n * m + (double)pl->n * m));
+    if (full) {
+      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
+      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xsrc, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
+    } else {
+      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, Xsrc, ldS, mp, P, pl->d_a,
+                         (int)pl->n, (int)m, (double2*)X, ldx);
+    }
+  };
   if (pl->precision == EXPM_PFD_FP64) {
     factor<double>(pl, A, lda, st);
     double2* Xs = (double2*)pl->Xs;
-    hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
-                       (const double2*)V, ldv, (int)pl->n, (int)m);
-    solves<double>(pl, Xs, ldS, mp, !full, st);
-    if (full) {
-      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
-      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xs, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
-    } else {
-      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, Xs, ldS, mp, P, pl->d_a,
-                         (int)pl->n, (int)m, (double2*)X, ldx);
+    {
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
+      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
+                         (const double2*)V, ldv, (int)pl->n, (int)m);
     }
+    solves<double>(pl, Xs, ldS, mp, !full, st);
+    accumulate(Xs);
   } else {
     factor<float>(pl, A, lda, st);
     float2* Xs = (float2*)pl->Xs;
-    hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
-                       (const double2*)V, ldv, (int)pl->n, (int)m);
+    {
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 8.0 * count);
+      hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
+                         (const double2*)V, ldv, (int)pl->n, (int)m);
+    }
     solves<float>(pl, Xs, ldS, mp, !full, st);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
+    {
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
+    }
     for (int it = 0; it < pl->ir_sweeps; ++it) {
       // R = V - (tA + theta I) X in FP64, all pole solves at once
-      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, nblk,
-                         (const double2*)V, ldv, (int)pl->n, (int)m);
-      gemm<double, false>(st, 1, npad, (int)ldS, npad, pl->Ah, 0, npad, pl->X64, 0, ldS, pl->R64, 0, ldS);
-      hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp, P,
-                         pl->d_theta);
-      hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, Xs, count);
+      {
+        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
+        hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp,
+                           nblk, (const double2*)V, ldv, (int)pl->n, (int)m);
+      }
+      gemm<double, false>(st, EXPM_PFD_K_IR_GEMM, 1, npad, (int)ldS, npad, pl->Ah, 0, npad, pl->X64, 0, ldS,
+                          pl->R64, 0, ldS);
+      {
+        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, 3 * e64 * count);
+        hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp,
+                           P, pl->d_theta);
+      }
+      {
+        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, Xs, count);
+      }
       solves<float>(pl, Xs, ldS, mp, !full, st);
-      hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
+      {
+        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
+        hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
+      }
     }
-    if (full) {
-      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
-      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, pl->X64, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
-    } else {
-      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, pl->X64, ldS, mp, P, pl->d_a,
-                         (int)pl->n, (int)m, (double2*)X, ldx);
-    }
+    accumulate(pl->X64);
   }
   if (hipGetLastError() != hipSuccess) return EXPM_PFD_ERR_HIP;
   return 0;
@@ -485,6 +570,33 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
     free_plan(kv.second);
   }
   return rc;
+}
+
+extern "C" int expm_pfd_trace(int class_mask) {
+  trace::clear();
+  trace::mask = (unsigned)class_mask & ((1u << EXPM_PFD_K_COUNT) - 1u);
+  return 0;
+}
+
+extern "C" int expm_pfd_trace_summary(int cls, double* ms, int64_t* launches, double* flops, double* bytes) {
+  if (cls < 0 || cls >= EXPM_PFD_K_COUNT) return EXPM_PFD_ERR_ARG;
+  double t = 0, f = 0, b = 0;
+  int64_t k = 0;
+  for (auto& r : trace::recs) {
+    if (r.cls != cls) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    float x = 0;
+    if (hipEventElapsedTime(&x, r.a, r.b) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    t += x;
+    f += r.flops;
+    b += r.bytes;
+    ++k;
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = k;
+  if (flops) *flops = f;
+  if (bytes) *bytes = b;
+  return 0;
 }
 
 extern "C" const char* expm_pfd_strerror(int code) {

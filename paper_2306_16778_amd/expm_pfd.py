@@ -34,7 +34,13 @@ EXPORTED = (
     "expm_pfd_destroy",
     "expm_pfd_apply_batched",
     "expm_pfd_strerror",
+    "expm_pfd_trace",
+    "expm_pfd_trace_summary",
 )
+
+# kernel classes of the tracer (EXPM_PFD_K_*)
+KERNEL_CLASSES = ("form", "panel", "lu_gemm", "lu_trsm", "moves", "solve_trsm", "solve_gemm", "accum",
+                  "ir_gemm", "elementwise")
 
 
 class ExpmPfdError(RuntimeError):
@@ -66,6 +72,9 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_destroy.argtypes = [vp]
     lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(_Opts), vp]
+    lib.expm_pfd_trace.argtypes = [c_int]
+    lib.expm_pfd_trace_summary.argtypes = [c_int, ctypes.POINTER(c_double), ctypes.POINTER(i64),
+                                           ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
     lib.expm_pfd_strerror.argtypes = [c_int]
     lib.expm_pfd_strerror.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -217,3 +226,21 @@ def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degr
                                       ldv.ctypes.data, m.ctypes.data, px, ldx.ctypes.data, ctypes.byref(o),
                                       _stream_ptr(stream, torch)), "expm_pfd_apply_batched")
     return Xs
+
+
+def expm_pfd_trace(classes=()):
+    """Time later launches of the given kernel classes (names or indices); () stops. Clears records."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << (KERNEL_CLASSES.index(c) if isinstance(c, str) else int(c))
+    _check(load_library().expm_pfd_trace(mask), "expm_pfd_trace")
+
+
+def expm_pfd_trace_summary(kernel_class):
+    """dict(ms, launches, flops, bytes) for a kernel class (name or EXPM_PFD_K_* index)."""
+    cls = KERNEL_CLASSES.index(kernel_class) if isinstance(kernel_class, str) else int(kernel_class)
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    k = ctypes.c_int64()
+    _check(load_library().expm_pfd_trace_summary(cls, ctypes.byref(ms), ctypes.byref(k), ctypes.byref(fl),
+                                                 ctypes.byref(by)), "expm_pfd_trace_summary")
+    return {"ms": ms.value, "launches": k.value, "flops": fl.value, "bytes": by.value}
