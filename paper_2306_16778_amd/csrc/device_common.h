@@ -97,6 +97,81 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
+// ---- wave-wide reductions through DPP (gfx9 row broadcasts) ---------------
+// dpp_ctrl codes: quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E, row_half_mirror
+// = 0x141, row_mirror = 0x140, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+// Lanes whose DPP source is masked off keep their own value (old = src).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(dpp_i32<CTRL, ROWMASK>(__float_as_int(v)));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL, ROWMASK>((int)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL, ROWMASK>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// maximum over the 16 lanes of each row, valid in every lane of the row
+template <typename R>
+__device__ __forceinline__ R row16_max(R x) {
+  x = fmax(x, dpp_move<0xB1, 0xF>(x));
+  x = fmax(x, dpp_move<0x4E, 0xF>(x));
+  x = fmax(x, dpp_move<0x141, 0xF>(x));
+  x = fmax(x, dpp_move<0x140, 0xF>(x));
+  return x;
+}
+__device__ __forceinline__ int row16_min(int x) {
+  x = min(x, dpp_i32<0xB1, 0xF>(x));
+  x = min(x, dpp_i32<0x4E, 0xF>(x));
+  x = min(x, dpp_i32<0x141, 0xF>(x));
+  x = min(x, dpp_i32<0x140, 0xF>(x));
+  return x;
+}
+// maximum over the wave, returned in every lane
+template <typename R>
+__device__ __forceinline__ R wave_max(R x) {
+  x = row16_max(x);
+  x = fmax(x, dpp_move<0x142, 0xA>(x));
+  x = fmax(x, dpp_move<0x143, 0xC>(x));
+  if constexpr (sizeof(R) == 8) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+  }
+}
+__device__ __forceinline__ int wave_min(int x) {
+  x = row16_min(x);
+  x = min(x, dpp_i32<0x142, 0xA>(x));
+  x = min(x, dpp_i32<0x143, 0xC>(x));
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+// Value of lane k (k uniform across the wave) in every lane.
+__device__ __forceinline__ float lane_bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T lane_bcast2(T v, int k) {
+  T r;
+  r.x = lane_bcast(v.x, k);
+  r.y = lane_bcast(v.y, k);
+  return r;
+}
+
 // ---- row interchanges -----------------------------------------------------
 // Row moves of one factorization step are stored as
 //   [count, dst[0..MOVE_CAP), src[0..MOVE_CAP)]
@@ -108,15 +183,18 @@ constexpr int MOVE_STRIDE = 1 + 2 * MOVE_CAP;
 // Run by one full wave.  Simulates the interchanges (base+i) <-> piv[i],
 // i = 0..cnt-1 (cnt <= 64, piv[i] >= base+i, applied in order), and writes the
 // net row moves to dst/src.  Returns the number of moves (same on all lanes).
+// piv is read once (one element per lane); every later exchange of values
+// between lanes uses readlane with a wave-uniform lane index.
 __device__ inline int composite_moves(const int* piv, int cnt, int base, int* dst, int* src) {
   const int lane = threadIdx.x & 63;
+  const int mypiv = lane < cnt ? piv[lane] : 0;
   int cur = base + lane;  // original row now at position base+lane
   int key = -1, val = 0;  // one position outside [base, base+cnt) tracked by this lane
   for (int i = 0; i < cnt; ++i) {
-    const int b = piv[i];
-    const int ta = __shfl(cur, i);
+    const int b = __builtin_amdgcn_readlane(mypiv, i);
+    const int ta = __builtin_amdgcn_readlane(cur, i);
     if (b < base + cnt) {
-      const int tb = __shfl(cur, b - base);
+      const int tb = __builtin_amdgcn_readlane(cur, b - base);
       if (lane == i) cur = tb;
       if (lane == b - base) cur = ta;
     } else {
@@ -124,7 +202,7 @@ __device__ inline int composite_moves(const int* piv, int cnt, int base, int* ds
       int slot, tb;
       if (m) {
         slot = __ffsll((long long)m) - 1;
-        tb = __shfl(val, slot);
+        tb = __builtin_amdgcn_readlane(val, slot);
       } else {
         slot = i;
         tb = b;

@@ -92,33 +92,42 @@ struct HipErr {
   }
 };
 
+// Inner panel width: the register panel holds IB columns of ceil(npad/1024)
+// rows per thread (<= 16 complex per thread in FP64, 32 in FP32) and is staged
+// through a 1024 x IB LDS buffer of 128 KB.
 int inner_width(int64_t npad, bool fp64) {
-  if (fp64) return npad <= 1024 ? 16 : npad <= 2048 ? 8 : npad <= 4096 ? 4 : 2;
+  if (fp64) return npad <= 2048 ? 8 : npad <= 4096 ? 4 : 2;
   return npad <= 2048 ? 16 : npad <= 4096 ? 8 : 4;
 }
 
 // ---- launch helpers ---------------------------------------------------------
 
+struct PanelArgs {
+  int64_t ws, ld, ps, ms;
+  int P, npad, j0, c0, nbo, step, last;
+  int* ipiv;
+  int* moves;
+};
+
 template <typename R, int IB, int S>
-void panel_launch(hipStream_t st, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0, int nbo,
-                  int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+void panel_launch(hipStream_t st, const PanelArgs& g, cx<R>* W) {
+  const int P = g.P;
   constexpr int LIMIT = sizeof(R) == 8 ? 16 : 32;
-  if constexpr (IB * S <= LIMIT) {
-    const double rows = npad - c0;
+  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 || IB <= 8)) {
+    const double rows = g.npad - g.c0;
     trace::Scope ts(st, EXPM_PFD_K_PANEL, (double)P * 4.0 * rows * IB * IB,
                     (double)P * 2.0 * rows * IB * sizeof(cx<R>));
-    hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(1024), 0, st, W, ws, ld, npad, j0, c0, nbo, ipiv, ps,
-                       moves, ms, step, last);
+    hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(1024), 0, st, W, g.ws, g.ld, g.npad, g.j0, g.c0, g.nbo,
+                       g.ipiv, g.ps, g.moves, g.ms, g.step, g.last);
   }
 }
 
 template <typename R, int IB>
-void panel_dispatch(hipStream_t st, int S, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0,
-                    int nbo, int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+void panel_dispatch(hipStream_t st, int S, const PanelArgs& g, cx<R>* W) {
   switch (S) {
-#define CASE(s)                                                                                             \
-  case s:                                                                                                   \
-    panel_launch<R, IB, s>(st, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last); \
+#define CASE(s)                                   \
+  case s:                                         \
+    panel_launch<R, IB, s>(st, g, W); \
     break;
     CASE(1)
     CASE(2)
@@ -135,65 +144,72 @@ void panel_dispatch(hipStream_t st, int S, int P, cx<R>* W, int64_t ws, int64_t 
 }
 
 template <typename R>
-void panel(hipStream_t st, int IB, int S, int P, cx<R>* W, int64_t ws, int64_t ld, int npad, int j0, int c0,
-           int nbo, int* ipiv, int64_t ps, int* moves, int64_t ms, int step, int last) {
+void panel(hipStream_t st, int IB, int S, const PanelArgs& g, cx<R>* W) {
   switch (IB) {
     case 16:
-      panel_dispatch<R, 16>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      panel_dispatch<R, 16>(st, S, g, W);
       break;
     case 8:
-      panel_dispatch<R, 8>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      panel_dispatch<R, 8>(st, S, g, W);
       break;
     case 4:
-      panel_dispatch<R, 4>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      panel_dispatch<R, 4>(st, S, g, W);
       break;
     default:
-      panel_dispatch<R, 2>(st, S, P, W, ws, ld, npad, j0, c0, nbo, ipiv, ps, moves, ms, step, last);
+      panel_dispatch<R, 2>(st, S, g, W);
       break;
   }
 }
 
-// C -= op(A) B, batched.  Tile shape by N.
-template <typename R, bool CONJA>
-void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, const cx<R>* A, int64_t sA, int64_t lda,
+// MODE 0: C -= op(A) B;  MODE 1: C = op(A) B.  Batches < split use a0, others a1.
+template <typename R, int MODE>
+void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
           const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
   const double e = sizeof(cx<R>);
   trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * K,
-                  e * batch * ((double)M * K + (double)K * N + 2.0 * M * N));
+                  e * batch * ((double)M * K + (double)K * N + (MODE == 0 ? 2.0 : 1.0) * M * N));
   if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM) {
     const int tiles = (int)((M + 63) / 64);
-    hipLaunchKernelGGL((k_gemm<R, CONJA, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, A, sA, lda,
+    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, a0, a1, split,
                        B, sB, ldb, C, sC, ldc);
   } else {
     const int tiles = (int)(((M + 63) / 64) * ((N + 63) / 64));
-    hipLaunchKernelGGL((k_gemm<R, CONJA, 64, 64, 2, 2>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, A, sA,
-                       lda, B, sB, ldb, C, sC, ldc);
+    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 64, 2, 2>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, a0, a1, split,
+                       B, sB, ldb, C, sC, ldc);
   }
 }
 
-constexpr int TRSM_CW = 16;
-
-template <typename R, bool LOWER, bool UNIT, bool CONJT, bool MOVES>
-void trsm(hipStream_t st, int batch, const cx<R>* Tm, int64_t sT, int64_t ldt, cx<R>* Bm, int64_t sB, int64_t ldb,
-          int ncols, int base, int nb, const int* moves, int64_t smv) {
-  if (ncols <= 0) return;
-  const double e = sizeof(cx<R>);
-  trace::Scope ts(st, MOVES ? EXPM_PFD_K_LU_TRSM : EXPM_PFD_K_SOLVE_TRSM, 4.0 * batch * (double)nb * nb * ncols,
-                  e * batch * ((double)nb * nb + 2.0 * nb * ncols));
-  const int g = (ncols + TRSM_CW - 1) / TRSM_CW;
-  hipLaunchKernelGGL((k_trsm<R, LOWER, UNIT, CONJT, MOVES, TRSM_CW>), dim3(g, batch), dim3(256), 0, st, Tm, sT,
-                     ldt, Bm, sB, ldb, ncols, base, nb, moves, smv);
+template <typename R>
+GemmOperand<R> opnd(const cx<R>* p, int64_t stride, int64_t ld, bool conj) {
+  GemmOperand<R> o;
+  o.p = p;
+  o.stride = stride;
+  o.ld = ld;
+  o.conj = conj ? 1 : 0;
+  return o;
 }
 
 template <typename R>
-void moves_apply(hipStream_t st, int batch, cx<R>* Bm, int64_t sB, int64_t ldb, int ncols, const int* moves,
-                 int64_t smv, int s_begin, int s_end, int inverse) {
+void moves_apply(hipStream_t st, int batch, cx<R>* Bm, int64_t sB, int64_t ldb, int ncols, int gap_at, int gap_len,
+                 const int* moves, int64_t smv, int s_begin, int s_end, int inverse) {
   if (ncols <= 0 || s_end <= s_begin) return;
   trace::Scope ts(st, EXPM_PFD_K_MOVES, 0.0, 0.0);
   const int g = (ncols + 15) / 16;
-  hipLaunchKernelGGL((k_moves<R, 16>), dim3(g, batch), dim3(256), 0, st, Bm, sB, ldb, ncols, moves, smv, s_begin,
-                     s_end, inverse);
+  hipLaunchKernelGGL((k_moves<R, 16>), dim3(g, batch), dim3(256), 0, st, Bm, sB, ldb, ncols, gap_at, gap_len, moves,
+                     smv, s_begin, s_end, inverse);
+}
+
+// which: 0 = L11^{-1}, 1 = U11^{-1}, 2 = both, for steps [step0, step0 + nsteps)
+template <typename R>
+void block_inverse(hipStream_t st, int batch, const cx<R>* W, int64_t ws, int64_t ld, int step0, int nsteps,
+                   int which, cx<R>* dinv, int64_t ds) {
+  if (nsteps <= 0) return;
+  const int nmat = which == 2 ? 2 : 1;
+  trace::Scope ts(st, EXPM_PFD_K_PANEL, 8.0 * batch * nsteps * nmat * NB * NB * NB / 6.0,
+                  sizeof(cx<R>) * 2.0 * batch * nsteps * nmat * NB * NB);
+  hipLaunchKernelGGL((k_block_inverse<R>), dim3(16 * nmat * nsteps, batch), dim3(64), 0, st, W, ws, ld, step0, which,
+                     dinv, ds);
 }
 
 inline int grid_for(int64_t count) {
@@ -218,6 +234,7 @@ struct expm_pfd_plan_s {
   void* W = nullptr;    // P x npad x npad, FP64 or FP32 complex, row-major
   int* ipiv = nullptr;  // P x npad
   int* moves = nullptr; // P x nsteps x MOVE_STRIDE
+  void* dinv = nullptr;  // P x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
   void* Xs = nullptr;   // npad x cols_alloc, working type
   int64_t cols_alloc = 0;
   double2* Ah = nullptr;   // mixed: npad x npad FP64 t*A (Hermitian, row-major)
@@ -230,8 +247,8 @@ namespace {
 
 struct Sizes {
   int64_t npad, cols, w_elem;
-  size_t w, ipiv, moves, xs, ah, x64, r64, consts;
-  size_t total() const { return w + ipiv + moves + xs + ah + x64 + r64 + consts; }
+  size_t w, ipiv, moves, dinv, xs, ah, x64, r64, consts;
+  size_t total() const { return w + ipiv + moves + dinv + xs + ah + x64 + r64 + consts; }
 };
 
 Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
@@ -246,6 +263,7 @@ Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
   s.w = (size_t)P * s.npad * s.npad * s.w_elem;
   s.ipiv = (size_t)P * s.npad * sizeof(int);
   s.moves = (size_t)P * (s.npad / NB) * MOVE_STRIDE * sizeof(int);
+  s.dinv = (size_t)P * (s.npad / NB) * 2 * NB * NB * s.w_elem;
   s.xs = (size_t)s.npad * s.cols * s.w_elem;
   s.ah = fp64 ? 0 : (size_t)s.npad * s.npad * 16;
   s.x64 = fp64 ? 0 : (size_t)s.npad * s.cols * 16;
@@ -262,7 +280,7 @@ int check_opts(const expm_pfd_opts* o) {
 
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
-  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->Xs, p->Ah, p->X64, p->R64};
+  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->dinv, p->Xs, p->Ah, p->X64, p->R64};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -284,33 +302,53 @@ void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
                      ws, ld, pl->Ah, (int64_t)npad);
   }
   const int IB = pl->IB;
+  cx<R>* dinv = (cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
   int step = 0;
   for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
     const int nbo = std::min(NB, npad - j0);
     for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
-      const int last = (c0 + IB >= j0 + nbo);
-      const int S = (npad - c0 + 1023) / 1024;
-      panel<R>(st, IB, S, P, W, ws, ld, npad, j0, c0, nbo, pl->ipiv, npad, pl->moves,
-               (int64_t)pl->nsteps * MOVE_STRIDE, step, last);
+      PanelArgs g;
+      g.ws = ws;
+      g.ld = ld;
+      g.ps = npad;
+      g.ms = mstride;
+      g.P = P;
+      g.npad = npad;
+      g.j0 = j0;
+      g.c0 = c0;
+      g.nbo = nbo;
+      g.step = step;
+      g.last = (c0 + IB >= j0 + nbo);
+      g.ipiv = pl->ipiv;
+      g.moves = pl->moves;
+      panel<R>(st, IB, (npad - c0 + 1023) / 1024, g, W);
       const int rest = j0 + nbo - c0 - IB;
       if (rest > 0) {
         const int64_t r1 = c0 + IB;
-        gemm<R, false>(st, EXPM_PFD_K_LU_GEMM, P, npad - c0 - IB, rest, IB, W + r1 * ld + c0, ws, ld, W + (int64_t)c0 * ld + r1, ws,
-                       ld, W + r1 * ld + r1, ws, ld);
+        gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, P, npad - c0 - IB, rest, IB, opnd<R>(W + r1 * ld + c0, ws, ld, false),
+                   opnd<R>(nullptr, 0, 0, false), P, W + (int64_t)c0 * ld + r1, ws, ld, W + r1 * ld + r1, ws, ld);
       }
     }
     const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
-    const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-    if (j0 > 0) moves_apply<R>(st, P, W, ws, ld, j0, mv, mstride, 0, 1, 0);
     const int ntr = npad - j0 - nbo;
+    // the step's interchanges on the columns left and right of the panel
+    moves_apply<R>(st, P, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
     if (ntr > 0) {
       const int64_t c1 = j0 + nbo;
-      trsm<R, true, true, false, true>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, W + c1, ws, ld, ntr, j0, nbo, mv,
-                                       mstride);
-      gemm<R, false>(st, EXPM_PFD_K_LU_GEMM, P, ntr, ntr, nbo, W + c1 * ld + j0, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld,
-                     W + c1 * ld + c1, ws, ld);
+      block_inverse<R>(st, P, W, ws, ld, step, 1, 0, dinv, ds);
+      const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
+      // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
+      gemm<R, 1>(st, EXPM_PFD_K_LU_GEMM, P, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
+                 P, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
+      gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, P, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+                 opnd<R>(nullptr, 0, 0, false), P, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
     }
   }
+  // diagonal-block inverses still missing for the sweeps: every U11, the last L11
+  block_inverse<R>(st, P, W, ws, ld, 0, pl->nsteps, 1, dinv, ds);
+  block_inverse<R>(st, P, W, ws, ld, pl->nsteps - 1, 1, 0, dinv, ds);
 }
 
 // ---- solves on all right-hand-side blocks ----------------------------------------
@@ -322,44 +360,40 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
   const int npad = (int)pl->npad;
   const int64_t ld = npad, ws = (int64_t)npad * npad;
   const cx<R>* W = (const cx<R>*)pl->W;
+  const cx<R>* dinv = (const cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
   const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-  cx<R>* Xa = X + (int64_t)P * mp;
   const int nsteps = pl->nsteps;
+  const int nb_batch = adjoint ? 2 * P : P;  // primal blocks 0..P-1, adjoint blocks P..2P-1
   // P^T on the primal blocks
-  moves_apply<R>(st, P, X, mp, ldS, mp, pl->moves, mstride, 0, nsteps, 0);
-  // forward sweeps: L (primal), U^H (adjoint)
+  moves_apply<R>(st, P, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  // forward sweeps: L (primal) and U^H (adjoint); diagonal blocks by their inverses
   for (int s = 0; s < nsteps; ++s) {
     const int j0 = s * NB, nb = std::min(NB, npad - j0);
     const int64_t r1 = j0 + nb;
     const int below = npad - j0 - nb;
-    trsm<R, true, true, false, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, X, mp, ldS, mp, j0, nb, nullptr, 0);
-    if (adjoint)
-      trsm<R, true, false, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
-                                        0);
-    if (below > 0) {
-      gemm<R, false>(st, EXPM_PFD_K_SOLVE_GEMM, P, below, mp, nb, W + r1 * ld + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
-                     mp, ldS);
-      if (adjoint)
-        gemm<R, true>(st, EXPM_PFD_K_SOLVE_GEMM, P, below, mp, nb, W + (int64_t)j0 * ld + r1, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS,
-                      Xa + r1 * ldS, mp, ldS);
-    }
+    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
+    const cx<R>* Uinv = Linv + NB * NB;
+    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Linv, ds, NB, false), opnd<R>(Uinv, ds, NB, true),
+               P, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+    if (below > 0)
+      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, below, mp, nb, opnd<R>(W + r1 * ld + j0, ws, ld, false),
+                 opnd<R>(W + (int64_t)j0 * ld + r1, ws, ld, true), P, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS, mp,
+                 ldS);
   }
-  // backward sweeps: U (primal), L^H (adjoint)
+  // backward sweeps: U (primal) and L^H (adjoint)
   for (int s = nsteps - 1; s >= 0; --s) {
     const int j0 = s * NB, nb = std::min(NB, npad - j0);
-    trsm<R, false, false, false, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, X, mp, ldS, mp, j0, nb, nullptr,
-                                        0);
-    if (adjoint)
-      trsm<R, false, true, true, false>(st, P, W + (int64_t)j0 * ld + j0, ws, ld, Xa, mp, ldS, mp, j0, nb, nullptr,
-                                        0);
-    if (j0 > 0) {
-      gemm<R, false>(st, EXPM_PFD_K_SOLVE_GEMM, P, j0, mp, nb, W + j0, ws, ld, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
-      if (adjoint)
-        gemm<R, true>(st, EXPM_PFD_K_SOLVE_GEMM, P, j0, mp, nb, W + (int64_t)j0 * ld, ws, ld, Xa + (int64_t)j0 * ldS, mp, ldS, Xa, mp, ldS);
-    }
+    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
+    const cx<R>* Uinv = Linv + NB * NB;
+    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Uinv, ds, NB, false), opnd<R>(Linv, ds, NB, true),
+               P, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+    if (j0 > 0)
+      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, j0, mp, nb, opnd<R>(W + j0, ws, ld, false),
+                 opnd<R>(W + (int64_t)j0 * ld, ws, ld, true), P, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
   }
   // P on the adjoint blocks
-  if (adjoint) moves_apply<R>(st, P, Xa, mp, ldS, mp, pl->moves, mstride, 0, nsteps, 1);
+  if (adjoint) moves_apply<R>(st, P, X + (int64_t)P * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
 }
 
 int validate_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m, void* X,
@@ -424,6 +458,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   he(hipMalloc(&pl->W, sz.w));
   he(hipMalloc(&pl->ipiv, sz.ipiv));
   he(hipMalloc(&pl->moves, sz.moves));
+  he(hipMalloc(&pl->dinv, sz.dinv));
   he(hipMalloc(&pl->Xs, sz.xs));
   if (pl->precision == EXPM_PFD_MIXED) {
     he(hipMalloc(&pl->Ah, sz.ah));
@@ -507,8 +542,8 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
         hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp,
                            nblk, (const double2*)V, ldv, (int)pl->n, (int)m);
       }
-      gemm<double, false>(st, EXPM_PFD_K_IR_GEMM, 1, npad, (int)ldS, npad, pl->Ah, 0, npad, pl->X64, 0, ldS,
-                          pl->R64, 0, ldS);
+      gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, 1, npad, (int)ldS, npad, opnd<double>(pl->Ah, 0, npad, false),
+                      opnd<double>(nullptr, 0, 0, false), 1, pl->X64, 0, ldS, pl->R64, 0, ldS);
       {
         trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, 3 * e64 * count);
         hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp,

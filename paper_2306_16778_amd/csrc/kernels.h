@@ -74,28 +74,125 @@ __global__ __launch_bounds__(256) void k_form(const double2* __restrict__ A, int
 
 // ---------------------------------------------------------------------------
 // K2: panel factorization with partial pivoting (LAPACK getf2 order) of the
-// IB columns [c0, c0+IB) over rows [c0, npad), for one shifted matrix per
+// IB columns [c0, c0+IB) over rows [c0, npad), one shifted matrix per
 // workgroup.  The panel lives in registers: thread t owns rows c0+t+1024s.
-// Per column: pivot = argmax |Re|+|Im| (lowest row on ties) by wave reductions
-// and one LDS exchange, pivot row broadcast through LDS, rank-1 update in
-// registers (two barriers per column).
+// Per column (one barrier): every wave finds its candidate row (largest
+// |Re|+|Im|, lowest row on ties) with DPP reductions and publishes value, row
+// index and row contents in LDS; after the barrier every wave reduces the 16
+// candidates the same way, swaps the pivot row in and applies the rank-1
+// update in registers.  The panel is loaded and stored through LDS so that
+// global accesses are coalesced.
 // Then, inside the enclosing outer panel [j0, j0+nbo): the IB interchanges are
 // applied to the other outer-panel columns and the IB x (rest) block of U is
-// solved with the unit lower IB x IB factor.  If this is the last inner step,
-// the net row moves of the whole outer step are written for later use.
-// grid (P), block 1024
+// solved with the unit lower IB x IB factor.  On the last inner step the net
+// row moves of the whole outer step are written for the later updates.
+// grid (batch), block 1024
 // ---------------------------------------------------------------------------
+template <typename R, int IB>
+struct PanelShared {
+  R cand_v[2][16];
+  int cand_i[2][16];
+  cx<R> cand_row[2][16][IB];  // each wave's candidate row
+  cx<R> crow[2][IB];          // row gc before the interchange
+  int piv[NB_MAX];
+};
+
+template <typename R, int IB, int S, int C>
+__device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, IB>& sh, int c0, int j0, int npad,
+                                             int tid) {
+  if constexpr (C < IB) {
+    using T = cx<R>;
+    constexpr int NONE = 0x7fffffff;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int gc = c0 + C;
+    constexpr int buf = C & 1;
+    R bv = -1;
+    int bi = NONE;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = c0 + tid + 1024 * s;
+      if (r >= gc && r < npad) {
+        const R v = fabs(a[s][C].x) + fabs(a[s][C].y);
+        if (v > bv) {
+          bv = v;
+          bi = r;
+        }
+      }
+    }
+    // wave candidate: maximum value, then the lowest row among the lanes holding it
+    const R wv = wave_max(bv);
+    const unsigned long long m = __ballot(bv == wv);
+    const int wi = (__popcll(m) == 1) ? __builtin_amdgcn_readlane(bi, __ffsll((long long)m) - 1)
+                                       : wave_min(bv == wv ? bi : NONE);
+    if (lane == 0) {
+      sh.cand_v[buf][wid] = wv;
+      sh.cand_i[buf][wid] = wi;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = c0 + tid + 1024 * s;
+      if (r == wi) {
+#pragma unroll
+        for (int cc = 0; cc < IB; ++cc) sh.cand_row[buf][wid][cc] = a[s][cc];
+      }
+      if (r == gc) {
+#pragma unroll
+        for (int cc = 0; cc < IB; ++cc) sh.crow[buf][cc] = a[s][cc];
+      }
+    }
+    __syncthreads();
+    // global pivot: each row of 16 lanes reduces the 16 wave candidates
+    const R cv = sh.cand_v[buf][lane & 15];
+    const int ci = sh.cand_i[buf][lane & 15];
+    const R gv = row16_max(cv);
+    const int gi = __builtin_amdgcn_readlane(row16_min(cv == gv ? ci : NONE), 0);
+    // no candidate compared greater (a column of NaNs): keep the diagonal row, so
+    // every later row index stays inside the matrix
+    const bool found = gi >= gc && gi < npad;
+    const int p = found ? gi : gc;
+    const T* prow = found ? sh.cand_row[buf][((p - c0) & 1023) >> 6] : sh.crow[buf];
+    if (tid == 0) sh.piv[gc - j0] = p;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = c0 + tid + 1024 * s;
+      if (r == gc) {
+#pragma unroll
+        for (int cc = 0; cc < IB; ++cc) a[s][cc] = prow[cc];
+      } else if (r == p) {
+#pragma unroll
+        for (int cc = 0; cc < IB; ++cc) a[s][cc] = sh.crow[buf][cc];
+      }
+    }
+    const T inv = crecip(prow[C]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = c0 + tid + 1024 * s;
+      if (r > gc && r < npad) {
+        const T l = cmul(a[s][C], inv);
+        a[s][C] = l;
+#pragma unroll
+        for (int cc = C + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, prow[cc]);
+      }
+    }
+    panel_column<R, IB, S, C + 1>(a, sh, c0, j0, npad, tid);
+  }
+}
+
+// LDS staging slot of element (row, col) of a 1024 x IB block; the column is
+// XOR-swizzled with the row so that one-row-per-lane reads spread over banks.
+template <int IB>
+__device__ __forceinline__ int stage_slot(int row, int col) {
+  return row * IB + (col ^ (row & (IB - 1)));
+}
+
 template <typename R, int IB, int S>
 __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld, int npad, int j0,
                                                 int c0, int nbo, int* __restrict__ ipivb, int64_t pstride,
                                                 int* __restrict__ movesb, int64_t mstride, int step, int last) {
   using T = cx<R>;
-  __shared__ R red_v[2][16];
-  __shared__ int red_i[2][16];
-  __shared__ T prow[2][IB];
-  __shared__ T crow[2][IB];
+  __shared__ PanelShared<R, IB> sh;
+  __shared__ T stage[1024 * IB];  // panel staging; reused as the row-move buffer
   __shared__ T Lib[IB][IB + 1];
-  __shared__ T mvbuf[2 * IB][NB_MAX];
   __shared__ int mv_dst[MOVE_CAP], mv_src[MOVE_CAP];
   __shared__ int mv_cnt;
 
@@ -104,127 +201,70 @@ __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t 
   int* ipiv = ipivb + b * pstride;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
+  if (tid < c0 - j0) sh.piv[tid] = ipiv[j0 + tid];  // pivots of the earlier inner steps
   T a[S][IB];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int r = c0 + tid + 1024 * s;
+    const int rbase = c0 + 1024 * s;
+    const int nr = npad - rbase < 1024 ? npad - rbase : 1024;
+    if (nr > 0) {
+      for (int e = tid; e < nr * IB; e += 1024) {
+        const int row = e / IB, col = e % IB;
+        stage[stage_slot<IB>(row, col)] = W[(int64_t)(rbase + row) * ld + c0 + col];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int c = 0; c < IB; ++c) a[s][c] = (r < npad) ? W[(int64_t)r * ld + c0 + c] : czero<T>();
+      for (int c = 0; c < IB; ++c) a[s][c] = tid < nr ? stage[stage_slot<IB>(tid, c)] : czero<T>();
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int c = 0; c < IB; ++c) a[s][c] = czero<T>();
+    }
   }
-
-#pragma unroll
-  for (int c = 0; c < IB; ++c) {
-    const int gc = c0 + c, buf = c & 1;
-    R bv = -1;
-    int bi = 0x7fffffff;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
-      if (r >= gc && r < npad) {
-        const R v = fabs(a[s][c].x) + fabs(a[s][c].y);
-        if (v > bv) {
-          bv = v;
-          bi = r;
-        }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const R ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      red_v[buf][wid] = bv;
-      red_i[buf][wid] = bi;
-    }
-    __syncthreads();
-    bv = red_v[buf][0];
-    bi = red_i[buf][0];
-#pragma unroll
-    for (int w = 1; w < 16; ++w) {
-      const R ov = red_v[buf][w];
-      const int oi = red_i[buf][w];
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    const int p = bi;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
-      if (r == p) {
-#pragma unroll
-        for (int cc = 0; cc < IB; ++cc) prow[buf][cc] = a[s][cc];
-      }
-      if (r == gc && p != gc) {
-#pragma unroll
-        for (int cc = 0; cc < IB; ++cc) crow[buf][cc] = a[s][cc];
-      }
-    }
-    __syncthreads();
-    // the pivot row is read from LDS where needed (broadcast reads), not held in registers
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
-      if (r == gc) {
-#pragma unroll
-        for (int cc = 0; cc < IB; ++cc) a[s][cc] = prow[buf][cc];
-      } else if (r == p) {
-#pragma unroll
-        for (int cc = 0; cc < IB; ++cc) a[s][cc] = crow[buf][cc];
-      }
-    }
-    const T inv = crecip(prow[buf][c]);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
-      if (r > gc && r < npad) {
-        const T l = cmul(a[s][c], inv);
-        a[s][c] = l;
-#pragma unroll
-        for (int cc = c + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, prow[buf][cc]);
-      }
-    }
-    if (tid == 0) ipiv[gc] = p;
-  }
+  panel_column<R, IB, S, 0>(a, sh, c0, j0, npad, tid);
 
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int r = c0 + tid + 1024 * s;
-    if (r < npad) {
+    const int rbase = c0 + 1024 * s;
+    const int nr = npad - rbase < 1024 ? npad - rbase : 1024;
+    if (nr > 0) {
+      if (tid < nr) {
 #pragma unroll
-      for (int c = 0; c < IB; ++c) W[(int64_t)r * ld + c0 + c] = a[s][c];
+        for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(tid, c)] = a[s][c];
+      }
+      __syncthreads();
+      for (int e = tid; e < nr * IB; e += 1024) {
+        const int row = e / IB, col = e % IB;
+        W[(int64_t)(rbase + row) * ld + c0 + col] = stage[stage_slot<IB>(row, col)];
+      }
+      __syncthreads();
     }
+  }
+  if (tid < IB) {
+#pragma unroll
+    for (int c = 0; c < IB; ++c) Lib[tid][c] = a[0][c];  // rows c0..c0+IB of the factored panel
+    ipiv[c0 + tid] = sh.piv[c0 - j0 + tid];
+  }
+  if (wid == 0) {
+    const int cnt = composite_moves(sh.piv + (c0 - j0), IB, c0, mv_dst, mv_src);
+    if (lane == 0) mv_cnt = cnt;
   }
   __syncthreads();
 
   // ---- interchanges on the other columns of the outer panel, then U block --
-  if (wid == 0) {
-    const int cnt = composite_moves(ipiv + c0, IB, c0, mv_dst, mv_src);
-    if (lane == 0) mv_cnt = cnt;
-  }
-  if (tid < IB * IB) {
-    const int i = tid / IB, k = tid % IB;
-    Lib[i][k] = W[(int64_t)(c0 + i) * ld + c0 + k];
-  }
-  __syncthreads();
+  T* mvbuf = stage;  // [2*IB][NB_MAX]
   const int nleft = c0 - j0, nright = j0 + nbo - c0 - IB, nother = nleft + nright;
   const int cnt = mv_cnt;
   for (int e = tid; e < cnt * nother; e += 1024) {
     const int i = e / nother, cc = e % nother;
     const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
-    mvbuf[i][cc] = W[(int64_t)mv_src[i] * ld + col];
+    mvbuf[i * NB_MAX + cc] = W[(int64_t)mv_src[i] * ld + col];
   }
   __syncthreads();
   for (int e = tid; e < cnt * nother; e += 1024) {
     const int i = e / nother, cc = e % nother;
     const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
-    W[(int64_t)mv_dst[i] * ld + col] = mvbuf[i][cc];
+    W[(int64_t)mv_dst[i] * ld + col] = mvbuf[i * NB_MAX + cc];
   }
   __syncthreads();
   if (tid < nright) {
@@ -240,16 +280,95 @@ __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t 
     for (int i = 1; i < IB; ++i) W[(int64_t)(c0 + i) * ld + col] = x[i];
   }
   if (last && wid == 0) {
+    // net row moves of the whole outer step
     int* mv = movesb + b * mstride + (int64_t)step * MOVE_STRIDE;
-    const int cnt2 = composite_moves(ipiv + j0, nbo, j0, mv + 1, mv + 1 + MOVE_CAP);
+    const int cnt2 = composite_moves(sh.piv, nbo, j0, mv + 1, mv + 1 + MOVE_CAP);
     if (lane == 0) mv[0] = cnt2;
   }
 }
 
 // ---------------------------------------------------------------------------
-// K5: C -= op(A) * B for complex matrices on the matrix cores, batched over
-// blockIdx.y.  op(A) = A (row-major M x K, lda) or, with CONJA, the conjugate
-// transpose of a row-major K x M array.  B row-major K x N, C row-major M x N.
+// Inverses of the nb x nb diagonal blocks of the LU factors: L11^{-1} (unit
+// lower) and U11^{-1} (upper), so that the triangular solves of the update and
+// the sweeps run as matrix-core products.  One wave per column of an inverse:
+// lane i holds row i; forward (L) or backward (U) substitution with the
+// current pivot value broadcast by readlane.  Four columns per wave are
+// carried together to overlap the dependency chains.
+// grid (16 * nsteps_range * (1 or 2), batch), block 64; blockIdx.x encodes
+// (step, L or U, group of 4 columns).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld,
+                                                      int step0, int which, cx<R>* __restrict__ dinvb,
+                                                      int64_t dstride) {
+  using T = cx<R>;
+  constexpr int NB = NB_MAX;
+  __shared__ T D[NB][NB + 1];
+  __shared__ T rdiag[NB];
+  const int nmat = which == 2 ? 2 : 1;  // which: 0 = L only, 1 = U only, 2 = both
+  const int g = blockIdx.x;
+  const int cgrp = g % 16;
+  const int mat = (g / 16) % nmat;
+  const int step = step0 + g / (16 * nmat);
+  const bool upper = which == 1 || (which == 2 && mat == 1);
+  const int b = blockIdx.y;
+  const T* W = Wb + b * wstride;
+  const int j0 = step * NB;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < NB * NB; e += 64) {
+    const int i = e / NB, k = e % NB;
+    D[i][k] = W[(int64_t)(j0 + i) * ld + j0 + k];
+  }
+  __syncthreads();
+  if (upper) rdiag[lane] = crecip(D[lane][lane]);
+  __syncthreads();
+  T one = czero<T>();
+  one.x = 1;
+  const int i = lane;
+  T x[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) x[q] = (i == cgrp * 4 + q) ? one : czero<T>();
+  if (!upper) {
+    const int cmin = cgrp * 4;
+    for (int k = cmin; k < NB - 1; ++k) {
+      const T lik = D[i][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T xk = lane_bcast2(x[q], k);
+        if (i > k) x[q] = cfms(x[q], lik, xk);
+      }
+    }
+  } else {
+    const int cmax = cgrp * 4 + 3;
+    for (int k = cmax; k >= 0; --k) {
+      const T uik = D[i][k];
+      const T rk = rdiag[k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (i == k) x[q] = cmul(x[q], rk);
+        const T xk = lane_bcast2(x[q], k);
+        if (i < k) x[q] = cfms(x[q], uik, xk);
+      }
+    }
+  }
+  T* out = dinvb + b * dstride + (int64_t)step * 2 * NB * NB + (upper ? NB * NB : 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cgrp * 4 + q;
+    const bool keep = upper ? (i <= c) : (i >= c);
+    out[i * NB + c] = keep ? x[q] : czero<T>();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K5: complex matrix products on the matrix cores, batched over blockIdx.y:
+//   MODE 0:  C -= op(A) B        MODE 1:  C = op(A) B
+// op(A) = A (row-major M x K) or, with conj, the conjugate transpose of a
+// row-major K x M array.  Batches b < split use operand a0 (at a0.p +
+// b*a0.stride), the others a1 (at a1.p + (b-split)*a1.stride), so a primal and
+// an adjoint sweep share one launch.  B row-major K x N, C row-major M x N.
+// MODE 1 may overwrite B in place when one row tile covers M (BM >= M): every
+// workgroup reads all of its B columns before writing them.
 // Complex products from real 16x16x4 products: the K dimension is interleaved
 // (real index 2k = real part, 2k+1 = imaginary part), so with b = (Re B, Im B)
 // per k, Re C uses a = (Re A, -Im A) and Im C uses a = (Im A, Re A): two real
@@ -257,10 +376,17 @@ __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t 
 // Tiles BM x BN per 256-thread workgroup, waves WGM x WGN, K staged through LDS
 // in chunks of 16.
 // ---------------------------------------------------------------------------
-template <typename R, bool CONJA, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cx<R>* __restrict__ A, int64_t sA,
-                                              int64_t lda, const cx<R>* __restrict__ B, int64_t sB, int64_t ldb,
-                                              cx<R>* __restrict__ C, int64_t sC, int64_t ldc) {
+template <typename R>
+struct GemmOperand {
+  const cx<R>* p;
+  int64_t stride, ld;
+  int conj;
+};
+
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
+                                              const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
+                                              int64_t ldc) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
@@ -273,7 +399,10 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cx<R>* 
   const int tiles_m = (M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
   const int bb = blockIdx.y;
-  A += bb * sA;
+  const bool second = bb >= split;
+  const GemmOperand<R> op = second ? a1 : a0;
+  const T* A = op.p + (second ? bb - split : bb) * op.stride;
+  const int64_t lda = op.ld;
   B += bb * sB;
   C += bb * sC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -291,7 +420,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cx<R>* 
     }
 
   for (int k0 = 0; k0 < K; k0 += KC) {
-    if (!CONJA) {
+    if (!op.conj) {
       for (int e = tid; e < BM * KC; e += 256) {
         const int i = e / KC, k = e % KC;
         T v = czero<T>();
@@ -348,112 +477,35 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const cx<R>* 
         const int row = m0 + wm0 + i * 16 + MF::row(kq, r);
         const int col = n0 + wn0 + j * 16 + r16;
         if (row < M && col < N) {
-          T c = C[(int64_t)row * ldc + col];
-          c.x -= accR[i][j][r];
-          c.y -= accI[i][j][r];
+          T c;
+          if (MODE == 0) {
+            c = C[(int64_t)row * ldc + col];
+            c.x -= accR[i][j][r];
+            c.y -= accI[i][j][r];
+          } else {
+            c.x = accR[i][j][r];
+            c.y = accI[i][j][r];
+          }
           C[(int64_t)row * ldc + col] = c;
         }
       }
 }
 
 // ---------------------------------------------------------------------------
-// K3/K4: triangular solve with an nb x nb diagonal block, on CW columns per
-// workgroup: B[base:base+nb, cols] <- op(T)^{-1} B[base:base+nb, cols].
-// op(T) is the stored row-major block (LOWER/UPPER part, UNIT diagonal or not)
-// or, with CONJT, the conjugate transpose of the stored block.
-// With MOVES the step's row moves are applied to the columns first (rows
-// anywhere in the matrix; moved rows outside the block are written back).
-// grid (ceil(ncols/CW), batch), block 256.  Substitution in LDS, row by row.
-// ---------------------------------------------------------------------------
-template <typename R, bool LOWER, bool UNIT, bool CONJT, bool MOVES, int CW>
-__global__ __launch_bounds__(256) void k_trsm(const cx<R>* __restrict__ Tm, int64_t sT, int64_t ldt,
-                                              cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols,
-                                              int base, int nb, const int* __restrict__ moves, int64_t smv) {
-  using T = cx<R>;
-  __shared__ T Ts[NB_MAX][NB_MAX + 1];
-  __shared__ T Bt[NB_MAX][CW];
-  __shared__ T Mv[MOVES ? MOVE_CAP : 1][CW];
-  const int bb = blockIdx.y;
-  Tm += bb * sT;
-  Bm += bb * sB;
-  const int tid = threadIdx.x;
-  const int cb = blockIdx.x * CW;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e / nb, k = e % nb;
-    T v;
-    if (!CONJT) {
-      v = Tm[(int64_t)i * ldt + k];
-    } else {
-      v = cconj(Tm[(int64_t)k * ldt + i]);
-    }
-    Ts[i][k] = v;
-  }
-  for (int e = tid; e < nb * CW; e += 256) {
-    const int i = e / CW, c = e % CW;
-    Bt[i][c] = (cb + c < ncols) ? Bm[(int64_t)(base + i) * ldb + cb + c] : czero<T>();
-  }
-  if (MOVES) {
-    const int* mv = moves + bb * smv;
-    const int cnt = mv[0];
-    const int* dst = mv + 1;
-    const int* src = mv + 1 + MOVE_CAP;
-    for (int e = tid; e < cnt * CW; e += 256) {
-      const int i = e / CW, c = e % CW;
-      Mv[i][c] = (cb + c < ncols) ? Bm[(int64_t)src[i] * ldb + cb + c] : czero<T>();
-    }
-    __syncthreads();
-    for (int e = tid; e < cnt * CW; e += 256) {
-      const int i = e / CW, c = e % CW;
-      const int d = dst[i];
-      if (d >= base && d < base + nb)
-        Bt[d - base][c] = Mv[i][c];
-      else if (cb + c < ncols)
-        Bm[(int64_t)d * ldb + cb + c] = Mv[i][c];
-    }
-  }
-  __syncthreads();
-  if (LOWER) {
-    for (int k = 0; k < nb; ++k) {
-      if (!UNIT) {
-        if (tid < CW) Bt[k][tid] = cdiv(Bt[k][tid], Ts[k][k]);
-        __syncthreads();
-      }
-      for (int e = tid; e < (nb - k - 1) * CW; e += 256) {
-        const int i = k + 1 + e / CW, c = e % CW;
-        Bt[i][c] = cfms(Bt[i][c], Ts[i][k], Bt[k][c]);
-      }
-      __syncthreads();
-    }
-  } else {
-    for (int k = nb - 1; k >= 0; --k) {
-      if (!UNIT) {
-        if (tid < CW) Bt[k][tid] = cdiv(Bt[k][tid], Ts[k][k]);
-        __syncthreads();
-      }
-      for (int e = tid; e < k * CW; e += 256) {
-        const int i = e / CW, c = e % CW;
-        Bt[i][c] = cfms(Bt[i][c], Ts[i][k], Bt[k][c]);
-      }
-      __syncthreads();
-    }
-  }
-  for (int e = tid; e < nb * CW; e += 256) {
-    const int i = e / CW, c = e % CW;
-    if (cb + c < ncols) Bm[(int64_t)(base + i) * ldb + cb + c] = Bt[i][c];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Row moves of factorization steps [s_begin, s_end) applied to ncols columns:
 // forward (P^T, steps in order, new[dst] = old[src]) or inverse (P, steps in
-// reverse order, new[src] = old[dst]).  grid (ceil(ncols/CW), batch)
+// reverse order, new[src] = old[dst]).  Logical column c is physical column
+// c (c < gap_at) or c + gap_len, so the columns on both sides of a panel are
+// moved by one launch.  grid (ceil(ncols/CW), batch)
 // ---------------------------------------------------------------------------
 template <typename R, int CW>
-__global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols,
-                                               const int* __restrict__ moves, int64_t smv, int s_begin,
+__global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols, int gap_at,
+                                               int gap_len, const int* __restrict__ moves, int64_t smv, int s_begin,
                                                int s_end, int inverse) {
   using T = cx<R>;
   __shared__ T Mv[MOVE_CAP][CW];
+  __shared__ int from_s[MOVE_CAP], to_s[MOVE_CAP];
+  __shared__ int cnt_s;
   const int bb = blockIdx.y;
   Bm += bb * sB;
   const int* mvb = moves + bb * smv;
@@ -463,17 +515,23 @@ __global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t s
   for (int q = 0; q < ns; ++q) {
     const int step = inverse ? s_end - 1 - q : s_begin + q;
     const int* mv = mvb + (int64_t)step * MOVE_STRIDE;
-    const int cnt = mv[0];
-    const int* from = inverse ? mv + 1 : mv + 1 + MOVE_CAP;
-    const int* to = inverse ? mv + 1 + MOVE_CAP : mv + 1;
+    if (tid == 0) cnt_s = mv[0];
+    if (tid < MOVE_CAP) {
+      from_s[tid] = inverse ? mv[1 + tid] : mv[1 + MOVE_CAP + tid];
+      to_s[tid] = inverse ? mv[1 + MOVE_CAP + tid] : mv[1 + tid];
+    }
+    __syncthreads();
+    const int cnt = cnt_s;
     for (int e = tid; e < cnt * CW; e += 256) {
       const int i = e / CW, c = e % CW;
-      if (cb + c < ncols) Mv[i][c] = Bm[(int64_t)from[i] * ldb + cb + c];
+      const int lc = cb + c;
+      if (lc < ncols) Mv[i][c] = Bm[(int64_t)from_s[i] * ldb + (lc < gap_at ? lc : lc + gap_len)];
     }
     __syncthreads();
     for (int e = tid; e < cnt * CW; e += 256) {
       const int i = e / CW, c = e % CW;
-      if (cb + c < ncols) Bm[(int64_t)to[i] * ldb + cb + c] = Mv[i][c];
+      const int lc = cb + c;
+      if (lc < ncols) Bm[(int64_t)to_s[i] * ldb + (lc < gap_at ? lc : lc + gap_len)] = Mv[i][c];
     }
     __syncthreads();
   }
