@@ -235,6 +235,7 @@ struct expm_pfd_plan_s {
   int* ipiv = nullptr;  // P x npad
   int* moves = nullptr; // P x nsteps x MOVE_STRIDE
   void* dinv = nullptr;  // P x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
+  void* sweepbuf = nullptr;  // 2 x 2P x 64 x 16 staging of the fused sweeps
   void* Xs = nullptr;   // npad x cols_alloc, working type
   int64_t cols_alloc = 0;
   double2* Ah = nullptr;   // mixed: npad x npad FP64 t*A (Hermitian, row-major)
@@ -247,8 +248,8 @@ namespace {
 
 struct Sizes {
   int64_t npad, cols, w_elem;
-  size_t w, ipiv, moves, dinv, xs, ah, x64, r64, consts;
-  size_t total() const { return w + ipiv + moves + dinv + xs + ah + x64 + r64 + consts; }
+  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, consts;
+  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + consts; }
 };
 
 Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
@@ -264,6 +265,7 @@ Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
   s.ipiv = (size_t)P * s.npad * sizeof(int);
   s.moves = (size_t)P * (s.npad / NB) * MOVE_STRIDE * sizeof(int);
   s.dinv = (size_t)P * (s.npad / NB) * 2 * NB * NB * s.w_elem;
+  s.sweep = (size_t)2 * 2 * P * NB * 16 * s.w_elem;
   s.xs = (size_t)s.npad * s.cols * s.w_elem;
   s.ah = fp64 ? 0 : (size_t)s.npad * s.npad * 16;
   s.x64 = fp64 ? 0 : (size_t)s.npad * s.cols * 16;
@@ -280,7 +282,7 @@ int check_opts(const expm_pfd_opts* o) {
 
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
-  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->dinv, p->Xs, p->Ah, p->X64, p->R64};
+  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->dinv, p->sweepbuf, p->Xs, p->Ah, p->X64, p->R64};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -355,7 +357,62 @@ void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
 // Blocks [0, P) hold primal right-hand sides (pair p), blocks [P, 2P) (if adjoint)
 // the conjugate-pole ones; each block is mp columns of the row-major npad x ldS X.
 template <typename R>
+SweepOperand<R> sweep_op(const cx<R>* p, int64_t stride, int64_t ld, bool conj) {
+  SweepOperand<R> o;
+  o.p = p;
+  o.stride = stride;
+  o.ld = ld;
+  o.conj = conj ? 1 : 0;
+  return o;
+}
+
+// Right-hand sides of 16 columns: one fused launch per block step and sweep.
+template <typename R>
+void solves16(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, bool adjoint, hipStream_t st) {
+  const int P = pl->P, mp = 16;
+  const int npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const cx<R>* W = (const cx<R>*)pl->W;
+  const cx<R>* dinv = (const cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  const int nsteps = pl->nsteps;
+  const int nbatch = adjoint ? 2 * P : P;
+  const int64_t sbuf = NB * 16;
+  cx<R>* buf[2] = {(cx<R>*)pl->sweepbuf, (cx<R>*)pl->sweepbuf + (int64_t)nbatch * sbuf};
+  const double e = sizeof(cx<R>);
+  moves_apply<R>(st, P, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  for (int dirn = 0; dirn < 2; ++dirn) {
+    const bool fwd = dirn == 0;
+    {
+      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 0.0, 2.0 * e * nbatch * sbuf);
+      hipLaunchKernelGGL((k_gather16<R>), dim3(nbatch), dim3(256), 0, st, X, (int64_t)mp, ldS,
+                         fwd ? 0 : (nsteps - 1) * NB, buf[0], sbuf);
+    }
+    // forward: L (primal), U^H (adjoint); backward: U (primal), L^H (adjoint)
+    const SweepOperand<R> d0 = sweep_op<R>(fwd ? dinv : dinv + NB * NB, ds, NB, false);
+    const SweepOperand<R> d1 = sweep_op<R>(fwd ? dinv + NB * NB : dinv, ds, NB, true);
+    const SweepOperand<R> a0 = sweep_op<R>(W, ws, ld, false);
+    const SweepOperand<R> a1 = sweep_op<R>(W, ws, ld, true);
+    for (int q = 0; q < nsteps; ++q) {
+      const int J = fwd ? q : nsteps - 1 - q;
+      const int ntiles = fwd ? nsteps - 1 - J : J;
+      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nbatch * (1.0 + ntiles) * NB * NB * 16 + 8.0 * nbatch * ntiles * NB * NB * 16,
+                      e * nbatch * ((1.0 + ntiles) * NB * NB + 2.0 * ntiles * NB * 16));
+      hipLaunchKernelGGL((k_sweep16<R>), dim3(1 + ntiles, nbatch), dim3(256), 0, st, J, fwd ? J + 1 : J - 1,
+                         fwd ? 1 : -1, d0, d1, a0, a1, P, X, (int64_t)mp, ldS, buf[q & 1], buf[(q + 1) & 1], sbuf);
+    }
+  }
+  if (adjoint) moves_apply<R>(st, P, X + (int64_t)P * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
+}
+
+template <typename R>
 void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+  // fused sweeps pay off in FP32; in FP64 their 84 KB of LDS leaves one workgroup per CU
+  if (mp == 16 && sizeof(R) == 4) {
+    solves16<R>(pl, X, ldS, adjoint, st);
+    return;
+  }
   const int P = pl->P;
   const int npad = (int)pl->npad;
   const int64_t ld = npad, ws = (int64_t)npad * npad;
@@ -459,6 +516,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   he(hipMalloc(&pl->ipiv, sz.ipiv));
   he(hipMalloc(&pl->moves, sz.moves));
   he(hipMalloc(&pl->dinv, sz.dinv));
+  he(hipMalloc(&pl->sweepbuf, sz.sweep));
   he(hipMalloc(&pl->Xs, sz.xs));
   if (pl->precision == EXPM_PFD_MIXED) {
     he(hipMalloc(&pl->Ah, sz.ah));

@@ -392,9 +392,11 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
   using V = typename MF::V;
   constexpr int KC = 16;
   constexpr int WM = BM / WGM, WN = BN / WGN, MI = WM / 16, NJ = WN / 16;
+  constexpr int AE = BM * KC / 256, BE = KC * BN / 256;  // chunk elements per thread
   static_assert(WGM * WGN == 4, "four waves");
-  __shared__ T As[BM][KC + 1];
-  __shared__ T Bs[KC][BN + 1];
+  static_assert(AE >= 1 && BE >= 1, "tile too small");
+  __shared__ T As[2][BM][KC + 1];
+  __shared__ T Bs[2][KC][BN + 1];
 
   const int tiles_m = (M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
@@ -403,6 +405,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
   const GemmOperand<R> op = second ? a1 : a0;
   const T* A = op.p + (second ? bb - split : bb) * op.stride;
   const int64_t lda = op.ld;
+  const bool conj = op.conj != 0;
   B += bb * sB;
   C += bb * sC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -410,6 +413,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
   const int r16 = lane & 15, kq = lane >> 4;
   const int m0 = tm * BM, n0 = tn * BN;
 
+  // the products are summed on their own and subtracted from C once, in the
+  // epilogue (MODE 0), so C's magnitude does not enter every rounding step
   V accR[MI][NJ], accI[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -419,29 +424,54 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
       accI[i][j] = V{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    if (!op.conj) {
-      for (int e = tid; e < BM * KC; e += 256) {
+  // one K chunk of A (op applied, conjugated if needed) and B into registers
+  T ra[AE], rb[BE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = tid + 256 * q;
+      T v = czero<T>();
+      if (!conj) {
         const int i = e / KC, k = e % KC;
-        T v = czero<T>();
         if (m0 + i < M && k0 + k < K) v = A[(int64_t)(m0 + i) * lda + k0 + k];
-        As[i][k] = v;
-      }
-    } else {
-      for (int e = tid; e < BM * KC; e += 256) {
+      } else {
         const int i = e % BM, k = e / BM;
-        T v = czero<T>();
         if (m0 + i < M && k0 + k < K) v = cconj(A[(int64_t)(k0 + k) * lda + m0 + i]);
-        As[i][k] = v;
       }
+      ra[q] = v;
     }
-    for (int e = tid; e < KC * BN; e += 256) {
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = tid + 256 * q;
       const int j = e % BN, k = e / BN;
       T v = czero<T>();
       if (n0 + j < N && k0 + k < K) v = B[(int64_t)(k0 + k) * ldb + n0 + j];
-      Bs[k][j] = v;
+      rb[q] = v;
     }
-    __syncthreads();
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = tid + 256 * q;
+      if (!conj)
+        As[buf][e / KC][e % KC] = ra[q];
+      else
+        As[buf][e % BM][e / BM] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = tid + 256 * q;
+      Bs[buf][e / BN][e % BN] = rb[q];
+    }
+  };
+
+  const int nchunks = (K + KC - 1) / KC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < nchunks) fetch((ch + 1) * KC);  // in flight during the products below
 #pragma unroll
     for (int k2 = 0; k2 < KC / 2; ++k2) {
       const int kc = 2 * k2 + (kq >> 1);
@@ -449,13 +479,13 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
       R aR[MI], aI[MI], bR[NJ];
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
-        const T av = As[wm0 + i * 16 + r16][kc];
+        const T av = As[cur][wm0 + i * 16 + r16][kc];
         aR[i] = odd ? -av.y : av.x;
         aI[i] = odd ? av.x : av.y;
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const T bv = Bs[kc][wn0 + j * 16 + r16];
+        const T bv = Bs[cur][kc][wn0 + j * 16 + r16];
         bR[j] = odd ? bv.y : bv.x;
       }
 #pragma unroll
@@ -466,6 +496,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
           accI[i][j] = MF::run(aI[i], bR[j], accI[i][j]);
         }
     }
+    if (ch + 1 < nchunks) stash(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -489,6 +520,130 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
           C[(int64_t)row * ldc + col] = c;
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// One step J of a block triangular sweep on 16-column right-hand sides,
+// fused into one launch (nb = 64):
+//   x_J = D_J b_J           D_J = inverse of the diagonal block (or its
+//                            conjugate transpose), applied as a product
+//   X_I -= A_IJ x_J         for the row tiles I still to be updated
+// Workgroup 0 of a batch writes x_J into rows J; workgroup t >= 1 updates row
+// tile I = tile0 + dir*(t-1) and, if I is the next diagonal block, also copies
+// the updated rows to bout so the next step reads b_{J+dir} from there (the
+// rows of X itself are rewritten concurrently by that step's workgroup 0).
+// A_IJ is W[I rows][J cols] or, with conj, the conjugate transpose of
+// W[J rows][I cols].  Batches < split use operands *0, the others *1.
+// grid (1 + ntiles, batch), block 256 (four waves, 16 rows each)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct SweepOperand {
+  const cx<R>* p;
+  int64_t stride, ld;
+  int conj;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sweep16(int J, int tile0, int dir, SweepOperand<R> d0, SweepOperand<R> d1,
+                                                 SweepOperand<R> a0, SweepOperand<R> a1, int split, cx<R>* X,
+                                                 int64_t sX, int64_t ldx, const cx<R>* bin, cx<R>* bout,
+                                                 int64_t sbuf) {
+  using T = cx<R>;
+  using MF = Mfma<R>;
+  using V = typename MF::V;
+  constexpr int NB = NB_MAX;
+  __shared__ T As[NB][NB + 1];
+  __shared__ T Bs[NB][17];
+  const int bb = blockIdx.y;
+  const bool second = bb >= split;
+  const int hb = second ? bb - split : bb;
+  const SweepOperand<R> dop = second ? d1 : d0;
+  const SweepOperand<R> aop = second ? a1 : a0;
+  X += bb * sX;
+  bin += bb * sbuf;
+  bout += bb * sbuf;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+
+  // x_J = D_J b_J
+  const T* D = dop.p + hb * dop.stride + (int64_t)J * 2 * NB * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e / NB, k = e % NB;
+    As[i][k] = dop.conj ? cconj(D[k * NB + i]) : D[i * NB + k];
+  }
+  for (int e = tid; e < NB * 16; e += 256) Bs[e / 16][e % 16] = bin[e];
+  __syncthreads();
+  auto product = [&](V& accR, V& accI) {
+    accR = V{0, 0, 0, 0};
+    accI = V{0, 0, 0, 0};
+#pragma unroll 8
+    for (int k2 = 0; k2 < NB / 2; ++k2) {
+      const int kc = 2 * k2 + (kq >> 1);
+      const bool odd = kq & 1;
+      const T av = As[16 * w + r16][kc];
+      const T bv = Bs[kc][r16];
+      const R bR = odd ? bv.y : bv.x;
+      accR = MF::run(odd ? -av.y : av.x, bR, accR);
+      accI = MF::run(odd ? av.x : av.y, bR, accI);
+    }
+  };
+  V xR, xI;
+  product(xR, xI);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + MF::row(kq, r);
+      T v;
+      v.x = xR[r];
+      v.y = xI[r];
+      X[(int64_t)(J * NB + row) * ldx + r16] = v;
+    }
+    return;
+  }
+  // X_I -= A_IJ x_J
+  const int I = tile0 + dir * ((int)blockIdx.x - 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T v;
+    v.x = xR[r];
+    v.y = xI[r];
+    Bs[16 * w + MF::row(kq, r)][r16] = v;
+  }
+  const T* W = aop.p + hb * aop.stride;
+  for (int e = tid; e < NB * NB; e += 256) {
+    if (!aop.conj) {
+      const int i = e / NB, k = e % NB;
+      As[i][k] = W[(int64_t)(I * NB + i) * aop.ld + J * NB + k];
+    } else {
+      const int k = e / NB, i = e % NB;
+      As[i][k] = cconj(W[(int64_t)(J * NB + k) * aop.ld + I * NB + i]);
+    }
+  }
+  __syncthreads();
+  V yR, yI;
+  product(yR, yI);
+  const bool next = I == J + dir;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * w + MF::row(kq, r);
+    T* px = X + (int64_t)(I * NB + row) * ldx + r16;
+    T v = *px;
+    v.x -= yR[r];
+    v.y -= yI[r];
+    *px = v;
+    if (next) bout[row * 16 + r16] = v;
+  }
+}
+
+// Copy rows [row0, row0+64) of every 16-column block into a staging buffer
+// (the first b_J of a fused sweep).  grid (batch), block 256.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather16(const cx<R>* __restrict__ X, int64_t sX, int64_t ldx, int row0,
+                                                  cx<R>* __restrict__ buf, int64_t sbuf) {
+  const int bb = blockIdx.x;
+  for (int e = threadIdx.x; e < NB_MAX * 16; e += 256)
+    buf[bb * sbuf + e] = X[bb * sX + (int64_t)(row0 + e / 16) * ldx + e % 16];
 }
 
 // ---------------------------------------------------------------------------
