@@ -172,6 +172,23 @@ __device__ __forceinline__ T lane_bcast2(T v, int k) {
   return r;
 }
 
+// ---- problem descriptors ----------------------------------------------------
+// One exp(t A) V problem as the caller laid it out (column-major, FP64 complex).
+struct ProblemDesc {
+  const double2* A;
+  int64_t lda;
+  const double2* V;  // nullptr: V = I
+  int64_t ldv;
+  double2* X;
+  int64_t ldx;
+  double t;
+  int n, m;
+};
+// descriptor g of a group: from the device array, or the single inline one
+__device__ __forceinline__ ProblemDesc desc_of(const ProblemDesc* arr, const ProblemDesc& one, int g) {
+  return arr ? arr[g] : one;
+}
+
 // ---- row interchanges -----------------------------------------------------
 // Row moves of one factorization step are stored as
 //   [count, dst[0..MOVE_CAP), src[0..MOVE_CAP)]

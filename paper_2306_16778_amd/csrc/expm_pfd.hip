@@ -220,27 +220,29 @@ inline int grid_for(int64_t count) {
 }  // namespace
 
 // ============================================================================
-// plan
+// plan: workspace for G problems of the same padded order (G = 1 for
+// expm_pfd_plan; groups of the batched entry point use G > 1).  Every launch of
+// the factorization and the solves covers all G*P shifted matrices.
 // ============================================================================
 struct expm_pfd_plan_s {
-  int64_t n = 0, npad = 0, m_max = 0;
-  int degree = 0, P = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16;
+  int64_t n = 0, npad = 0, m_max = 0;  // n, m_max: the single-problem arguments
+  int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
   double t = 1;
   bool full_ok = false;
-  int nsteps = 0;
+  int64_t mp_max = 16, cols_alloc = 0;
   std::vector<double2> h_theta, h_a;
   double2* d_theta = nullptr;
   double2* d_a = nullptr;
-  void* W = nullptr;    // P x npad x npad, FP64 or FP32 complex, row-major
-  int* ipiv = nullptr;  // P x npad
-  int* moves = nullptr; // P x nsteps x MOVE_STRIDE
-  void* dinv = nullptr;  // P x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
-  void* sweepbuf = nullptr;  // 2 x 2P x 64 x 16 staging of the fused sweeps
-  void* Xs = nullptr;   // npad x cols_alloc, working type
-  int64_t cols_alloc = 0;
-  double2* Ah = nullptr;   // mixed: npad x npad FP64 t*A (Hermitian, row-major)
-  double2* X64 = nullptr;  // mixed: npad x cols_alloc
-  double2* R64 = nullptr;  // mixed: npad x cols_alloc
+  void* W = nullptr;         // PB x npad x npad, FP64 or FP32 complex, row-major
+  int* ipiv = nullptr;       // PB x npad
+  int* moves = nullptr;      // PB x nsteps x MOVE_STRIDE
+  void* dinv = nullptr;      // PB x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
+  void* sweepbuf = nullptr;  // 2 x 2PB x 64 x 16 staging of the fused sweeps
+  void* Xs = nullptr;        // npad x cols_alloc, working type
+  double2* Ah = nullptr;     // mixed: G x npad x npad FP64 t*A (Hermitian, row-major)
+  double2* X64 = nullptr;    // mixed: npad x cols_alloc
+  double2* R64 = nullptr;    // mixed: npad x cols_alloc
+  ProblemDesc* d_descs = nullptr;  // G problem descriptors on the device (batched entry point)
   int device = 0;
 };
 
@@ -248,29 +250,28 @@ namespace {
 
 struct Sizes {
   int64_t npad, cols, w_elem;
-  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, consts;
-  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + consts; }
+  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, consts, descs;
+  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + consts + descs; }
 };
 
-Sizes plan_sizes(int64_t n, int degree, int64_t m_max, int precision) {
+Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision) {
   Sizes s{};
-  const int P = degree / 2;
-  s.npad = round_up(n, NB);
-  const bool full_ok = (m_max == 0 || m_max >= n);
-  const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
-  s.cols = std::max<int64_t>(full_ok ? (int64_t)P * s.npad : 0, 2 * (int64_t)P * mp);
+  const int64_t PB = (int64_t)G * (degree / 2);
+  s.npad = npad;
+  s.cols = std::max<int64_t>(full_ok ? PB * npad : 0, 2 * PB * mp_max);
   const bool fp64 = precision == EXPM_PFD_FP64;
   s.w_elem = fp64 ? 16 : 8;
-  s.w = (size_t)P * s.npad * s.npad * s.w_elem;
-  s.ipiv = (size_t)P * s.npad * sizeof(int);
-  s.moves = (size_t)P * (s.npad / NB) * MOVE_STRIDE * sizeof(int);
-  s.dinv = (size_t)P * (s.npad / NB) * 2 * NB * NB * s.w_elem;
-  s.sweep = (size_t)2 * 2 * P * NB * 16 * s.w_elem;
-  s.xs = (size_t)s.npad * s.cols * s.w_elem;
-  s.ah = fp64 ? 0 : (size_t)s.npad * s.npad * 16;
-  s.x64 = fp64 ? 0 : (size_t)s.npad * s.cols * 16;
+  s.w = (size_t)PB * npad * npad * s.w_elem;
+  s.ipiv = (size_t)PB * npad * sizeof(int);
+  s.moves = (size_t)PB * (npad / NB) * MOVE_STRIDE * sizeof(int);
+  s.dinv = (size_t)PB * (npad / NB) * 2 * NB * NB * s.w_elem;
+  s.sweep = (size_t)2 * 2 * PB * NB * 16 * s.w_elem;
+  s.xs = (size_t)npad * s.cols * s.w_elem;
+  s.ah = fp64 ? 0 : (size_t)G * npad * npad * 16;
+  s.x64 = fp64 ? 0 : (size_t)npad * s.cols * 16;
   s.r64 = s.x64;
   s.consts = 2 * 64 * 16;
+  s.descs = (size_t)G * sizeof(ProblemDesc);
   return s;
 }
 
@@ -282,225 +283,29 @@ int check_opts(const expm_pfd_opts* o) {
 
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
-  void* ptrs[] = {p->d_theta, p->d_a, p->W, p->ipiv, p->moves, p->dinv, p->sweepbuf, p->Xs, p->Ah, p->X64, p->R64};
+  void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
+                  p->sweepbuf, p->Xs, p->Ah, p->X64,  p->R64,   p->d_descs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
 }
 
-// ---- factorization of all pairs ------------------------------------------------
-template <typename R>
-void factor(expm_pfd_plan_t pl, const void* A, int64_t lda, hipStream_t st) {
-  const int P = pl->P;
-  const int npad = (int)pl->npad;
-  const int64_t ld = npad, ws = (int64_t)npad * npad;
-  cx<R>* W = (cx<R>*)pl->W;
-  dim3 g(npad / 32, npad / 32), b(32, 8);
-  {
-    trace::Scope ts(st, EXPM_PFD_K_FORM, 0.0,
-                    (double)pl->n * pl->n * 16 + (double)P * npad * npad * sizeof(cx<R>) +
-                        (pl->Ah ? (double)npad * npad * 16 : 0.0));
-    hipLaunchKernelGGL((k_form<R>), g, b, 0, st, (const double2*)A, lda, (int)pl->n, npad, pl->t, pl->d_theta, P, W,
-                     ws, ld, pl->Ah, (int64_t)npad);
-  }
-  const int IB = pl->IB;
-  cx<R>* dinv = (cx<R>*)pl->dinv;
-  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
-  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-  int step = 0;
-  for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
-    const int nbo = std::min(NB, npad - j0);
-    for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
-      PanelArgs g;
-      g.ws = ws;
-      g.ld = ld;
-      g.ps = npad;
-      g.ms = mstride;
-      g.P = P;
-      g.npad = npad;
-      g.j0 = j0;
-      g.c0 = c0;
-      g.nbo = nbo;
-      g.step = step;
-      g.last = (c0 + IB >= j0 + nbo);
-      g.ipiv = pl->ipiv;
-      g.moves = pl->moves;
-      panel<R>(st, IB, (npad - c0 + 1023) / 1024, g, W);
-      const int rest = j0 + nbo - c0 - IB;
-      if (rest > 0) {
-        const int64_t r1 = c0 + IB;
-        gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, P, npad - c0 - IB, rest, IB, opnd<R>(W + r1 * ld + c0, ws, ld, false),
-                   opnd<R>(nullptr, 0, 0, false), P, W + (int64_t)c0 * ld + r1, ws, ld, W + r1 * ld + r1, ws, ld);
-      }
-    }
-    const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
-    const int ntr = npad - j0 - nbo;
-    // the step's interchanges on the columns left and right of the panel
-    moves_apply<R>(st, P, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
-    if (ntr > 0) {
-      const int64_t c1 = j0 + nbo;
-      block_inverse<R>(st, P, W, ws, ld, step, 1, 0, dinv, ds);
-      const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
-      // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
-      gemm<R, 1>(st, EXPM_PFD_K_LU_GEMM, P, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
-                 P, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
-      gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, P, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
-                 opnd<R>(nullptr, 0, 0, false), P, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
-    }
-  }
-  // diagonal-block inverses still missing for the sweeps: every U11, the last L11
-  block_inverse<R>(st, P, W, ws, ld, 0, pl->nsteps, 1, dinv, ds);
-  block_inverse<R>(st, P, W, ws, ld, pl->nsteps - 1, 1, 0, dinv, ds);
-}
-
-// ---- solves on all right-hand-side blocks ----------------------------------------
-// Blocks [0, P) hold primal right-hand sides (pair p), blocks [P, 2P) (if adjoint)
-// the conjugate-pole ones; each block is mp columns of the row-major npad x ldS X.
-template <typename R>
-SweepOperand<R> sweep_op(const cx<R>* p, int64_t stride, int64_t ld, bool conj) {
-  SweepOperand<R> o;
-  o.p = p;
-  o.stride = stride;
-  o.ld = ld;
-  o.conj = conj ? 1 : 0;
-  return o;
-}
-
-// Right-hand sides of 16 columns: one fused launch per block step and sweep.
-template <typename R>
-void solves16(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, bool adjoint, hipStream_t st) {
-  const int P = pl->P, mp = 16;
-  const int npad = (int)pl->npad;
-  const int64_t ld = npad, ws = (int64_t)npad * npad;
-  const cx<R>* W = (const cx<R>*)pl->W;
-  const cx<R>* dinv = (const cx<R>*)pl->dinv;
-  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
-  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-  const int nsteps = pl->nsteps;
-  const int nbatch = adjoint ? 2 * P : P;
-  const int64_t sbuf = NB * 16;
-  cx<R>* buf[2] = {(cx<R>*)pl->sweepbuf, (cx<R>*)pl->sweepbuf + (int64_t)nbatch * sbuf};
-  const double e = sizeof(cx<R>);
-  moves_apply<R>(st, P, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
-  for (int dirn = 0; dirn < 2; ++dirn) {
-    const bool fwd = dirn == 0;
-    {
-      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 0.0, 2.0 * e * nbatch * sbuf);
-      hipLaunchKernelGGL((k_gather16<R>), dim3(nbatch), dim3(256), 0, st, X, (int64_t)mp, ldS,
-                         fwd ? 0 : (nsteps - 1) * NB, buf[0], sbuf);
-    }
-    // forward: L (primal), U^H (adjoint); backward: U (primal), L^H (adjoint)
-    const SweepOperand<R> d0 = sweep_op<R>(fwd ? dinv : dinv + NB * NB, ds, NB, false);
-    const SweepOperand<R> d1 = sweep_op<R>(fwd ? dinv + NB * NB : dinv, ds, NB, true);
-    const SweepOperand<R> a0 = sweep_op<R>(W, ws, ld, false);
-    const SweepOperand<R> a1 = sweep_op<R>(W, ws, ld, true);
-    for (int q = 0; q < nsteps; ++q) {
-      const int J = fwd ? q : nsteps - 1 - q;
-      const int ntiles = fwd ? nsteps - 1 - J : J;
-      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nbatch * (1.0 + ntiles) * NB * NB * 16 + 8.0 * nbatch * ntiles * NB * NB * 16,
-                      e * nbatch * ((1.0 + ntiles) * NB * NB + 2.0 * ntiles * NB * 16));
-      hipLaunchKernelGGL((k_sweep16<R>), dim3(1 + ntiles, nbatch), dim3(256), 0, st, J, fwd ? J + 1 : J - 1,
-                         fwd ? 1 : -1, d0, d1, a0, a1, P, X, (int64_t)mp, ldS, buf[q & 1], buf[(q + 1) & 1], sbuf);
-    }
-  }
-  if (adjoint) moves_apply<R>(st, P, X + (int64_t)P * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
-}
-
-template <typename R>
-void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
-  // fused sweeps pay off in FP32; in FP64 their 84 KB of LDS leaves one workgroup per CU
-  if (mp == 16 && sizeof(R) == 4) {
-    solves16<R>(pl, X, ldS, adjoint, st);
-    return;
-  }
-  const int P = pl->P;
-  const int npad = (int)pl->npad;
-  const int64_t ld = npad, ws = (int64_t)npad * npad;
-  const cx<R>* W = (const cx<R>*)pl->W;
-  const cx<R>* dinv = (const cx<R>*)pl->dinv;
-  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
-  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-  const int nsteps = pl->nsteps;
-  const int nb_batch = adjoint ? 2 * P : P;  // primal blocks 0..P-1, adjoint blocks P..2P-1
-  // P^T on the primal blocks
-  moves_apply<R>(st, P, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
-  // forward sweeps: L (primal) and U^H (adjoint); diagonal blocks by their inverses
-  for (int s = 0; s < nsteps; ++s) {
-    const int j0 = s * NB, nb = std::min(NB, npad - j0);
-    const int64_t r1 = j0 + nb;
-    const int below = npad - j0 - nb;
-    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
-    const cx<R>* Uinv = Linv + NB * NB;
-    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Linv, ds, NB, false), opnd<R>(Uinv, ds, NB, true),
-               P, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
-    if (below > 0)
-      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, below, mp, nb, opnd<R>(W + r1 * ld + j0, ws, ld, false),
-                 opnd<R>(W + (int64_t)j0 * ld + r1, ws, ld, true), P, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS, mp,
-                 ldS);
-  }
-  // backward sweeps: U (primal) and L^H (adjoint)
-  for (int s = nsteps - 1; s >= 0; --s) {
-    const int j0 = s * NB, nb = std::min(NB, npad - j0);
-    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
-    const cx<R>* Uinv = Linv + NB * NB;
-    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Uinv, ds, NB, false), opnd<R>(Linv, ds, NB, true),
-               P, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
-    if (j0 > 0)
-      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, j0, mp, nb, opnd<R>(W + j0, ws, ld, false),
-                 opnd<R>(W + (int64_t)j0 * ld, ws, ld, true), P, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
-  }
-  // P on the adjoint blocks
-  if (adjoint) moves_apply<R>(st, P, X + (int64_t)P * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
-}
-
-int validate_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m, void* X,
-                   int64_t ldx) {
-  if (!pl || !A || !X) return EXPM_PFD_ERR_NULL;
-  if (lda < pl->n || ldx < pl->n) return EXPM_PFD_ERR_LD;
-  if (V == nullptr) {
-    if (!pl->full_ok || m != pl->n) return EXPM_PFD_ERR_DIM;
-  } else {
-    if (ldv < pl->n) return EXPM_PFD_ERR_LD;
-    const int64_t cap = pl->m_max == 0 ? pl->n : pl->m_max;
-    if (m < 1 || m > cap) return EXPM_PFD_ERR_DIM;
-  }
-  return 0;
-}
-
-}  // namespace
-
-extern "C" int expm_pfd_workspace_bytes(int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
-                                        size_t* bytes) {
-  if (!bytes) return EXPM_PFD_ERR_NULL;
-  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
-  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
-  if (int e = check_opts(opts)) return e;
-  *bytes = plan_sizes(n, degree, m_max, opts ? opts->precision : EXPM_PFD_FP64).total();
-  return 0;
-}
-
-extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double t, int64_t m_max,
-                             const expm_pfd_opts* opts) {
-  if (!out) return EXPM_PFD_ERR_NULL;
-  *out = nullptr;
-  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
-  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
-  if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
-  if (int e = check_opts(opts)) return e;
+int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
+                int ir_sweeps) {
   auto* pl = new expm_pfd_plan_s();
-  pl->n = n;
+  pl->G = G;
   pl->degree = degree;
   pl->P = degree / 2;
-  pl->t = t;
-  pl->m_max = m_max;
-  pl->precision = opts ? opts->precision : EXPM_PFD_FP64;
-  pl->ir_sweeps = (opts && opts->ir_sweeps > 0) ? opts->ir_sweeps : 2;
-  pl->full_ok = (m_max == 0 || m_max >= n);
-  const Sizes sz = plan_sizes(n, degree, m_max, pl->precision);
-  pl->npad = sz.npad;
-  pl->nsteps = (int)(sz.npad / NB);
+  pl->PB = G * pl->P;
+  pl->precision = precision;
+  pl->ir_sweeps = ir_sweeps > 0 ? ir_sweeps : 2;
+  pl->full_ok = full_ok;
+  pl->mp_max = mp_max;
+  const Sizes sz = plan_sizes(npad, G, degree, mp_max, full_ok, precision);
+  pl->npad = npad;
+  pl->nsteps = (int)(npad / NB);
   pl->cols_alloc = sz.cols;
-  pl->IB = inner_width(sz.npad, pl->precision == EXPM_PFD_FP64);
+  pl->IB = inner_width(npad, precision == EXPM_PFD_FP64);
   pl->h_theta.resize(pl->P);
   pl->h_a.resize(pl->P);
   int rc = expm_pfd_constants(degree, (double*)pl->h_theta.data(), (double*)pl->h_a.data());
@@ -518,7 +323,8 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   he(hipMalloc(&pl->dinv, sz.dinv));
   he(hipMalloc(&pl->sweepbuf, sz.sweep));
   he(hipMalloc(&pl->Xs, sz.xs));
-  if (pl->precision == EXPM_PFD_MIXED) {
+  he(hipMalloc(&pl->d_descs, sz.descs));
+  if (precision == EXPM_PFD_MIXED) {
     he(hipMalloc(&pl->Ah, sz.ah));
     he(hipMalloc(&pl->X64, sz.x64));
     he(hipMalloc(&pl->R64, sz.r64));
@@ -538,73 +344,237 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   return 0;
 }
 
-extern "C" int expm_pfd_destroy(expm_pfd_plan_t pl) {
-  if (!pl) return EXPM_PFD_ERR_NULL;
-  (void)hipDeviceSynchronize();
-  free_plan(pl);
-  return 0;
+// ---- factorization of all shifted matrices of the group --------------------------
+template <typename R>
+void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, hipStream_t st) {
+  const int P = pl->P, PB = pl->PB;
+  const int npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  cx<R>* W = (cx<R>*)pl->W;
+  {
+    dim3 g(npad / 32, npad / 32, pl->G), b(32, 8);
+    trace::Scope ts(st, EXPM_PFD_K_FORM, 0.0,
+                    (double)pl->G * npad * npad * 16 + (double)PB * npad * npad * sizeof(cx<R>) +
+                        (pl->Ah ? (double)pl->G * npad * npad * 16 : 0.0));
+    hipLaunchKernelGGL((k_form<R>), g, b, 0, st, descs, one, npad, pl->d_theta, P, W, ws, ld, pl->Ah, (int64_t)npad);
+  }
+  const int IB = pl->IB;
+  cx<R>* dinv = (cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  int step = 0;
+  for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
+    const int nbo = std::min(NB, npad - j0);
+    for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
+      PanelArgs g;
+      g.ws = ws;
+      g.ld = ld;
+      g.ps = npad;
+      g.ms = mstride;
+      g.P = PB;
+      g.npad = npad;
+      g.j0 = j0;
+      g.c0 = c0;
+      g.nbo = nbo;
+      g.step = step;
+      g.last = (c0 + IB >= j0 + nbo);
+      g.ipiv = pl->ipiv;
+      g.moves = pl->moves;
+      panel<R>(st, IB, (npad - c0 + 1023) / 1024, g, W);
+      const int rest = j0 + nbo - c0 - IB;
+      if (rest > 0) {
+        const int64_t r1 = c0 + IB;
+        gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, npad - c0 - IB, rest, IB, opnd<R>(W + r1 * ld + c0, ws, ld, false),
+                   opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)c0 * ld + r1, ws, ld, W + r1 * ld + r1, ws, ld);
+      }
+    }
+    const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
+    const int ntr = npad - j0 - nbo;
+    // the step's interchanges on the columns left and right of the panel
+    moves_apply<R>(st, PB, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
+    if (ntr > 0) {
+      const int64_t c1 = j0 + nbo;
+      block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
+      const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
+      // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
+      gemm<R, 1>(st, EXPM_PFD_K_LU_GEMM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false),
+                 opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws,
+                 ld);
+      gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+                 opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
+    }
+  }
+  // diagonal-block inverses still missing for the sweeps: every U11, the last L11
+  block_inverse<R>(st, PB, W, ws, ld, 0, pl->nsteps, 1, dinv, ds);
+  block_inverse<R>(st, PB, W, ws, ld, pl->nsteps - 1, 1, 0, dinv, ds);
 }
 
-extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m,
-                              void* X, int64_t ldx, void* stream) {
-  if (int e = validate_apply(pl, A, lda, V, ldv, m, X, ldx)) return e;
-  hipStream_t st = (hipStream_t)stream;
-  const bool full = (V == nullptr);
-  const int P = pl->P;
+// ---- solves on all right-hand-side blocks ----------------------------------------
+// Blocks [0, PB) hold primal right-hand sides (shifted matrix b), blocks [PB, 2PB)
+// (if adjoint) the conjugate-pole ones; each block is mp columns of the
+// row-major npad x ldS array X.
+template <typename R>
+SweepOperand<R> sweep_op(const cx<R>* p, int64_t stride, int64_t ld, bool conj) {
+  SweepOperand<R> o;
+  o.p = p;
+  o.stride = stride;
+  o.ld = ld;
+  o.conj = conj ? 1 : 0;
+  return o;
+}
+
+// Right-hand sides of 16 columns: one fused launch per block step and sweep.
+template <typename R>
+void solves16(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, bool adjoint, hipStream_t st) {
+  const int PB = pl->PB, mp = 16;
   const int npad = (int)pl->npad;
-  const int mp = full ? npad : (int)round_up(m, 16);
-  const int nblk = full ? P : 2 * P;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const cx<R>* W = (const cx<R>*)pl->W;
+  const cx<R>* dinv = (const cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  const int nsteps = pl->nsteps;
+  const int nbatch = adjoint ? 2 * PB : PB;
+  const int64_t sbuf = NB * 16;
+  cx<R>* buf[2] = {(cx<R>*)pl->sweepbuf, (cx<R>*)pl->sweepbuf + (int64_t)nbatch * sbuf};
+  const double e = sizeof(cx<R>);
+  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  for (int dirn = 0; dirn < 2; ++dirn) {
+    const bool fwd = dirn == 0;
+    {
+      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 0.0, 2.0 * e * nbatch * sbuf);
+      hipLaunchKernelGGL((k_gather16<R>), dim3(nbatch), dim3(256), 0, st, X, (int64_t)mp, ldS,
+                         fwd ? 0 : (nsteps - 1) * NB, buf[0], sbuf);
+    }
+    // forward: L (primal), U^H (adjoint); backward: U (primal), L^H (adjoint)
+    const SweepOperand<R> d0 = sweep_op<R>(fwd ? dinv : dinv + NB * NB, ds, NB, false);
+    const SweepOperand<R> d1 = sweep_op<R>(fwd ? dinv + NB * NB : dinv, ds, NB, true);
+    const SweepOperand<R> a0 = sweep_op<R>(W, ws, ld, false);
+    const SweepOperand<R> a1 = sweep_op<R>(W, ws, ld, true);
+    for (int q = 0; q < nsteps; ++q) {
+      const int J = fwd ? q : nsteps - 1 - q;
+      const int ntiles = fwd ? nsteps - 1 - J : J;
+      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nbatch * (1.0 + 2.0 * ntiles) * NB * NB * 16,
+                      e * nbatch * ((1.0 + ntiles) * NB * NB + 2.0 * ntiles * NB * 16));
+      hipLaunchKernelGGL((k_sweep16<R>), dim3(1 + ntiles, nbatch), dim3(256), 0, st, J, fwd ? J + 1 : J - 1,
+                         fwd ? 1 : -1, d0, d1, a0, a1, PB, X, (int64_t)mp, ldS, buf[q & 1], buf[(q + 1) & 1], sbuf);
+    }
+  }
+  if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
+}
+
+template <typename R>
+void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+  // fused sweeps pay off in FP32; in FP64 their 84 KB of LDS leaves one workgroup per CU
+  if (mp == 16 && sizeof(R) == 4) {
+    solves16<R>(pl, X, ldS, adjoint, st);
+    return;
+  }
+  const int PB = pl->PB;
+  const int npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const cx<R>* W = (const cx<R>*)pl->W;
+  const cx<R>* dinv = (const cx<R>*)pl->dinv;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  const int nsteps = pl->nsteps;
+  const int nb_batch = adjoint ? 2 * PB : PB;  // primal blocks 0..PB-1, adjoint blocks PB..2PB-1
+  // P^T on the primal blocks
+  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  // forward sweeps: L (primal) and U^H (adjoint); diagonal blocks by their inverses
+  for (int s = 0; s < nsteps; ++s) {
+    const int j0 = s * NB, nb = std::min(NB, npad - j0);
+    const int64_t r1 = j0 + nb;
+    const int below = npad - j0 - nb;
+    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
+    const cx<R>* Uinv = Linv + NB * NB;
+    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Linv, ds, NB, false),
+               opnd<R>(Uinv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+    if (below > 0)
+      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, below, mp, nb, opnd<R>(W + r1 * ld + j0, ws, ld, false),
+                 opnd<R>(W + (int64_t)j0 * ld + r1, ws, ld, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
+                 mp, ldS);
+  }
+  // backward sweeps: U (primal) and L^H (adjoint)
+  for (int s = nsteps - 1; s >= 0; --s) {
+    const int j0 = s * NB, nb = std::min(NB, npad - j0);
+    const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
+    const cx<R>* Uinv = Linv + NB * NB;
+    gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Uinv, ds, NB, false),
+               opnd<R>(Linv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+    if (j0 > 0)
+      gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, j0, mp, nb, opnd<R>(W + j0, ws, ld, false),
+                 opnd<R>(W + (int64_t)j0 * ld, ws, ld, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
+  }
+  // P on the adjoint blocks
+  if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
+}
+
+// ---- one pass of the whole path over the plan's G problems ------------------------
+// descs: device descriptors (group plans) or nullptr with `one` inline.
+// full: V = I for every problem; mp: right-hand-side block width (npad if full);
+// nmax, mmax: largest n and m in the group (launch extents).
+int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bool full, int mp, int nmax, int mmax,
+        hipStream_t st) {
+  const int P = pl->P, PB = pl->PB, G = pl->G;
+  const int npad = (int)pl->npad;
+  const int nblk = full ? PB : 2 * PB;
   const int64_t ldS = (int64_t)nblk * mp;
   const int64_t count = (int64_t)npad * ldS;
-  (void)hipGetLastError();
+  if (ldS > pl->cols_alloc) return EXPM_PFD_ERR_DIM;
   const double e64 = 16.0;
-  // residue-weighted accumulation of the solution blocks into X
   auto accumulate = [&](const double2* Xsrc) {
-    trace::Scope ts(st, EXPM_PFD_K_ACCUM, 8.0 * nblk * (double)pl->n * m,
-                    e64 * ((double)nblk * pl->n * m + (double)pl->n * m));
+    trace::Scope ts(st, EXPM_PFD_K_ACCUM, 8.0 * nblk * (double)nmax * mmax,
+                    e64 * ((double)nblk * nmax * mmax + (double)G * nmax * mmax));
     if (full) {
-      dim3 g((unsigned)((pl->n + 31) / 32), (unsigned)((pl->n + 31) / 32)), b(32, 8);
-      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xsrc, ldS, npad, P, pl->d_a, (int)pl->n, (double2*)X, ldx);
+      dim3 g((unsigned)((nmax + 31) / 32), (unsigned)((nmax + 31) / 32), (unsigned)G), b(32, 8);
+      hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xsrc, ldS, npad, P, pl->d_a, descs, one);
     } else {
-      hipLaunchKernelGGL(k_accum_thin, dim3(grid_for(pl->n * m)), dim3(256), 0, st, Xsrc, ldS, mp, P, pl->d_a,
-                         (int)pl->n, (int)m, (double2*)X, ldx);
+      dim3 g((unsigned)(((int64_t)nmax * mmax + 255) / 256), (unsigned)G);
+      hipLaunchKernelGGL(k_accum_thin, g, dim3(256), 0, st, Xsrc, ldS, mp, PB, P, pl->d_a, descs, one);
     }
   };
   if (pl->precision == EXPM_PFD_FP64) {
-    factor<double>(pl, A, lda, st);
+    factor<double>(pl, descs, one, st);
     double2* Xs = (double2*)pl->Xs;
     {
       trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
-      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
-                         (const double2*)V, ldv, (int)pl->n, (int)m);
+      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
+                         one);
     }
     solves<double>(pl, Xs, ldS, mp, !full, st);
     accumulate(Xs);
   } else {
-    factor<float>(pl, A, lda, st);
+    factor<float>(pl, descs, one, st);
     float2* Xs = (float2*)pl->Xs;
     {
       trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 8.0 * count);
-      hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, nblk,
-                         (const double2*)V, ldv, (int)pl->n, (int)m);
+      hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
+                         one);
     }
     solves<float>(pl, Xs, ldS, mp, !full, st);
     {
       trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
       hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
     }
+    const int64_t nn = (int64_t)npad * npad;
     for (int it = 0; it < pl->ir_sweeps; ++it) {
-      // R = V - (tA + theta I) X in FP64, all pole solves at once
+      // R = V - (tA + theta I) X in FP64 for every pole solve: one product per
+      // problem and half (primal / adjoint blocks) with the problem's FP64 t*A
       {
         trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
-        hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp,
-                           nblk, (const double2*)V, ldv, (int)pl->n, (int)m);
+        hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, PB, P,
+                           descs, one);
       }
-      gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, 1, npad, (int)ldS, npad, opnd<double>(pl->Ah, 0, npad, false),
-                      opnd<double>(nullptr, 0, 0, false), 1, pl->X64, 0, ldS, pl->R64, 0, ldS);
+      for (int half = 0; half < (full ? 1 : 2); ++half) {
+        const int64_t off = (int64_t)half * PB * mp;
+        gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, G, npad, P * mp, npad, opnd<double>(pl->Ah, nn, npad, false),
+                        opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS, pl->R64 + off,
+                        (int64_t)P * mp, ldS);
+      }
       {
         trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, 3 * e64 * count);
-        hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp,
+        hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp, PB,
                            P, pl->d_theta);
       }
       {
@@ -619,6 +589,88 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
     }
     accumulate(pl->X64);
   }
+  return 0;
+}
+
+int validate_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m, void* X,
+                   int64_t ldx) {
+  if (!pl || !A || !X) return EXPM_PFD_ERR_NULL;
+  if (pl->G != 1) return EXPM_PFD_ERR_ARG;
+  if (lda < pl->n || ldx < pl->n) return EXPM_PFD_ERR_LD;
+  if (V == nullptr) {
+    if (!pl->full_ok || m != pl->n) return EXPM_PFD_ERR_DIM;
+  } else {
+    if (ldv < pl->n) return EXPM_PFD_ERR_LD;
+    const int64_t cap = pl->m_max == 0 ? pl->n : pl->m_max;
+    if (m < 1 || m > cap) return EXPM_PFD_ERR_DIM;
+  }
+  return 0;
+}
+
+int check_degree(int degree) {
+  return (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) ? EXPM_PFD_ERR_DEGREE : 0;
+}
+
+}  // namespace
+
+extern "C" int expm_pfd_workspace_bytes(int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
+                                        size_t* bytes) {
+  if (!bytes) return EXPM_PFD_ERR_NULL;
+  if (int e = check_degree(degree)) return e;
+  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
+  if (int e = check_opts(opts)) return e;
+  const bool full_ok = (m_max == 0 || m_max >= n);
+  const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
+  *bytes = plan_sizes(round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64).total();
+  return 0;
+}
+
+extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double t, int64_t m_max,
+                             const expm_pfd_opts* opts) {
+  if (!out) return EXPM_PFD_ERR_NULL;
+  *out = nullptr;
+  if (int e = check_degree(degree)) return e;
+  if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 0) return EXPM_PFD_ERR_DIM;
+  if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
+  if (int e = check_opts(opts)) return e;
+  const bool full_ok = (m_max == 0 || m_max >= n);
+  const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
+  expm_pfd_plan_t pl = nullptr;
+  int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64,
+                       opts ? opts->ir_sweeps : 0);
+  if (rc) return rc;
+  pl->n = n;
+  pl->t = t;
+  pl->m_max = m_max;
+  *out = pl;
+  return 0;
+}
+
+extern "C" int expm_pfd_destroy(expm_pfd_plan_t pl) {
+  if (!pl) return EXPM_PFD_ERR_NULL;
+  (void)hipDeviceSynchronize();
+  free_plan(pl);
+  return 0;
+}
+
+extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V, int64_t ldv, int64_t m,
+                              void* X, int64_t ldx, void* stream) {
+  if (int e = validate_apply(pl, A, lda, V, ldv, m, X, ldx)) return e;
+  hipStream_t st = (hipStream_t)stream;
+  const bool full = (V == nullptr);
+  ProblemDesc one;
+  one.A = (const double2*)A;
+  one.lda = lda;
+  one.V = (const double2*)V;
+  one.ldv = ldv;
+  one.X = (double2*)X;
+  one.ldx = ldx;
+  one.t = pl->t;
+  one.n = (int)pl->n;
+  one.m = (int)m;
+  (void)hipGetLastError();
+  const int mp = full ? (int)pl->npad : (int)round_up(m, 16);
+  if (int e = run(pl, nullptr, one, full, mp, (int)pl->n, (int)m, st)) return e;
   if (hipGetLastError() != hipSuccess) return EXPM_PFD_ERR_HIP;
   return 0;
 }
@@ -629,39 +681,61 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
                                       const expm_pfd_opts* opts, void* stream) {
   if (count < 1) return EXPM_PFD_ERR_DIM;
   if (!n || !t || !A || !lda || !V || !ldv || !m || !X || !ldx) return EXPM_PFD_ERR_NULL;
-  if (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) return EXPM_PFD_ERR_DEGREE;
+  if (int e = check_degree(degree)) return e;
   if (int e = check_opts(opts)) return e;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
     if (!A[i] || !X[i]) return EXPM_PFD_ERR_NULL;
     if (lda[i] < n[i] || ldx[i] < n[i]) return EXPM_PFD_ERR_LD;
-    if (V[i] ? (ldv[i] < n[i] || m[i] < 1 || m[i] > n[i]) : (m[i] != n[i])) return V[i] && ldv[i] < n[i] ? EXPM_PFD_ERR_LD : EXPM_PFD_ERR_DIM;
+    if (V[i] && ldv[i] < n[i]) return EXPM_PFD_ERR_LD;
+    if (V[i] ? (m[i] < 1 || m[i] > n[i]) : (m[i] != n[i])) return EXPM_PFD_ERR_DIM;
     if (!std::isfinite(t[i])) return EXPM_PFD_ERR_ARG;
   }
+  const int precision = opts ? opts->precision : EXPM_PFD_FP64;
   hipStream_t st = (hipStream_t)stream;
-  // one plan per problem, reused across problems of the same (n, m, full) shape
+  // groups: same padded order and same kind (V = I, or 16-column-rounded width)
+  std::map<std::pair<int64_t, int64_t>, std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    const int64_t npad = round_up(n[i], NB);
+    const int64_t mp = V[i] ? round_up(m[i], 16) : 0;
+    groups[{npad, mp}].push_back(i);
+  }
+  (void)hipGetLastError();
   int rc = 0;
-  std::map<std::pair<int64_t, int64_t>, expm_pfd_plan_t> plans;
-  for (int i = 0; i < count && !rc; ++i) {
-    const int64_t mm = V[i] ? m[i] : 0;
-    auto key = std::make_pair(n[i], mm);
-    expm_pfd_plan_t pl;
-    auto it = plans.find(key);
-    if (it == plans.end()) {
-      rc = expm_pfd_plan(&pl, n[i], degree, t[i], mm, opts);
-      if (rc) break;
-      plans[key] = pl;
-    } else {
-      pl = it->second;
+  for (auto& kv : groups) {
+    const int64_t npad = kv.first.first, mpk = kv.first.second;
+    const std::vector<int>& idx = kv.second;
+    const bool full = mpk == 0;
+    const int G = (int)idx.size();
+    expm_pfd_plan_t pl = nullptr;
+    rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0);
+    if (rc) break;
+    std::vector<ProblemDesc> hd(G);
+    int nmax = 0, mmax = 0;
+    for (int g = 0; g < G; ++g) {
+      const int i = idx[g];
+      ProblemDesc& d = hd[g];
+      d.A = (const double2*)A[i];
+      d.lda = lda[i];
+      d.V = (const double2*)V[i];
+      d.ldv = ldv[i];
+      d.X = (double2*)X[i];
+      d.ldx = ldx[i];
+      d.t = t[i];
+      d.n = (int)n[i];
+      d.m = (int)m[i];
+      nmax = std::max(nmax, d.n);
+      mmax = std::max(mmax, d.m);
     }
-    pl->t = t[i];
-    rc = expm_pfd_apply(pl, A[i], lda[i], V[i], ldv[i], m[i], X[i], ldx[i], st);
+    if (hipMemcpyAsync(pl->d_descs, hd.data(), G * sizeof(ProblemDesc), hipMemcpyHostToDevice, st) != hipSuccess)
+      rc = EXPM_PFD_ERR_HIP;
+    ProblemDesc none{};
+    if (!rc) rc = run(pl, pl->d_descs, none, full, full ? (int)npad : (int)mpk, nmax, mmax, st);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+    free_plan(pl);
+    if (rc) break;
   }
-  for (auto& kv : plans) {
-    (void)hipStreamSynchronize(st);
-    free_plan(kv.second);
-  }
+  if (!rc && hipGetLastError() != hipSuccess) rc = EXPM_PFD_ERR_HIP;
   return rc;
 }
 

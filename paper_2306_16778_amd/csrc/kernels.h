@@ -23,11 +23,18 @@ namespace expm {
 // grid (npad/32, npad/32), block (32, 8)
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_form(const double2* __restrict__ A, int64_t lda, int n, int npad,
-                                              double t, const double2* __restrict__ theta, int P,
-                                              cx<R>* __restrict__ W, int64_t wstride, int64_t ldw,
-                                              double2* __restrict__ Ah, int64_t ldh) {
+__global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ descs, ProblemDesc one, int npad,
+                                              const double2* __restrict__ theta, int P, cx<R>* __restrict__ Wb,
+                                              int64_t wstride, int64_t ldw, double2* __restrict__ Ahb, int64_t ldh) {
   __shared__ double2 tile[32][33];
+  const int g = blockIdx.z;
+  const ProblemDesc d = desc_of(descs, one, g);
+  const double2* A = d.A;
+  const int64_t lda = d.lda;
+  const int n = d.n;
+  const double t = d.t;
+  cx<R>* W = Wb + (int64_t)g * P * wstride;
+  double2* Ah = Ahb ? Ahb + (int64_t)g * npad * ldh : nullptr;
   const int bi = blockIdx.y, bj = blockIdx.x;
   const int R0 = (bi > bj ? bi : bj) * 32, C0 = (bi < bj ? bi : bj) * 32;
   for (int cc = threadIdx.y; cc < 32; cc += 8) {
@@ -693,22 +700,25 @@ __global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t s
 }
 
 // ---------------------------------------------------------------------------
-// Right-hand-side staging: nblk copies of V (column-major n x m, FP64) into the
-// row-major solution array (npad x ldS, block b at columns [b*mp, b*mp+mp)),
-// zero-padded; V == nullptr stages the identity.  grid-stride over npad*ldS.
+// Right-hand-side staging: every solution block of the row-major npad x ldS
+// array gets its problem's V (column-major n x m, FP64), zero-padded, or the
+// identity when V is absent.  Block b (mp columns at b*mp) belongs to pair
+// (b mod GP) of the group, i.e. to problem (b mod GP) / P.
+// grid-stride over npad*ldS.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ldS, int npad, int mp, int nblk,
-                                               const double2* __restrict__ Vin, int64_t ldv, int n, int m) {
+__global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ldS, int npad, int mp, int GP, int P,
+                                               const ProblemDesc* __restrict__ descs, ProblemDesc one) {
   const int64_t total = (int64_t)npad * ldS;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / ldS);
     const int jj = (int)(e % ldS);
-    const int j = jj % mp;
+    const int b = jj / mp, j = jj % mp;
+    const ProblemDesc d = desc_of(descs, one, (b % GP) / P);
     double2 v = czero<double2>();
-    if (Vin) {
-      if (i < n && j < m) v = Vin[i + (int64_t)j * ldv];
-    } else if (i == j && i < n) {
+    if (d.V) {
+      if (i < d.n && j < d.m) v = d.V[i + (int64_t)j * d.ldv];
+    } else if (i == j && i < d.n) {
       v.x = 1;
     }
     cx<R> o;
@@ -720,48 +730,55 @@ __global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ld
 
 // ---------------------------------------------------------------------------
 // K10 (thin V): X = sum_p (a_p Y_p + conj(a_p) Z_p), Y_p the solution for pole
-// theta_p (block p) and Z_p the one for conj(theta_p) (block P+p), in FP64 in
-// the fixed pair order (eq. equ:expAx with Remark rem:two_time_real_part).
-// Output column-major n x m.  One thread per output element.
+// theta_p (block g*P+p) and Z_p the one for conj(theta_p) (block GP+g*P+p), in
+// FP64 in the fixed pair order (eq. equ:expAx with Remark
+// rem:two_time_real_part).  Output column-major n x m of problem g =
+// blockIdx.y.  One thread per output element.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_accum_thin(const double2* __restrict__ Xs, int64_t ldS, int mp, int P,
-                                                    const double2* __restrict__ a, int n, int m,
-                                                    double2* __restrict__ out, int64_t ldx) {
+__global__ __launch_bounds__(256) void k_accum_thin(const double2* __restrict__ Xs, int64_t ldS, int mp, int GP, int P,
+                                                    const double2* __restrict__ a,
+                                                    const ProblemDesc* __restrict__ descs, ProblemDesc one) {
+  const int g = blockIdx.y;
+  const ProblemDesc d = desc_of(descs, one, g);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * m) return;
-  const int i = (int)(e / m), j = (int)(e % m);
+  if (e >= (int64_t)d.n * d.m) return;
+  const int i = (int)(e / d.m), j = (int)(e % d.m);
   const double2* row = Xs + (int64_t)i * ldS;
   double sr = 0, si = 0;
   for (int p = 0; p < P; ++p) {
     const double2 ap = a[p];
-    const double2 y = row[p * mp + j];
-    const double2 z = row[(P + p) * mp + j];
+    const double2 y = row[(g * P + p) * mp + j];
+    const double2 z = row[(GP + g * P + p) * mp + j];
     sr += ap.x * y.x - ap.y * y.y + ap.x * z.x + ap.y * z.y;
     si += ap.x * y.y + ap.y * y.x + ap.x * z.y - ap.y * z.x;
   }
   double2 o;
   o.x = sr;
   o.y = si;
-  out[i + (int64_t)j * ldx] = o;
+  d.X[i + (int64_t)j * d.ldx] = o;
 }
 
 // ---------------------------------------------------------------------------
 // K10 (V = I): X = sum_p (a_p Y_p + (a_p Y_p)^H), Y_p = (tA + theta_p I)^{-1}
-// (block p of the solution array, npad columns each): the conjugate pole's
-// inverse is the adjoint of Y_p (eq. equ:ExpoMatRat with Remark
+// (block g*P+p of the solution array, npad columns each): the conjugate
+// pole's inverse is the adjoint of Y_p (eq. equ:ExpoMatRat with Remark
 // rem:two_time_real_part).  32x32 output tiles through LDS; column-major out.
-// grid (ceil(n/32), ceil(n/32)), block (32, 8)
+// grid (ceil(nmax/32), ceil(nmax/32), G), block (32, 8)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_accum_full(const double2* __restrict__ Xs, int64_t ldS, int npad, int P,
-                                                    const double2* __restrict__ a, int n,
-                                                    double2* __restrict__ out, int64_t ldx) {
+                                                    const double2* __restrict__ a,
+                                                    const ProblemDesc* __restrict__ descs, ProblemDesc one) {
   __shared__ double2 t1[32][33];
   __shared__ double2 t2[32][33];
+  const int g = blockIdx.z;
+  const ProblemDesc d = desc_of(descs, one, g);
+  const int n = d.n;
   const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  if (bi >= n || bj >= n) return;
   const int tx = threadIdx.x, ty = threadIdx.y;
   double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
   for (int p = 0; p < P; ++p) {
-    const double2* Y = Xs + (int64_t)p * npad;
+    const double2* Y = Xs + (int64_t)(g * P + p) * npad;
     __syncthreads();
     for (int q = 0; q < 4; ++q) {
       const int rr = ty + 8 * q;
@@ -789,7 +806,7 @@ __global__ __launch_bounds__(256) void k_accum_full(const double2* __restrict__ 
       double2 o;
       o.x = sr[q];
       o.y = si[q];
-      out[i + (int64_t)j * ldx] = o;
+      d.X[i + (int64_t)j * d.ldx] = o;
     }
   }
 }
@@ -817,15 +834,16 @@ __global__ __launch_bounds__(256) void k_add_correction(double2* __restrict__ X,
   }
 }
 
-// Rres -= shift_b * X for block b (primal blocks theta_p, adjoint blocks conj(theta_p)).
+// Rres -= shift_b * X for block b: primal blocks (b < GP) theta of pair b mod P,
+// adjoint blocks its conjugate.
 __global__ __launch_bounds__(256) void k_shift_sub(double2* __restrict__ Rres, const double2* __restrict__ X,
-                                                   int64_t ldS, int npad, int mp, int P,
+                                                   int64_t ldS, int npad, int mp, int GP, int P,
                                                    const double2* __restrict__ theta) {
   const int64_t total = (int64_t)npad * ldS;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int blk = (int)((e % ldS) / mp);
-    double2 th = theta[blk < P ? blk : blk - P];
-    if (blk >= P) th.y = -th.y;
+    double2 th = theta[(blk % GP) % P];
+    if (blk >= GP) th.y = -th.y;
     const double2 x = X[e];
     Rres[e].x -= th.x * x.x - th.y * x.y;
     Rres[e].y -= th.x * x.y + th.y * x.x;
