@@ -182,6 +182,67 @@ int expm_pfd_trace(int class_mask);
  */
 int expm_pfd_trace_summary(int kernel_class, double* ms, int64_t* launches, double* flops, double* bytes);
 
+/* ---- queued serving --------------------------------------------------------- */
+/*
+ * A queue serves exp(t_i A_i) v_i requests as they arrive (continuous
+ * batching).  A scheduler thread owned by the queue repeatedly takes the
+ * pending requests whose workspace fits the HBM budget, groups them by padded
+ * order and launches each group as one batched evaluation (every pole of
+ * every request in the group in each launch) on one of several worker
+ * streams, so groups overlap on the device and requests arriving while others
+ * run join the next group.  Matrices are registered once (copied into queue
+ * memory, counted against the budget) and can be reused with new t and v.
+ * Completion is observed by events; latency is host time from submit to the
+ * observed completion.  All requests of a queue share degree and precision.
+ * Entry points are thread-safe with respect to each other.
+ */
+typedef struct expm_pfd_queue_s* expm_pfd_queue_t;
+
+typedef struct expm_pfd_queue_stats {
+  int64_t submitted, completed;
+  int64_t groups;            /* batched evaluations launched */
+  double p50_ms, p99_ms;     /* latency percentiles of completed requests */
+  double mean_ms, max_ms;
+  double solves_per_s;       /* completed / (last completion - first submit) */
+  double mean_group_size;
+  size_t peak_bytes;         /* peak of registered matrices + in-flight workspace */
+} expm_pfd_queue_stats;
+
+/*
+ * hbm_budget  device bytes the queue may hold (registered matrices plus
+ *             in-flight workspace); a request whose workspace alone exceeds
+ *             it is rejected by expm_pfd_submit with EXPM_PFD_ERR_BUDGET.
+ * degree      even degree used for every request.
+ * max_group   most requests evaluated together (<= 0: 64).
+ * streams     worker streams (<= 0: 3).
+ */
+int expm_pfd_queue_create(expm_pfd_queue_t* q, size_t hbm_budget, int degree, const expm_pfd_opts* opts,
+                          int max_group, int streams);
+
+/* Copy the n x n column-major device matrix A (lower triangle read) into the
+ * queue; *mat_id identifies it in expm_pfd_submit.  Synchronous. */
+int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, int64_t* mat_id);
+
+/*
+ * Enqueue X = R_d(t A_mat) V.  V: device n x m column-major (ldv >= n), m <= 16;
+ * X: device n x m (ldx >= n), written when the ticket completes.  V and X must
+ * stay valid and V unchanged until then.  Returns at once.
+ */
+int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, const void* V, int64_t m, int64_t ldv, void* X,
+                    int64_t ldx, uint64_t* ticket);
+
+/* *done = 1 once the ticket's result is in X (0 otherwise).  Returns
+ * EXPM_PFD_ERR_BUDGET for a request that was failed because it could no longer
+ * fit the budget (matrices registered after it was submitted filled it). */
+int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done);
+/* Block until the ticket completes (same return codes as expm_pfd_poll). */
+int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket);
+/* Block until every submitted request completes. */
+int expm_pfd_queue_drain(expm_pfd_queue_t q);
+int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats* out);
+/* Drain, stop the scheduler and free everything the queue owns. */
+int expm_pfd_queue_destroy(expm_pfd_queue_t q);
+
 /* Human-readable text for a return code (static storage). */
 const char* expm_pfd_strerror(int code);
 

@@ -21,10 +21,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/expm_pfd.h"
@@ -47,8 +53,10 @@ struct Rec {
 };
 unsigned mask = 0;  // bit c set: launches of kernel class c are timed
 std::vector<Rec> recs;
+std::mutex mu;  // records may come from the serving thread
 std::vector<hipEvent_t> pool;
 hipEvent_t get_event() {
+  std::lock_guard<std::mutex> lk(mu);
   if (!pool.empty()) {
     hipEvent_t e = pool.back();
     pool.pop_back();
@@ -79,6 +87,7 @@ struct Scope {
   ~Scope() {
     if (active) {
       (void)hipEventRecord(r.b, s);
+      std::lock_guard<std::mutex> lk(mu);
       recs.push_back(r);
     }
   }
@@ -227,6 +236,7 @@ inline int grid_for(int64_t count) {
 struct expm_pfd_plan_s {
   int64_t n = 0, npad = 0, m_max = 0;  // n, m_max: the single-problem arguments
   int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
+  int Gcap = 1;  // problems the workspace was sized for; G <= Gcap is the active count
   double t = 1;
   bool full_ok = false;
   int64_t mp_max = 16, cols_alloc = 0;
@@ -294,6 +304,7 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
                 int ir_sweeps) {
   auto* pl = new expm_pfd_plan_s();
   pl->G = G;
+  pl->Gcap = G;
   pl->degree = degree;
   pl->P = degree / 2;
   pl->PB = G * pl->P;
@@ -737,6 +748,372 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
   }
   if (!rc && hipGetLastError() != hipSuccess) rc = EXPM_PFD_ERR_HIP;
   return rc;
+}
+
+// ============================================================================
+// queued serving (continuous batching)
+// ============================================================================
+struct expm_pfd_queue_s {
+  using clock = std::chrono::steady_clock;
+  struct Req {
+    uint64_t ticket;
+    int64_t mat;
+    double t;
+    const void* V;
+    int64_t m, ldv;
+    void* X;
+    int64_t ldx;
+    clock::time_point submitted;
+  };
+  struct Mat {
+    double2* A = nullptr;
+    int64_t n = 0;
+  };
+  struct Flight {
+    hipEvent_t ev = nullptr;
+    int stream = 0;
+    expm_pfd_plan_t plan = nullptr;
+    std::vector<Req> reqs;
+    std::vector<ProblemDesc> descs;  // source of the descriptor upload, kept until completion
+    size_t bytes = 0;
+  };
+
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<Req> pending;
+  std::unordered_map<uint64_t, int> state;  // 1 pending/in flight, 2 done, 3 failed (budget)
+  std::vector<Mat> mats;
+  std::vector<Flight> flights;
+  std::map<std::pair<int64_t, int>, std::vector<expm_pfd_plan_t>> free_plans;  // (npad, Gcap)
+  std::vector<hipStream_t> streams;
+  std::vector<bool> busy;
+  std::thread worker;
+  bool stop = false;
+  size_t budget = 0, mat_bytes = 0, flight_bytes = 0, cached_bytes = 0, peak = 0;
+  int degree = 16, precision = EXPM_PFD_FP64, ir = 0, max_group = 64, device = 0;
+  uint64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
+  std::vector<double> lat_ms;
+  clock::time_point first_submit, last_done;
+  bool any_submit = false;
+
+  size_t plan_bytes(int64_t npad, int Gcap) const {
+    return plan_sizes(npad, Gcap, degree, 16, false, precision).total();
+  }
+  // plans are cached by (padded order, capacity); capacities are powers of two
+  static int capacity_for(int G) {
+    int c = 1;
+    while (c < G) c <<= 1;
+    return c;
+  }
+  void release_cached(size_t need) {
+    // free cached plans until `need` more bytes fit the budget
+    for (auto it = free_plans.begin(); it != free_plans.end() && mat_bytes + flight_bytes + cached_bytes + need > budget;) {
+      auto& v = it->second;
+      while (!v.empty() && mat_bytes + flight_bytes + cached_bytes + need > budget) {
+        cached_bytes -= plan_bytes(it->first.first, it->first.second);
+        free_plan(v.back());
+        v.pop_back();
+      }
+      it = v.empty() ? free_plans.erase(it) : std::next(it);
+    }
+  }
+  void retire() {
+    for (size_t i = 0; i < flights.size();) {
+      Flight& f = flights[i];
+      if (hipEventQuery(f.ev) != hipSuccess) {
+        ++i;
+        continue;
+      }
+      const auto now = clock::now();
+      for (const Req& r : f.reqs) {
+        state[r.ticket] = 2;
+        lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
+        ++completed;
+      }
+      last_done = now;
+      busy[f.stream] = false;
+      flight_bytes -= f.bytes;
+      cached_bytes += f.bytes;
+      free_plans[{f.plan->npad, f.plan->Gcap}].push_back(f.plan);
+      (void)hipEventDestroy(f.ev);
+      flights.erase(flights.begin() + i);
+      cv_done.notify_all();
+    }
+  }
+  // launch one group on a free stream; returns false if nothing could be launched
+  bool launch_one() {
+    int s = -1;
+    for (int i = 0; i < (int)streams.size(); ++i)
+      if (!busy[i]) {
+        s = i;
+        break;
+      }
+    if (s < 0 || pending.empty()) return false;
+    const int64_t npad = round_up(mats[pending.front().mat].n, NB);
+    std::vector<size_t> pick;
+    for (size_t i = 0; i < pending.size() && (int)pick.size() < max_group; ++i)
+      if (round_up(mats[pending[i].mat].n, NB) == npad) pick.push_back(i);
+    // largest group whose workspace fits next to the registered matrices and the
+    // flights (cached idle plans can be released to make room)
+    int G = (int)pick.size();
+    int Gcap = capacity_for(G);
+    auto reusable = [&](int cap) {
+      auto it = free_plans.find({npad, cap});
+      return it != free_plans.end() && !it->second.empty();
+    };
+    for (;;) {
+      if (reusable(Gcap) || mat_bytes + flight_bytes + plan_bytes(npad, Gcap) <= budget) break;
+      if (Gcap == 1) {
+        G = 0;
+        break;
+      }
+      Gcap /= 2;
+      G = std::min(G, Gcap);
+    }
+    if (G == 0) return false;
+    pick.resize(G);
+    expm_pfd_plan_t pl = nullptr;
+    const size_t bytes = plan_bytes(npad, Gcap);
+    auto it = free_plans.find({npad, Gcap});
+    if (it != free_plans.end() && !it->second.empty()) {
+      pl = it->second.back();
+      it->second.pop_back();
+      cached_bytes -= bytes;
+    } else {
+      release_cached(bytes);
+      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir) != 0) {
+        (void)hipGetLastError();
+        return false;
+      }
+    }
+    Flight f;
+    f.stream = s;
+    f.plan = pl;
+    f.bytes = bytes;
+    int nmax = 0, mmax = 0;
+    for (int g = G - 1; g >= 0; --g) {  // erase from the back so earlier indices stay valid
+      f.reqs.push_back(pending[pick[g]]);
+      pending.erase(pending.begin() + (int64_t)pick[g]);
+    }
+    std::reverse(f.reqs.begin(), f.reqs.end());
+    for (const Req& r : f.reqs) {
+      ProblemDesc d;
+      d.A = mats[r.mat].A;
+      d.lda = mats[r.mat].n;
+      d.V = (const double2*)r.V;
+      d.ldv = r.ldv;
+      d.X = (double2*)r.X;
+      d.ldx = r.ldx;
+      d.t = r.t;
+      d.n = (int)mats[r.mat].n;
+      d.m = (int)r.m;
+      nmax = std::max(nmax, d.n);
+      mmax = std::max(mmax, d.m);
+      f.descs.push_back(d);
+    }
+    pl->G = G;
+    pl->PB = G * pl->P;
+    hipStream_t st = streams[s];
+    (void)hipMemcpyAsync(pl->d_descs, f.descs.data(), G * sizeof(ProblemDesc), hipMemcpyHostToDevice, st);
+    ProblemDesc none{};
+    (void)run(pl, pl->d_descs, none, false, 16, nmax, mmax, st);
+    (void)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+    (void)hipEventRecord(f.ev, st);
+    busy[s] = true;
+    flight_bytes += bytes;
+    peak = std::max(peak, mat_bytes + flight_bytes + cached_bytes);
+    ++groups;
+    grouped += G;
+    flights.push_back(std::move(f));
+    return true;
+  }
+  void loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      retire();
+      while (launch_one()) {
+      }
+      if (flights.empty() && !pending.empty()) {
+        // nothing runs and the oldest request still does not fit (matrices were
+        // registered after it was submitted): fail it rather than wait forever
+        const Req r = pending.front();
+        pending.pop_front();
+        state[r.ticket] = 3;
+        ++completed;
+        ++failed;
+        cv_done.notify_all();
+        continue;
+      }
+      if (stop && pending.empty() && flights.empty()) break;
+      if (flights.empty())
+        cv.wait(lk, [&] { return stop || !pending.empty(); });
+      else
+        cv.wait_for(lk, std::chrono::microseconds(30));
+    }
+  }
+};
+
+extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, int degree, const expm_pfd_opts* opts,
+                                     int max_group, int nstreams) {
+  if (!out) return EXPM_PFD_ERR_NULL;
+  *out = nullptr;
+  if (int e = check_degree(degree)) return e;
+  if (int e = check_opts(opts)) return e;
+  auto* q = new expm_pfd_queue_s();
+  q->budget = hbm_budget;
+  q->degree = degree;
+  q->precision = opts ? opts->precision : EXPM_PFD_FP64;
+  q->ir = opts ? opts->ir_sweeps : 0;
+  q->max_group = max_group > 0 ? max_group : 64;
+  (void)hipGetDevice(&q->device);
+  const int ns = nstreams > 0 ? nstreams : 3;
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t x : q->streams) (void)hipStreamDestroy(x);
+      delete q;
+      return EXPM_PFD_ERR_HIP;
+    }
+    q->streams.push_back(st);
+    q->busy.push_back(false);
+  }
+  q->worker = std::thread([q] { q->loop(); });
+  *out = q;
+  return 0;
+}
+
+extern "C" int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, int64_t* mat_id) {
+  if (!q || !A || !mat_id) return EXPM_PFD_ERR_NULL;
+  if (n < 1 || n > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
+  if (lda < n) return EXPM_PFD_ERR_LD;
+  const size_t bytes = (size_t)n * n * sizeof(double2);
+  double2* d = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (q->mat_bytes + bytes > q->budget) return EXPM_PFD_ERR_BUDGET;
+    q->release_cached(bytes);
+    q->mat_bytes += bytes;
+  }
+  if (hipMalloc(&d, bytes) != hipSuccess ||
+      hipMemcpy2D(d, n * sizeof(double2), A, lda * sizeof(double2), n * sizeof(double2), n, hipMemcpyDeviceToDevice) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    if (d) (void)hipFree(d);
+    std::lock_guard<std::mutex> lk(q->mu);
+    q->mat_bytes -= bytes;
+    return EXPM_PFD_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(q->mu);
+  expm_pfd_queue_s::Mat m;
+  m.A = d;
+  m.n = n;
+  q->mats.push_back(m);
+  q->peak = std::max(q->peak, q->mat_bytes + q->flight_bytes + q->cached_bytes);
+  *mat_id = (int64_t)q->mats.size() - 1;
+  return 0;
+}
+
+extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, const void* V, int64_t m, int64_t ldv,
+                               void* X, int64_t ldx, uint64_t* ticket) {
+  if (!q || !V || !X || !ticket) return EXPM_PFD_ERR_NULL;
+  if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(q->mu);
+  if (mat_id < 0 || mat_id >= (int64_t)q->mats.size()) return EXPM_PFD_ERR_TICKET;
+  const int64_t n = q->mats[mat_id].n;
+  if (m < 1 || m > 16) return EXPM_PFD_ERR_DIM;
+  if (ldv < n || ldx < n) return EXPM_PFD_ERR_LD;
+  if (q->mat_bytes + q->plan_bytes(round_up(n, NB), 1) > q->budget) return EXPM_PFD_ERR_BUDGET;
+  expm_pfd_queue_s::Req r;
+  r.ticket = q->next_ticket++;
+  r.mat = mat_id;
+  r.t = t;
+  r.V = V;
+  r.m = m;
+  r.ldv = ldv;
+  r.X = X;
+  r.ldx = ldx;
+  r.submitted = expm_pfd_queue_s::clock::now();
+  if (!q->any_submit) {
+    q->first_submit = r.submitted;
+    q->any_submit = true;
+  }
+  q->pending.push_back(r);
+  q->state[r.ticket] = 1;
+  ++q->submitted;
+  *ticket = r.ticket;
+  q->cv.notify_all();
+  return 0;
+}
+
+extern "C" int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done) {
+  if (!q || !done) return EXPM_PFD_ERR_NULL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->state.find(ticket);
+  if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
+  *done = it->second == 2 ? 1 : 0;
+  return it->second == 3 ? EXPM_PFD_ERR_BUDGET : 0;
+}
+
+extern "C" int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket) {
+  if (!q) return EXPM_PFD_ERR_NULL;
+  std::unique_lock<std::mutex> lk(q->mu);
+  auto it = q->state.find(ticket);
+  if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
+  q->cv_done.wait(lk, [&] { return q->state[ticket] >= 2; });
+  return q->state[ticket] == 3 ? EXPM_PFD_ERR_BUDGET : 0;
+}
+
+extern "C" int expm_pfd_queue_drain(expm_pfd_queue_t q) {
+  if (!q) return EXPM_PFD_ERR_NULL;
+  std::unique_lock<std::mutex> lk(q->mu);
+  q->cv_done.wait(lk, [&] { return q->completed == q->submitted; });
+  return 0;
+}
+
+extern "C" int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats* out) {
+  if (!q || !out) return EXPM_PFD_ERR_NULL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  expm_pfd_queue_stats s{};
+  s.submitted = q->submitted;
+  s.completed = q->completed;
+  s.groups = q->groups;
+  s.mean_group_size = q->groups ? (double)q->grouped / q->groups : 0.0;
+  s.peak_bytes = q->peak;
+  std::vector<double> v = q->lat_ms;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) { return v[std::min(v.size() - 1, (size_t)std::llround(p * (v.size() - 1)))]; };
+    s.p50_ms = pct(0.5);
+    s.p99_ms = pct(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    s.mean_ms = sum / v.size();
+    s.max_ms = v.back();
+    const double span = std::chrono::duration<double>(q->last_done - q->first_submit).count();
+    s.solves_per_s = span > 0 ? q->completed / span : 0.0;
+  }
+  *out = s;
+  return 0;
+}
+
+extern "C" int expm_pfd_queue_destroy(expm_pfd_queue_t q) {
+  if (!q) return EXPM_PFD_ERR_NULL;
+  {
+    std::lock_guard<std::mutex> lk(q->mu);
+    q->stop = true;
+    q->cv.notify_all();
+  }
+  q->worker.join();
+  (void)hipDeviceSynchronize();
+  for (auto& kv : q->free_plans)
+    for (expm_pfd_plan_t p : kv.second) free_plan(p);
+  for (auto& m : q->mats)
+    if (m.A) (void)hipFree(m.A);
+  for (hipStream_t s : q->streams) (void)hipStreamDestroy(s);
+  delete q;
+  return 0;
 }
 
 extern "C" int expm_pfd_trace(int class_mask) {

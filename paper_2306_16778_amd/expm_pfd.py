@@ -36,6 +36,14 @@ EXPORTED = (
     "expm_pfd_strerror",
     "expm_pfd_trace",
     "expm_pfd_trace_summary",
+    "expm_pfd_queue_create",
+    "expm_pfd_register_matrix",
+    "expm_pfd_submit",
+    "expm_pfd_poll",
+    "expm_pfd_wait",
+    "expm_pfd_queue_drain",
+    "expm_pfd_queue_stats_get",
+    "expm_pfd_queue_destroy",
 )
 
 # kernel classes of the tracer (EXPM_PFD_K_*)
@@ -47,6 +55,13 @@ class ExpmPfdError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {expm_pfd_strerror(code)} (code {code})")
         self.code = code
+
+
+class _QueueStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("groups", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("mean_group_size", ctypes.c_double), ("peak_bytes", ctypes.c_size_t)]
 
 
 class _Opts(ctypes.Structure):
@@ -75,6 +90,15 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_trace.argtypes = [c_int]
     lib.expm_pfd_trace_summary.argtypes = [c_int, ctypes.POINTER(c_double), ctypes.POINTER(i64),
                                            ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
+    lib.expm_pfd_queue_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, c_int, ctypes.POINTER(_Opts), c_int,
+                                          c_int]
+    lib.expm_pfd_register_matrix.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i64)]
+    lib.expm_pfd_submit.argtypes = [vp, i64, c_double, vp, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.expm_pfd_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(c_int)]
+    lib.expm_pfd_wait.argtypes = [vp, ctypes.c_uint64]
+    lib.expm_pfd_queue_drain.argtypes = [vp]
+    lib.expm_pfd_queue_stats_get.argtypes = [vp, ctypes.POINTER(_QueueStats)]
+    lib.expm_pfd_queue_destroy.argtypes = [vp]
     lib.expm_pfd_strerror.argtypes = [c_int]
     lib.expm_pfd_strerror.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -244,3 +268,88 @@ def expm_pfd_trace_summary(kernel_class):
     _check(load_library().expm_pfd_trace_summary(cls, ctypes.byref(ms), ctypes.byref(k), ctypes.byref(fl),
                                                  ctypes.byref(by)), "expm_pfd_trace_summary")
     return {"ms": ms.value, "launches": k.value, "flops": fl.value, "bytes": by.value}
+
+
+# ---- queued serving ---------------------------------------------------------------
+
+class Queue:
+    """Owns an expm_pfd_queue_t and keeps each request's device tensors alive until it completes."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self._live = {}
+
+    def __del__(self):
+        try:
+            if self.handle:
+                expm_pfd_queue_destroy(self)
+        except Exception:
+            pass
+
+
+def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_sweeps: int = 0, max_group: int = 64,
+                          streams: int = 3) -> Queue:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    o = _opts(precision, ir_sweeps)
+    _check(lib.expm_pfd_queue_create(ctypes.byref(h), int(hbm_budget), int(degree), ctypes.byref(o), int(max_group),
+                                     int(streams)), "expm_pfd_queue_create")
+    return Queue(h.value)
+
+
+def expm_pfd_register_matrix(q: Queue, A) -> int:
+    import torch
+
+    Ac, lda = _colmajor(A, torch)
+    mid = ctypes.c_int64()
+    torch.cuda.current_stream().synchronize()
+    _check(load_library().expm_pfd_register_matrix(q.handle, Ac.data_ptr(), Ac.shape[0], lda, ctypes.byref(mid)),
+           "expm_pfd_register_matrix")
+    return int(mid.value)
+
+
+def expm_pfd_submit(q: Queue, mat_id: int, t: float, V, X=None):
+    """Enqueue X = R_d(t A_mat) V; returns (ticket, X).  V: (n, m) complex128 device tensor, m <= 16."""
+    import torch
+
+    Vc, ldv = _colmajor(V, torch)
+    n, m = Vc.shape
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.complex128, device=Vc.device).t()
+    torch.cuda.current_stream().synchronize()  # V must be written before the queue's streams read it
+    tk = ctypes.c_uint64()
+    _check(load_library().expm_pfd_submit(q.handle, int(mat_id), float(t), Vc.data_ptr(), m, ldv, X.data_ptr(),
+                                          X.stride(1), ctypes.byref(tk)), "expm_pfd_submit")
+    q._live[tk.value] = (Vc, X)
+    return tk.value, X
+
+
+def expm_pfd_poll(q: Queue, ticket: int) -> bool:
+    d = ctypes.c_int()
+    _check(load_library().expm_pfd_poll(q.handle, ctypes.c_uint64(ticket), ctypes.byref(d)), "expm_pfd_poll")
+    if d.value:
+        q._live.pop(ticket, None)
+    return bool(d.value)
+
+
+def expm_pfd_wait(q: Queue, ticket: int):
+    _check(load_library().expm_pfd_wait(q.handle, ctypes.c_uint64(ticket)), "expm_pfd_wait")
+    q._live.pop(ticket, None)
+
+
+def expm_pfd_queue_drain(q: Queue):
+    _check(load_library().expm_pfd_queue_drain(q.handle), "expm_pfd_queue_drain")
+    q._live.clear()
+
+
+def expm_pfd_queue_stats_get(q: Queue) -> dict:
+    st = _QueueStats()
+    _check(load_library().expm_pfd_queue_stats_get(q.handle, ctypes.byref(st)), "expm_pfd_queue_stats_get")
+    return {k: getattr(st, k) for k, _ in _QueueStats._fields_}
+
+
+def expm_pfd_queue_destroy(q: Queue):
+    if q.handle:
+        _check(load_library().expm_pfd_queue_destroy(q.handle), "expm_pfd_queue_destroy")
+        q.handle = None
+        q._live.clear()

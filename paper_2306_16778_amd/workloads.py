@@ -164,3 +164,25 @@ def config5_matrix(spec) -> np.ndarray:
     r = rng_for(5, idx + 1)
     lam = r.uniform(-200.0, 0.0, n)
     return hermitian_with_spectrum(r, lam, cheap=True)
+
+
+def config5_matrix_device(spec, device="cuda"):
+    """The config-5 matrix of ``spec`` assembled on the GPU with torch (same seeded
+    draws as ``config5_matrix``: spectrum uniform in [-200, 0], three Householder
+    reflections and a phase diagonal).  Rounding differs from the CPU assembly,
+    so checks must copy these bytes back rather than rebuild them on the host."""
+    import torch
+
+    n, idx = spec
+    r = rng_for(5, idx + 1)
+    lam = r.uniform(-200.0, 0.0, n)
+    vs = [complex_gaussian(r, n) for _ in range(3)]
+    phase = np.exp(2j * np.pi * r.random(n))
+    X = torch.diag(torch.from_numpy(lam.astype(np.complex128))).to(device)
+    for v in reversed(vs):
+        v = torch.from_numpy(v / np.linalg.norm(v)).to(device)
+        X = X - 2.0 * torch.outer(v, v.conj() @ X)
+        X = X - 2.0 * torch.outer(X @ v, v.conj())
+    ph = torch.from_numpy(phase).to(device)
+    X = ph[:, None] * X * ph.conj()[None, :]
+    return 0.5 * (X + X.conj().T)

@@ -1,0 +1,79 @@
+"""GPU tests of the queued serving path: results of a Poisson-arrival trace with
+matrix reuse match the oracle, and each equals the same request evaluated alone."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ep():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_16778_amd import expm_pfd
+    expm_pfd.load_library()
+    return expm_pfd
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_serving_trace_matches_oracle_and_alone(ep, precision, tol):
+    import torch
+    from paper_2306_16778_amd import serving
+
+    _announce(f"serving {precision} 48 requests n in [64, 700]")
+    stats, kept, _ = serving.replay(48, qps=2000.0, precision=precision, degree=16, n_lo=64, n_hi=700,
+                                    budget_bytes=16 << 30, keep=lambda r: True)
+    assert stats["completed"] == 48 and stats["submitted"] == 48
+    assert stats["groups"] < 48  # requests were grouped
+    assert any(r.reuse for r, *_ in kept)
+    for r, A, v, t, X in kept:
+        Y = matrix.expm_R(A, v, t, 16)
+        assert matrix.rel_fro(X, Y) < tol
+    # alone: the same request through a single-problem plan gives the same bits
+    for r, A, v, t, X in kept[:6]:
+        n = A.shape[0]
+        plan = ep.expm_pfd_plan(n, 16, t, 1, precision)
+        X1 = ep.expm_pfd_apply(plan, torch.from_numpy(np.asfortranarray(A)).cuda(),
+                               torch.from_numpy(np.asfortranarray(v)).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(X1.cpu().numpy(), X)
+
+
+def test_budget_admission(ep):
+    """A budget too small for one workspace rejects the request; a budget for one
+    group at a time still completes every request (they queue, never run out of memory)."""
+    import torch
+    from paper_2306_16778_amd import workloads as wl
+
+    n = 256
+    A = wl.config5_matrix_device((n, 3))
+    V = torch.randn(n, 1, dtype=torch.complex128, device="cuda")
+    one = ep.expm_pfd_workspace_bytes(n, 16, 16, "fp64")
+    q = ep.expm_pfd_queue_create(n * n * 16 + one // 2, 16, "fp64")
+    mid = ep.expm_pfd_register_matrix(q, A)
+    with pytest.raises(ep.ExpmPfdError):
+        ep.expm_pfd_submit(q, mid, 0.5, V)
+    ep.expm_pfd_queue_destroy(q)
+    _announce("budget for about one workspace, 10 requests")
+    q = ep.expm_pfd_queue_create(n * n * 16 + int(1.5 * one), 16, "fp64")
+    mid = ep.expm_pfd_register_matrix(q, A)
+    outs = [ep.expm_pfd_submit(q, mid, 0.1 * (k + 1), V) for k in range(10)]
+    ep.expm_pfd_queue_drain(q)
+    st = ep.expm_pfd_queue_stats_get(q)
+    assert st["completed"] == 10
+    assert st["peak_bytes"] <= n * n * 16 + int(1.5 * one)
+    Ah = A.cpu().numpy()
+    for k, (tk, X) in enumerate(outs):
+        Y = matrix.expm_R(Ah, V.cpu().numpy(), 0.1 * (k + 1), 16)
+        assert matrix.rel_fro(X.cpu().numpy(), Y) < 1e-12
+    ep.expm_pfd_queue_destroy(q)
