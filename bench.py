@@ -13,7 +13,14 @@ refinement, the reported value) and the plain FP64 path.  The oracle
 (eigendecomposition, FP64, host CPU) is timed once on the same input as the CPU
 baseline and provides the error check of both GPU results.
 
+Also reported (extra fields, not the headline value): the batched entry point on
+512 Hermitian matrices of orders log-uniform in [32, 512] (V n x 4, degree 16),
+and the queued serving path replaying a Poisson trace of requests with orders
+log-uniform in [64, 4096] (single vectors, 20% matrix reuse, degree 16) on both
+precision paths.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--serving-requests R] [--serving-qps Q] [--no-batched]
 """
 
 from __future__ import annotations
@@ -30,6 +37,31 @@ if ROOT not in sys.path:
 
 METRIC = "exp(tA)V solves/s at rel err<=1e-10, mixed vs FP64 GPU path; p50/p99 latency"
 PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
+
+
+KERNEL_SOURCES = ("device_common.h", "kernels.h", "expm_pfd.hip")
+# HBM bytes per launch of the dominant kernel, from one FETCH_SIZE and one
+# WRITE_SIZE counter pass, each scaled by what the counter reads for a plain
+# copy kernel of known size (read 0.50006 x, write 1.0 x the true bytes);
+# valid for the kernel sources with this digest only, otherwise reported null
+TRAFFIC = {"mixed": {"bytes_per_launch": 57.80e6 + 34.64e6, "sources_sha256": "2fe908a785286c8af4630da46eb22f49f311a3513f2b5332a713984830f05213"}}
+
+
+def kernel_sources_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2306_16778_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    t = TRAFFIC.get(precision)
+    if t is None or t["sources_sha256"] != kernel_sources_digest():
+        return None
+    return t["bytes_per_launch"]
 
 
 def algorithmic_flops(n, m, degree):
@@ -82,13 +114,14 @@ def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
         "gflops": flops / (ms * 1e-3) / 1e9,
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99)},
         "roofline": {
-            "kernel": "k_gemm<%s,64x64> (LU trailing and in-panel updates)" % ("double" if precision == "fp64" else "float"),
+            "kernel": "k_gemm<%s, 0, 64, 64, 2, 2> (C -= L21 U12: LU in-panel and trailing updates)" % ("double" if precision == "fp64" else "float"),
             "bound": "mfma",
             "achieved": achieved,
             "peak": PEAK[precision],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK[precision],
-            "traffic": None,
+            "traffic": measured_traffic(precision),
+            "traffic_unit": "bytes per launch",
             "launches_per_step": dom["launches"] / steps,
             "avg_launch_us": dom["ms"] * 1e3 / max(dom["launches"], 1),
             "flops_per_launch": dom["flops"] / max(dom["launches"], 1),
@@ -113,12 +146,81 @@ def cpu_baseline(prob):
                "sample": "one full exp(tA)V of the workload (n=2048 Hermitian eigendecomposition + 2 products), %.1f s" % dt}
 
 
+def batched_section(ep, torch, workloads, matrix):
+    """All 512 problems of the batched workload in one call per precision path."""
+    import numpy as np
+
+    probs = workloads.config4_batch(512)
+    As = [torch.from_numpy(np.asfortranarray(p.A)).cuda() for p in probs]
+    Vs = [torch.from_numpy(np.asfortranarray(p.V)).cuda() for p in probs]
+    ts = [p.t for p in probs]
+    out = {"workload": "512 Hermitian matrices, n log-uniform in [32, 512], spectrum U[-50,0], V n x 4, "
+                       "t U[0.1,1], degree 16", "problems": 512}
+    for prec in ("mixed", "fp64"):
+        ep.expm_pfd_apply_batched(As, Vs, ts, 16, prec)  # warm-up (kernels, allocator)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xs = ep.expm_pfd_apply_batched(As, Vs, ts, 16, prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = max(matrix.rel_fro(Xs[i].cpu().numpy(), matrix.expm_R(probs[i].A, probs[i].V, probs[i].t, 16))
+                  for i in range(0, 512, 32))
+        out[prec] = {"solves_per_s": 512 / dt, "ms_per_batch": dt * 1e3, "max_rel_err_16_sampled": err}
+    return out
+
+
+def serving_section(requests, qps, matrix):
+    """Identical Poisson trace replayed through the queue on both precision paths; every
+    8th request of order <= 1024 is checked against the oracle."""
+    from paper_2306_16778_amd import serving
+
+    out = {"workload": f"{requests} requests, Poisson arrivals at {qps:g}/s, n log-uniform in [64, 4096], "
+                       "spectrum U[-200,0], one Gaussian vector each, t U[0.1,1], 20% matrix reuse, degree 16",
+           "qps": qps, "requests": requests}
+    for prec in ("mixed", "fp64"):
+        seen = [0]
+
+        def keep(r):
+            if r.n > 1024:
+                return False
+            seen[0] += 1
+            return seen[0] % 8 == 1
+
+        st, kept, wall = serving.replay(requests, qps=qps, precision=prec, keep=keep)
+        err = None
+        if matrix is not None and kept:
+            err = max(matrix.rel_fro(X, matrix.expm_R(A, v, t, 16)) for _, A, v, t, X in kept)
+        out[prec] = {"solves_per_s": st["solves_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                     "mean_ms": st["mean_ms"], "groups": st["groups"], "mean_group_size": st["mean_group_size"],
+                     "peak_gb": st["peak_bytes"] / 1e9, "wall_s": wall,
+                     "max_rel_err_sampled": err, "checked": len(kept)}
+    return out
+
+
+def copy_calibration(torch):
+    """A plain elementwise copy (y = 1.0 * x) of 256 MiB, three launches: the HBM
+    counters of these launches give the bytes-per-count scale of FETCH_SIZE and
+    WRITE_SIZE on this device (each launch reads and writes exactly 256 MiB)."""
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-qps", type=float, default=100.0)
+    ap.add_argument("--paths", default="mixed,fp64", help="precision paths to time (mixed first: the reported value)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB copy kernel first (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the poles or the requests "
@@ -132,14 +234,20 @@ def main():
     from paper_2306_16778_amd import workloads
 
     ep.load_library()
+    if args.copy_calibration:
+        copy_calibration(torch)
+    paths = [p for p in args.paths.split(",") if p]
+    if "mixed" not in paths or any(p not in ("mixed", "fp64") for p in paths):
+        print("--paths must include mixed (the reported value) and may add fp64", file=sys.stderr)
+        sys.exit(2)
     prob = workloads.config2_fp64_at_scale()
     n, m = prob.V.shape
     Ad = torch.from_numpy(np.asfortranarray(prob.A)).to("cuda")
     Vd = torch.from_numpy(np.asfortranarray(prob.V)).to("cuda")
     torch.cuda.synchronize()
-    print(f"[bench] workload n={n} m={m} degree={prob.degree}; timing mixed then fp64 "
+    print(f"[bench] workload n={n} m={m} degree={prob.degree}; timing {' then '.join(paths)} "
           f"({args.warmup} warmup + {args.steps} steps each)", file=sys.stderr, flush=True)
-    res = {p: run_path(ep, torch, prob, Ad, Vd, p, args.steps, args.warmup) for p in ("mixed", "fp64")}
+    res = {p: run_path(ep, torch, prob, Ad, Vd, p, args.steps, args.warmup) for p in paths}
     print("[bench] GPU timing done", file=sys.stderr, flush=True)
 
     cpu = None
@@ -150,7 +258,26 @@ def main():
         errs = {p: matrix.rel_fro(r["X"], Y) for p, r in res.items()}
         print(f"[bench] oracle done: rel errs {errs}", file=sys.stderr, flush=True)
 
-    mx, f64 = res["mixed"], res["fp64"]
+    batched = None
+    if not args.no_batched:
+        from oracle import matrix
+        batched = batched_section(ep, torch, workloads, matrix)
+        print("[bench] batched done", file=sys.stderr, flush=True)
+    served = None
+    if args.serving_requests > 0:
+        check = None
+        if not args.no_cpu_baseline:
+            from oracle import matrix as check
+        served = serving_section(args.serving_requests, args.serving_qps, check)
+        print("[bench] serving done", file=sys.stderr, flush=True)
+
+    mx, f64 = res["mixed"], res.get("fp64")
+    fp64_path = None
+    if f64 is not None:
+        fp64_path = {"value": f64["solves_per_s"], "ms_per_step": f64["ms_per_step"],
+                     "latency_ms": f64["latency_ms"], "gflops": f64["gflops"],
+                     "rel_err_vs_oracle": errs.get("fp64"), "roofline": f64["roofline"],
+                     "breakdown_ms_per_step": f64["breakdown_ms_per_step"]}
     out = {
         "metric": METRIC,
         "value": mx["solves_per_s"],
@@ -170,14 +297,13 @@ def main():
         "gflops": mx["gflops"],
         "rel_err_vs_oracle": errs.get("mixed"),
         "meets_1e-10": (errs["mixed"] <= 1e-10) if errs else None,
-        "speedup_vs_fp64_path": f64["ms_per_step"] / mx["ms_per_step"],
-        "fp64_path": {"value": f64["solves_per_s"], "ms_per_step": f64["ms_per_step"],
-                      "latency_ms": f64["latency_ms"], "gflops": f64["gflops"],
-                      "rel_err_vs_oracle": errs.get("fp64"), "roofline": f64["roofline"],
-                      "breakdown_ms_per_step": f64["breakdown_ms_per_step"]},
+        "speedup_vs_fp64_path": f64["ms_per_step"] / mx["ms_per_step"] if f64 else None,
+        "fp64_path": fp64_path,
         "breakdown_ms_per_step": mx["breakdown_ms_per_step"],
         "roofline": mx["roofline"],
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": served,
     }
     print(json.dumps(out), flush=True)
 

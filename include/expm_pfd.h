@@ -152,8 +152,8 @@ int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int deg
  * the stream the kernel is launched on). */
 #define EXPM_PFD_K_FORM        0  /* shifted-matrix formation */
 #define EXPM_PFD_K_PANEL       1  /* register-resident panel factorization */
-#define EXPM_PFD_K_LU_GEMM     2  /* LU updates, 64x64 complex tiles on the matrix cores */
-#define EXPM_PFD_K_LU_TRSM     3  /* LU interchanges + U12 triangular solve */
+#define EXPM_PFD_K_LU_GEMM     2  /* LU updates C -= L21 U12 (in-panel and trailing), 64x64 complex tiles */
+#define EXPM_PFD_K_LU_TRSM     3  /* LU U12 = L11^{-1} A12 as a product with the block inverse */
 #define EXPM_PFD_K_MOVES       4  /* row moves (left columns, right-hand sides) */
 #define EXPM_PFD_K_SOLVE_TRSM  5  /* diagonal-block solves of the sweeps */
 #define EXPM_PFD_K_SOLVE_GEMM  6  /* block updates of the sweeps */

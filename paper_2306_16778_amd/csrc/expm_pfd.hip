@@ -178,7 +178,7 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
   const double e = sizeof(cx<R>);
   trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * K,
                   e * batch * ((double)M * K + (double)K * N + (MODE == 0 ? 2.0 : 1.0) * M * N));
-  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM) {
+  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM) {
     const int tiles = (int)((M + 63) / 64);
     hipLaunchKernelGGL((k_gemm<R, MODE, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, a0, a1, split,
                        B, sB, ldb, C, sC, ldc);
@@ -408,7 +408,7 @@ void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one
       block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
       const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
       // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
-      gemm<R, 1>(st, EXPM_PFD_K_LU_GEMM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false),
+      gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false),
                  opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws,
                  ld);
       gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),

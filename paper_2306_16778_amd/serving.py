@@ -42,10 +42,11 @@ def replay(count: int, qps: float, precision: str = "mixed", degree: int = 16, n
         _, X = ep.expm_pfd_submit(q, mat_ids[r.matrix_id], r.t, V)
         if keep is not None and keep(r):
             kept.append((r, mats[r.matrix_id], r.v, r.t, X))
-        if len(mats) > 8:  # the queue holds its own copy of every registered matrix
+        # the queue holds its own copy of every registered matrix; the caller's copies are only
+        # kept when results are to be checked (a later request may reuse any earlier matrix)
+        if keep is None and len(mats) > 8:
             for k in list(mats)[:-8]:
-                if keep is None or not any(kk[0].matrix_id == k for kk in kept):
-                    del mats[k]
+                del mats[k]
     ep.expm_pfd_queue_drain(q)
     wall = time.perf_counter() - t0
     stats = ep.expm_pfd_queue_stats_get(q)
