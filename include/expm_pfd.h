@@ -56,6 +56,8 @@ extern "C" {
 #define EXPM_PFD_ERR_CONST    -8  /* root finding for the constants did not converge */
 #define EXPM_PFD_ERR_BUDGET   -9  /* a request can never fit the queue's HBM budget */
 #define EXPM_PFD_ERR_TICKET  -10  /* unknown ticket or matrix id */
+#define EXPM_PFD_ERR_SYNC    -11  /* a one-launch triangular sweep found its dependency
+                                     order broken (a wait hit its cap); results invalid */
 
 #define EXPM_PFD_MAX_DEGREE 64
 #define EXPM_PFD_MAX_N      8192
@@ -128,6 +130,17 @@ int expm_pfd_apply(expm_pfd_plan_t plan, const void* A, int64_t lda, const void*
 /* Release the plan and its device memory (synchronizes the device first). */
 int expm_pfd_destroy(expm_pfd_plan_t plan);
 
+/*
+ * expm_pfd_plan_check: synchronizes the device, then reports whether every
+ * triangular sweep run with this plan so far kept its dependency order.
+ * Thin right-hand sides (at most 64 columns) are solved by one launch per
+ * sweep whose workgroups wait on each other's results; each wait is capped,
+ * and a capped wait marks the plan.  Returns 0, or EXPM_PFD_ERR_SYNC once a
+ * wait has hit its cap (the plan's results since then are invalid and the
+ * plan should be destroyed), or EXPM_PFD_ERR_HIP.
+ */
+int expm_pfd_plan_check(expm_pfd_plan_t plan);
+
 /* ---- batched ------------------------------------------------------------ */
 /*
  * expm_pfd_apply_batched: X_i = R_d(t_i A_i) V_i for count independent problems
@@ -155,8 +168,8 @@ int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int deg
 #define EXPM_PFD_K_LU_GEMM     2  /* LU updates C -= L21 U12 (in-panel and trailing), 64x64 complex tiles */
 #define EXPM_PFD_K_LU_TRSM     3  /* LU U12 = L11^{-1} A12 as a product with the block inverse */
 #define EXPM_PFD_K_MOVES       4  /* row moves (left columns, right-hand sides) */
-#define EXPM_PFD_K_SOLVE_TRSM  5  /* diagonal-block solves of the sweeps */
-#define EXPM_PFD_K_SOLVE_GEMM  6  /* block updates of the sweeps */
+#define EXPM_PFD_K_SOLVE_TRSM  5  /* (unused; diagonal blocks are applied inside the sweeps) */
+#define EXPM_PFD_K_SOLVE_GEMM  6  /* triangular sweeps: one-launch chains or block products */
 #define EXPM_PFD_K_ACCUM       7  /* residue-weighted accumulation */
 #define EXPM_PFD_K_IR_GEMM     8  /* refinement residual product (FP64) */
 #define EXPM_PFD_K_ELEMENTWISE 9  /* staging, conversions, shift, correction */

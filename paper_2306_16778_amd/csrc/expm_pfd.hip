@@ -41,6 +41,7 @@ using namespace expm;
 namespace {
 
 constexpr int NB = 64;  // outer panel width (also the padding granularity)
+constexpr int CHAIN_MP_MAX = 64;  // widest right-hand-side block solved by one-launch sweeps
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -247,7 +248,11 @@ struct expm_pfd_plan_s {
   int* ipiv = nullptr;       // PB x npad
   int* moves = nullptr;      // PB x nsteps x MOVE_STRIDE
   void* dinv = nullptr;      // PB x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
-  void* sweepbuf = nullptr;  // 2 x 2PB x 64 x 16 staging of the fused sweeps
+  // one-launch sweeps: [0] ticket counter, [1] status, then from int FLAG_STRIDE on
+  // 2PB x chains x nsteps ready flags, FLAG_STRIDE ints apart
+  int* sweep_sync = nullptr;
+  unsigned ticket_base = 0;  // counter value at the start of the next sweep launch
+  int epoch = 0;             // value the flags of the last sweep launch carry
   void* Xs = nullptr;        // npad x cols_alloc, working type
   double2* Ah = nullptr;     // mixed: G x npad x npad FP64 t*A (Hermitian, row-major)
   double2* X64 = nullptr;    // mixed: npad x cols_alloc
@@ -275,7 +280,7 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
   s.ipiv = (size_t)PB * npad * sizeof(int);
   s.moves = (size_t)PB * (npad / NB) * MOVE_STRIDE * sizeof(int);
   s.dinv = (size_t)PB * (npad / NB) * 2 * NB * NB * s.w_elem;
-  s.sweep = (size_t)2 * 2 * PB * NB * 16 * s.w_elem;
+  s.sweep = (size_t)(FLAG_STRIDE + 2 * PB * (CHAIN_MP_MAX / 16) * (npad / NB) * FLAG_STRIDE) * sizeof(int);
   s.xs = (size_t)npad * s.cols * s.w_elem;
   s.ah = fp64 ? 0 : (size_t)G * npad * npad * 16;
   s.x64 = fp64 ? 0 : (size_t)npad * s.cols * 16;
@@ -294,10 +299,18 @@ int check_opts(const expm_pfd_opts* o) {
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
   void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
-                  p->sweepbuf, p->Xs, p->Ah, p->X64,  p->R64,   p->d_descs};
+                  p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->d_descs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
+}
+
+// sticky fault bits of the plan's one-launch sweeps (0: every wait ended in order);
+// call once the plan's work has completed
+int sweep_fault(expm_pfd_plan_t p) {
+  int f = 0;
+  if (hipMemcpy(&f, p->sweep_sync + 1, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return f;
 }
 
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
@@ -332,7 +345,7 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   he(hipMalloc(&pl->ipiv, sz.ipiv));
   he(hipMalloc(&pl->moves, sz.moves));
   he(hipMalloc(&pl->dinv, sz.dinv));
-  he(hipMalloc(&pl->sweepbuf, sz.sweep));
+  he(hipMalloc(&pl->sweep_sync, sz.sweep));
   he(hipMalloc(&pl->Xs, sz.xs));
   he(hipMalloc(&pl->d_descs, sz.descs));
   if (precision == EXPM_PFD_MIXED) {
@@ -344,6 +357,7 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
     he(hipMemcpy(pl->d_theta, pl->h_theta.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
     he(hipMemcpy(pl->d_a, pl->h_a.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
     he(hipMemset(pl->moves, 0, sz.moves));
+    he(hipMemset(pl->sweep_sync, 0, sz.sweep));
   }
   if (he.e != hipSuccess) {
     const bool oom = he.e == hipErrorOutOfMemory;
@@ -434,10 +448,11 @@ SweepOperand<R> sweep_op(const cx<R>* p, int64_t stride, int64_t ld, bool conj) 
   return o;
 }
 
-// Right-hand sides of 16 columns: one fused launch per block step and sweep.
+// Thin right-hand sides (mp <= CHAIN_MP_MAX): each sweep is one launch in which
+// every 16-column chain runs its block steps back to back (k_sweep_chain).
 template <typename R>
-void solves16(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, bool adjoint, hipStream_t st) {
-  const int PB = pl->PB, mp = 16;
+void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+  const int PB = pl->PB;
   const int npad = (int)pl->npad;
   const int64_t ld = npad, ws = (int64_t)npad * npad;
   const cx<R>* W = (const cx<R>*)pl->W;
@@ -445,40 +460,35 @@ void solves16(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, bool adjoint, hipStream
   const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
   const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
   const int nsteps = pl->nsteps;
-  const int nbatch = adjoint ? 2 * PB : PB;
-  const int64_t sbuf = NB * 16;
-  cx<R>* buf[2] = {(cx<R>*)pl->sweepbuf, (cx<R>*)pl->sweepbuf + (int64_t)nbatch * sbuf};
+  const int nblk = adjoint ? 2 * PB : PB;
+  const int cpb = mp / 16, nchain = nblk * cpb;
   const double e = sizeof(cx<R>);
   moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
   for (int dirn = 0; dirn < 2; ++dirn) {
     const bool fwd = dirn == 0;
-    {
-      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 0.0, 2.0 * e * nbatch * sbuf);
-      hipLaunchKernelGGL((k_gather16<R>), dim3(nbatch), dim3(256), 0, st, X, (int64_t)mp, ldS,
-                         fwd ? 0 : (nsteps - 1) * NB, buf[0], sbuf);
-    }
     // forward: L (primal), U^H (adjoint); backward: U (primal), L^H (adjoint)
     const SweepOperand<R> d0 = sweep_op<R>(fwd ? dinv : dinv + NB * NB, ds, NB, false);
     const SweepOperand<R> d1 = sweep_op<R>(fwd ? dinv + NB * NB : dinv, ds, NB, true);
     const SweepOperand<R> a0 = sweep_op<R>(W, ws, ld, false);
     const SweepOperand<R> a1 = sweep_op<R>(W, ws, ld, true);
-    for (int q = 0; q < nsteps; ++q) {
-      const int J = fwd ? q : nsteps - 1 - q;
-      const int ntiles = fwd ? nsteps - 1 - J : J;
-      trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nbatch * (1.0 + 2.0 * ntiles) * NB * NB * 16,
-                      e * nbatch * ((1.0 + ntiles) * NB * NB + 2.0 * ntiles * NB * 16));
-      hipLaunchKernelGGL((k_sweep16<R>), dim3(1 + ntiles, nbatch), dim3(256), 0, st, J, fwd ? J + 1 : J - 1,
-                         fwd ? 1 : -1, d0, d1, a0, a1, PB, X, (int64_t)mp, ldS, buf[q & 1], buf[(q + 1) & 1], sbuf);
-    }
+    const double tiles = (double)nsteps * (nsteps + 1) / 2.0;  // diagonal + off-diagonal blocks
+    trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nchain * tiles * NB * NB * 16,
+                    e * nblk * tiles * NB * NB + 2.0 * e * nchain * npad * 16);
+    const unsigned nwg = (unsigned)nchain * (unsigned)nsteps;
+    pl->epoch = pl->epoch == INT32_MAX ? 1 : pl->epoch + 1;
+    int* sync = pl->sweep_sync;
+    hipLaunchKernelGGL((k_sweep_chain<R>), dim3(nwg), dim3(256), 0, st, fwd ? 1 : 0, nsteps, nchain, cpb, d0, d1, a0,
+                       a1, PB, X, (int64_t)mp, ldS, (unsigned*)sync, pl->ticket_base, sync + FLAG_STRIDE, pl->epoch,
+                       sync + 1);
+    pl->ticket_base += nwg;
   }
   if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
 }
 
 template <typename R>
 void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
-  // fused sweeps pay off in FP32; in FP64 their 84 KB of LDS leaves one workgroup per CU
-  if (mp == 16 && sizeof(R) == 4) {
-    solves16<R>(pl, X, ldS, adjoint, st);
+  if (mp <= CHAIN_MP_MAX) {
+    solves_chain<R>(pl, X, ldS, mp, adjoint, st);
     return;
   }
   const int PB = pl->PB;
@@ -686,6 +696,13 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   return 0;
 }
 
+extern "C" int expm_pfd_plan_check(expm_pfd_plan_t pl) {
+  if (!pl) return EXPM_PFD_ERR_NULL;
+  if (hipDeviceSynchronize() != hipSuccess) return EXPM_PFD_ERR_HIP;
+  const int f = sweep_fault(pl);
+  return f < 0 ? EXPM_PFD_ERR_HIP : (f ? EXPM_PFD_ERR_SYNC : 0);
+}
+
 extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree, const void* const* A,
                                       const int64_t* lda, const void* const* V, const int64_t* ldv,
                                       const int64_t* m, void* const* X, const int64_t* ldx,
@@ -743,6 +760,7 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
     ProblemDesc none{};
     if (!rc) rc = run(pl, pl->d_descs, none, full, full ? (int)npad : (int)mpk, nmax, mmax, st);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+    if (!rc && sweep_fault(pl) != 0) rc = EXPM_PFD_ERR_SYNC;
     free_plan(pl);
     if (rc) break;
   }
@@ -781,7 +799,7 @@ struct expm_pfd_queue_s {
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::deque<Req> pending;
-  std::unordered_map<uint64_t, int> state;  // 1 pending/in flight, 2 done, 3 failed (budget)
+  std::unordered_map<uint64_t, int> state;  // 1 pending/in flight, 2 done, 3 failed (budget), 4 failed (sweep)
   std::vector<Mat> mats;
   std::vector<Flight> flights;
   std::map<std::pair<int64_t, int>, std::vector<expm_pfd_plan_t>> free_plans;  // (npad, Gcap)
@@ -826,16 +844,24 @@ struct expm_pfd_queue_s {
         continue;
       }
       const auto now = clock::now();
+      const bool bad = sweep_fault(f.plan) != 0;
       for (const Req& r : f.reqs) {
-        state[r.ticket] = 2;
-        lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
+        state[r.ticket] = bad ? 4 : 2;
+        if (bad)
+          ++failed;
+        else
+          lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
         ++completed;
       }
       last_done = now;
       busy[f.stream] = false;
       flight_bytes -= f.bytes;
-      cached_bytes += f.bytes;
-      free_plans[{f.plan->npad, f.plan->Gcap}].push_back(f.plan);
+      if (bad) {
+        free_plan(f.plan);  // its sweep counters can no longer be trusted
+      } else {
+        cached_bytes += f.bytes;
+        free_plans[{f.plan->npad, f.plan->Gcap}].push_back(f.plan);
+      }
       (void)hipEventDestroy(f.ev);
       flights.erase(flights.begin() + i);
       cv_done.notify_all();
@@ -1047,13 +1073,15 @@ extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, con
   return 0;
 }
 
+static int state_error(int st) { return st == 3 ? EXPM_PFD_ERR_BUDGET : st == 4 ? EXPM_PFD_ERR_SYNC : 0; }
+
 extern "C" int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done) {
   if (!q || !done) return EXPM_PFD_ERR_NULL;
   std::lock_guard<std::mutex> lk(q->mu);
   auto it = q->state.find(ticket);
   if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
   *done = it->second == 2 ? 1 : 0;
-  return it->second == 3 ? EXPM_PFD_ERR_BUDGET : 0;
+  return state_error(it->second);
 }
 
 extern "C" int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket) {
@@ -1062,7 +1090,7 @@ extern "C" int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket) {
   auto it = q->state.find(ticket);
   if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
   q->cv_done.wait(lk, [&] { return q->state[ticket] >= 2; });
-  return q->state[ticket] == 3 ? EXPM_PFD_ERR_BUDGET : 0;
+  return state_error(q->state[ticket]);
 }
 
 extern "C" int expm_pfd_queue_drain(expm_pfd_queue_t q) {
@@ -1156,6 +1184,7 @@ extern "C" const char* expm_pfd_strerror(int code) {
     case EXPM_PFD_ERR_CONST: return "root finding for the constants did not converge";
     case EXPM_PFD_ERR_BUDGET: return "request exceeds the queue's HBM budget";
     case EXPM_PFD_ERR_TICKET: return "unknown ticket or matrix id";
+    case EXPM_PFD_ERR_SYNC: return "a triangular sweep lost its dependency order; results are invalid";
     default: return "unknown error";
   }
 }

@@ -530,18 +530,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
 }
 
 // ---------------------------------------------------------------------------
-// One step J of a block triangular sweep on 16-column right-hand sides,
-// fused into one launch (nb = 64):
-//   x_J = D_J b_J           D_J = inverse of the diagonal block (or its
-//                            conjugate transpose), applied as a product
-//   X_I -= A_IJ x_J         for the row tiles I still to be updated
-// Workgroup 0 of a batch writes x_J into rows J; workgroup t >= 1 updates row
-// tile I = tile0 + dir*(t-1) and, if I is the next diagonal block, also copies
-// the updated rows to bout so the next step reads b_{J+dir} from there (the
-// rows of X itself are rewritten concurrently by that step's workgroup 0).
-// A_IJ is W[I rows][J cols] or, with conj, the conjugate transpose of
-// W[J rows][I cols].  Batches < split use operands *0, the others *1.
-// grid (1 + ntiles, batch), block 256 (four waves, 16 rows each)
+// A whole block triangular sweep on thin right-hand sides in ONE launch.
+// The right-hand sides are split into chains of 16 columns: chain c is
+// columns [c16*16, c16*16+16) of pole block bb = c / cpb (cpb = 16-column
+// chains per block), c16 = c % cpb, i.e. X + bb*sX + c16*16.  For row tile I
+// (64 rows; tiles visited in sweep order, I = q forward or nsteps-1-q backward):
+//   acc = sum over the tiles J before I in sweep order of A_IJ x_J
+//   x_I = D_I (b_I - acc)       written over b_I in X
+// D_I is the inverse of the diagonal block (or its conjugate transpose), A_IJ
+// the off-diagonal block W[I rows][J cols] or, with conj, the conjugate
+// transpose of W[J rows][I cols].  Blocks bb < split use operands *0, the
+// others *1.
+// Scheduling: a workgroup takes a ticket from `counter` when it starts; ticket
+// t = q*nchain + c handles tile position q of chain c.  Its waits are on
+// x_J of the same chain at positions < q, i.e. on smaller tickets, which were
+// taken by workgroups already running: every wait ends.  x_J is announced by
+// flags[(c*nsteps + J) * FLAG_STRIDE] == epoch.  Each wait is also capped; a
+// capped wait records 1 in *status and the sweep result is then invalid.
+// grid (nchain * nsteps), block 256: wave w owns rows 16w..16w+15 of the tile.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct SweepOperand {
@@ -550,107 +556,266 @@ struct SweepOperand {
   int conj;
 };
 
+constexpr int SWEEP_SPIN_CAP = 1 << 20;
+constexpr int FLAG_STRIDE = 32;  // one 128-byte line per ready flag
+
+// Complex loads and stores made coherent across the device per access
+// (relaxed agent-scope atomics: no cache-wide maintenance instructions).
+__device__ __forceinline__ float2 coherent_load(const float2* p) {
+  const unsigned long long v =
+      __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 r;
+  r.x = __uint_as_float((unsigned)v);
+  r.y = __uint_as_float((unsigned)(v >> 32));
+  return r;
+}
+__device__ __forceinline__ double2 coherent_load(const double2* p) {
+  unsigned long long* q = (unsigned long long*)p;
+  double2 r;
+  r.x = __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  r.y = __longlong_as_double((long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  return r;
+}
+__device__ __forceinline__ void coherent_store(float2* p, float2 v) {
+  const unsigned long long u = (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+  __hip_atomic_store((unsigned long long*)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(double2* p, double2 v) {
+  unsigned long long* q = (unsigned long long*)p;
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// eight consecutive complex values from a 16-byte aligned address
+template <typename T>
+__device__ __forceinline__ void load8(const T* p, T* a) {
+  if constexpr (sizeof(T) == 8) {
+    const float4* q = (const float4*)p;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float4 v = q[u];
+      a[2 * u].x = v.x;
+      a[2 * u].y = v.y;
+      a[2 * u + 1].x = v.z;
+      a[2 * u + 1].y = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = p[u];
+  }
+}
+
+// Element at a byte offset from a wave-uniform base (offsets within one 64-row
+// block always fit 32 bits), so loads take the scalar-base + 32-bit offset form.
+template <typename T>
+__device__ __forceinline__ const T& at_bytes(const T* base, unsigned off) {
+  return *(const T*)((const char*)base + off);
+}
+
+// One complex MAC block for the wave's 16 x 16 output: 8 consecutive complex k
+// of the lane's half (see below), a[u] = Blk(row, k), bv[u] = B(k, column).
 template <typename R>
-__global__ __launch_bounds__(256) void k_sweep16(int J, int tile0, int dir, SweepOperand<R> d0, SweepOperand<R> d1,
-                                                 SweepOperand<R> a0, SweepOperand<R> a1, int split, cx<R>* X,
-                                                 int64_t sX, int64_t ldx, const cx<R>* bin, cx<R>* bout,
-                                                 int64_t sbuf) {
+__device__ __forceinline__ void mac8(const cx<R>* a, const cx<R>* bv, bool odd, typename Mfma<R>::V& accR,
+                                     typename Mfma<R>::V& accI) {
+  using MF = Mfma<R>;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const R bR = odd ? bv[u].y : bv[u].x;
+    accR = MF::run(odd ? -a[u].y : a[u].x, bR, accR);
+    accI = MF::run(odd ? a[u].x : a[u].y, bR, accI);
+  }
+}
+
+// Eight elements of the wave's 16 x 64 slice of a 64 x 64 block, in the
+// product layout: lane (r16, kq) gets Blk(row0 + r16, 32h + k8 + u), u = 0..7,
+// h = kq >> 1.  Each lane walks 32 consecutive k over the four chunks, so a
+// row-major block is read with 16-byte loads along its rows.  Blk(i, k) =
+// p[i*ld + k], or conj(p[k*ld + i]) with CONJ.  The base pointer is
+// wave-uniform and all offsets inside one 64-row block fit 32 bits.
+template <typename R, bool CONJ>
+__device__ __forceinline__ void load_chunk(const cx<R>* p, int64_t ld, int row0, int k8, cx<R>* a) {
+  using T = cx<R>;
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, h = (lane >> 4) >> 1;
+  const unsigned e = sizeof(T), lde = (unsigned)ld * e;
+  const char* pb = (const char*)p;
+  if constexpr (CONJ) {
+    const unsigned off = (32u * h + k8) * lde + (unsigned)(row0 + r16) * e;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = cconj(*(const T*)(pb + off + u * lde));
+  } else {
+    load8((const T*)(pb + (unsigned)(row0 + r16) * lde + (32u * h + k8) * e), a);
+  }
+}
+
+// Eight elements of x (rows 32h + k8 + u, column r16) read with per-access
+// coherent loads: x was written by another workgroup of the same launch
+template <typename R>
+__device__ __forceinline__ void load_x_chunk(const cx<R>* x, int64_t ldx, int k8, cx<R>* bv) {
+  using T = cx<R>;
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, h = (lane >> 4) >> 1;
+  const unsigned e = sizeof(T), ldxe = (unsigned)ldx * e;
+  const char* xb = (const char*)x + (32u * h + k8) * ldxe + (unsigned)r16 * e;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) bv[u] = coherent_load((const T*)(xb + u * ldxe));
+}
+
+// Wait until the chain's flag for block J carries this launch's epoch (one
+// wave polls, then the workgroup is released by a barrier).  Capped; a failed
+// wait anywhere ends every later wait at once.
+__device__ __forceinline__ void chain_wait(const int* flag, int epoch, int* status) {
+  if ((threadIdx.x >> 6) == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      __builtin_amdgcn_s_sleep(2);
+      ++spins;
+      if ((spins & 127) == 0 && __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (spins > SWEEP_SPIN_CAP) {
+        atomicOr(status, 1);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// acc = sum over the blocks J before I in sweep order of A_IJ x_J.  FP32
+// slices are loaded before each wait (their loads overlap it); FP64 slices are
+// loaded chunk by chunk after it, which keeps the registers for three
+// workgroups per CU.
+template <typename R, bool CONJ>
+__device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nsteps, const cx<R>* W, int64_t ld,
+                                                 const cx<R>* Xc, int64_t ldx, int row0, const int* fl, int epoch,
+                                                 int* status, typename Mfma<R>::V& accR,
+                                                 typename Mfma<R>::V& accI) {
+  using T = cx<R>;
+  constexpr int NB = NB_MAX;
+  const bool odd = (threadIdx.x >> 4) & 1;
+  for (int qq = 0; qq < q; ++qq) {
+    const int J = fwd ? qq : nsteps - 1 - qq;
+    const T* Ablk = CONJ ? W + (int64_t)(J * NB) * ld + I * NB : W + (int64_t)(I * NB) * ld + J * NB;
+    const T* xJ = Xc + (int64_t)(J * NB) * ldx;
+    if constexpr (sizeof(R) == 4) {
+      T a[32];
+#pragma unroll
+      for (int k8 = 0; k8 < 32; k8 += 8) load_chunk<R, CONJ>(Ablk, ld, row0, k8, a + k8);
+      chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+#pragma unroll
+      for (int k8 = 0; k8 < 32; k8 += 8) {
+        T bv[8];
+        load_x_chunk<R>(xJ, ldx, k8, bv);
+        mac8<R>(a + k8, bv, odd, accR, accI);
+      }
+    } else {
+      chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+#pragma unroll
+      for (int k8 = 0; k8 < 32; k8 += 8) {
+        T a[8], bv[8];
+        load_chunk<R, CONJ>(Ablk, ld, row0, k8, a);
+        load_x_chunk<R>(xJ, ldx, k8, bv);
+        mac8<R>(a, bv, odd, accR, accI);
+      }
+    }
+  }
+}
+
+// Solution blocks are handed between workgroups without cache maintenance:
+// they are written and read with per-access coherent atomics, and a block's
+// flag is set only after its stores have completed.
+template <typename R>
+__global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nchain, int cpb, SweepOperand<R> d0,
+                                                     SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
+                                                     int split, cx<R>* X, int64_t sX, int64_t ldx,
+                                                     unsigned* counter, unsigned base, int* flags, int epoch,
+                                                     int* status) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
   constexpr int NB = NB_MAX;
-  __shared__ T As[NB][NB + 1];
-  __shared__ T Bs[NB][17];
-  const int bb = blockIdx.y;
+  constexpr bool DS_LDS = sizeof(R) == 4;  // FP32: D_I staged in LDS ahead of use
+  __shared__ T Ds[DS_LDS ? NB : 1][NB + 1];
+  __shared__ T Rs[NB][17];
+  __shared__ unsigned s_ticket;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  if (tid == 0) s_ticket = atomicAdd(counter, 1u) - base;
+  __syncthreads();
+  const unsigned ticket = (unsigned)__builtin_amdgcn_readfirstlane((int)s_ticket);
+  if (ticket >= (unsigned)(nchain * nsteps)) {
+    if (tid == 0) atomicOr(status, 2);
+    return;
+  }
+  const int q = (int)(ticket / (unsigned)nchain), c = (int)(ticket % (unsigned)nchain);
+  const int bb = c / cpb, c16 = c % cpb;
   const bool second = bb >= split;
   const int hb = second ? bb - split : bb;
   const SweepOperand<R> dop = second ? d1 : d0;
   const SweepOperand<R> aop = second ? a1 : a0;
-  X += bb * sX;
-  bin += bb * sbuf;
-  bout += bb * sbuf;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r16 = lane & 15, kq = lane >> 4;
+  const T* W = aop.p + hb * aop.stride;
+  T* Xc = X + bb * sX + c16 * 16;
+  const int* fl = flags + (int64_t)c * nsteps * FLAG_STRIDE;
+  const int I = fwd ? q : nsteps - 1 - q;
+  const int row0 = 16 * w;
+  const T* D = dop.p + hb * dop.stride + (int64_t)I * 2 * NB * NB;
 
-  // x_J = D_J b_J
-  const T* D = dop.p + hb * dop.stride + (int64_t)J * 2 * NB * NB;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e / NB, k = e % NB;
-    As[i][k] = dop.conj ? cconj(D[k * NB + i]) : D[i * NB + k];
-  }
-  for (int e = tid; e < NB * 16; e += 256) Bs[e / 16][e % 16] = bin[e];
-  __syncthreads();
-  auto product = [&](V& accR, V& accI) {
-    accR = V{0, 0, 0, 0};
-    accI = V{0, 0, 0, 0};
-#pragma unroll 8
-    for (int k2 = 0; k2 < NB / 2; ++k2) {
-      const int kc = 2 * k2 + (kq >> 1);
-      const bool odd = kq & 1;
-      const T av = As[16 * w + r16][kc];
-      const T bv = Bs[kc][r16];
-      const R bR = odd ? bv.y : bv.x;
-      accR = MF::run(odd ? -av.y : av.x, bR, accR);
-      accI = MF::run(odd ? av.x : av.y, bR, accI);
+  if constexpr (DS_LDS) {
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e / NB, k = e % NB;
+      Ds[i][k] = dop.conj ? cconj(D[k * NB + i]) : D[i * NB + k];
     }
-  };
-  V xR, xI;
-  product(xR, xI);
-  __syncthreads();
-  if (blockIdx.x == 0) {
+  }
+  // b_I in the product layout: lane (r16, kq), register r holds row MF::row(kq, r)
+  T b[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * w + MF::row(kq, r);
-      T v;
-      v.x = xR[r];
-      v.y = xI[r];
-      X[(int64_t)(J * NB + row) * ldx + r16] = v;
-    }
-    return;
+  for (int r = 0; r < 4; ++r) b[r] = Xc[(int64_t)(I * NB + row0 + MF::row(kq, r)) * ldx + r16];
+  V accR = V{0, 0, 0, 0}, accI = V{0, 0, 0, 0};
+  if (aop.conj)
+    chain_accumulate<R, true>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, accR, accI);
+  else
+    chain_accumulate<R, false>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, accR, accI);
+  // r = b_I - acc, shared by the four waves for the diagonal-block product
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T v;
+    v.x = b[r].x - accR[r];
+    v.y = b[r].y - accI[r];
+    Rs[row0 + MF::row(kq, r)][r16] = v;
   }
-  // X_I -= A_IJ x_J
-  const int I = tile0 + dir * ((int)blockIdx.x - 1);
+  __syncthreads();
+  V xR = V{0, 0, 0, 0}, xI = V{0, 0, 0, 0};
+  {
+    const int h = kq >> 1;
+#pragma unroll
+    for (int k8 = 0; k8 < 32; k8 += 8) {
+      T a[8], bv[8];
+      if constexpr (DS_LDS) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = Ds[row0 + r16][32 * h + k8 + u];
+      } else if (dop.conj) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = cconj(D[(32 * h + k8 + u) * NB + row0 + r16]);
+      } else {
+        load8(D + (row0 + r16) * NB + 32 * h + k8, a);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) bv[u] = Rs[32 * h + k8 + u][r16];
+      mac8<R>(a, bv, kq & 1, xR, xI);
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     T v;
     v.x = xR[r];
     v.y = xI[r];
-    Bs[16 * w + MF::row(kq, r)][r16] = v;
+    coherent_store(Xc + (int64_t)(I * NB + row0 + MF::row(kq, r)) * ldx + r16, v);
   }
-  const T* W = aop.p + hb * aop.stride;
-  for (int e = tid; e < NB * NB; e += 256) {
-    if (!aop.conj) {
-      const int i = e / NB, k = e % NB;
-      As[i][k] = W[(int64_t)(I * NB + i) * aop.ld + J * NB + k];
-    } else {
-      const int k = e / NB, i = e % NB;
-      As[i][k] = cconj(W[(int64_t)(J * NB + k) * aop.ld + I * NB + i]);
-    }
-  }
+  // publish x_I: every wave's stores have completed before the flag is set
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  V yR, yI;
-  product(yR, yI);
-  const bool next = I == J + dir;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = 16 * w + MF::row(kq, r);
-    T* px = X + (int64_t)(I * NB + row) * ldx + r16;
-    T v = *px;
-    v.x -= yR[r];
-    v.y -= yI[r];
-    *px = v;
-    if (next) bout[row * 16 + r16] = v;
-  }
-}
-
-// Copy rows [row0, row0+64) of every 16-column block into a staging buffer
-// (the first b_J of a fused sweep).  grid (batch), block 256.
-template <typename R>
-__global__ __launch_bounds__(256) void k_gather16(const cx<R>* __restrict__ X, int64_t sX, int64_t ldx, int row0,
-                                                  cx<R>* __restrict__ buf, int64_t sbuf) {
-  const int bb = blockIdx.x;
-  for (int e = threadIdx.x; e < NB_MAX * 16; e += 256)
-    buf[bb * sbuf + e] = X[bb * sX + (int64_t)(row0 + e / 16) * ldx + e % 16];
+  if (tid == 0) __hip_atomic_store((int*)fl + I * FLAG_STRIDE, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------

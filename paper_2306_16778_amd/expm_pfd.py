@@ -32,6 +32,7 @@ EXPORTED = (
     "expm_pfd_workspace_bytes",
     "expm_pfd_apply",
     "expm_pfd_destroy",
+    "expm_pfd_plan_check",
     "expm_pfd_apply_batched",
     "expm_pfd_strerror",
     "expm_pfd_trace",
@@ -85,6 +86,7 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_workspace_bytes.argtypes = [i64, c_int, i64, ctypes.POINTER(_Opts), ctypes.POINTER(ctypes.c_size_t)]
     lib.expm_pfd_apply.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
     lib.expm_pfd_destroy.argtypes = [vp]
+    lib.expm_pfd_plan_check.argtypes = [vp]
     lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(_Opts), vp]
     lib.expm_pfd_trace.argtypes = [c_int]
@@ -171,6 +173,11 @@ def expm_pfd_destroy(plan: Plan):
     if plan.handle:
         _check(load_library().expm_pfd_destroy(plan.handle), "expm_pfd_destroy")
         plan.handle = None
+
+
+def expm_pfd_plan_check(plan: Plan):
+    """Raise ExpmPfdError if a triangular sweep of this plan lost its dependency order."""
+    _check(load_library().expm_pfd_plan_check(plan.handle), "expm_pfd_plan_check")
 
 
 def _colmajor(x, torch):

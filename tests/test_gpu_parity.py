@@ -49,6 +49,7 @@ def _run(ep, A, V, t, d, precision="fp64", m_max=None):
     plan = ep.expm_pfd_plan(n, d, t, mm, precision)
     X = ep.expm_pfd_apply(plan, _dev(A), None if V is None else _dev(V))
     torch.cuda.synchronize()
+    ep.expm_pfd_plan_check(plan)  # every one-launch sweep kept its dependency order
     return X.cpu().numpy()
 
 
@@ -73,6 +74,9 @@ CASES = [
     (200, (-100, 0), 16, 24, 1.0),
     (257, (-100, 0), 5, 16, 1.0),
     (300, (-40, 0), None, 16, 0.9),
+    (150, (-100, 0), 40, 16, 1.0),   # three 16-column chains per pole block
+    (128, (-60, 0), 64, 16, 0.8),    # four chains: widest one-launch sweep
+    (96, (-30, 0), 65, 16, 1.0),     # 80-column blocks: sweeps by block products
 ]
 
 
@@ -153,6 +157,26 @@ def test_deterministic(ep):
     X1 = _run(ep, A, V, t, 24)
     X2 = _run(ep, A, V, t, 24)
     assert np.array_equal(X1, X2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plan_reuse_identical(ep, precision):
+    """One plan applied three times: every one-launch sweep starts from the
+    previous launch's counters and flags and gives the same bits."""
+    import torch
+    A, V, t = _problem(320, -100, 0, 7, 31)
+    _announce(f"plan reuse {precision} n=320 m=7 d=16")
+    plan = ep.expm_pfd_plan(320, 16, t, 7, precision)
+    Ad, Vd = _dev(A), _dev(V)
+    outs = []
+    for _ in range(3):
+        X = ep.expm_pfd_apply(plan, Ad, Vd)
+        torch.cuda.synchronize()
+        outs.append(X.cpu().numpy())
+    ep.expm_pfd_plan_check(plan)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    Y = matrix.expm_R(A, V, t, 16)
+    assert matrix.rel_fro(outs[0], Y) < (TOL64 if precision == "fp64" else TOLMX)
 
 
 def test_config2_full_size_fp64_and_mixed(ep):
