@@ -174,20 +174,31 @@ void panel(hipStream_t st, int IB, int S, const PanelArgs& g, cx<R>* W) {
 // MODE 0: C -= op(A) B;  MODE 1: C = op(A) B.  Batches < split use a0, others a1.
 template <typename R, int MODE>
 void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
-          const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc) {
+          const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp = {1, 0, 0, 0}) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
   const double e = sizeof(cx<R>);
-  trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * K,
-                  e * batch * ((double)M * K + (double)K * N + (MODE == 0 ? 2.0 : 1.0) * M * N));
+  const double Kt = (double)K * ksp.ks;
+  trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * Kt,
+                  e * batch * ((double)M * Kt + Kt * N + (MODE == 0 ? 2.0 : (double)ksp.ks) * M * N));
+  const unsigned gy = (unsigned)(batch * ksp.ks);
   if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM) {
     const int tiles = (int)((M + 63) / 64);
-    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 16, 4, 1>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, a0, a1, split,
-                       B, sB, ldb, C, sC, ldc);
+    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 16, 4, 1>), dim3(tiles, gy), dim3(256), 0, st, M, N, K, a0, a1, split, B,
+                       sB, ldb, C, sC, ldc, ksp);
   } else {
     const int tiles = (int)(((M + 63) / 64) * ((N + 63) / 64));
-    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 64, 2, 2>), dim3(tiles, batch), dim3(256), 0, st, M, N, K, a0, a1, split,
-                       B, sB, ldb, C, sC, ldc);
+    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 64, 2, 2>), dim3(tiles, gy), dim3(256), 0, st, M, N, K, a0, a1, split, B,
+                       sB, ldb, C, sC, ldc, ksp);
   }
+}
+
+// K slices of the FP64 refinement product (t A) X for thin right-hand sides: a
+// function of the padded order only, so a problem's bits do not depend on the
+// batch it runs in
+inline int ir_kslices(int64_t npad) {
+  int s = 1;
+  while (s < 8 && npad / (2 * s) >= 256) s *= 2;
+  return s;
 }
 
 template <typename R>
@@ -257,6 +268,7 @@ struct expm_pfd_plan_s {
   double2* Ah = nullptr;     // mixed: G x npad x npad FP64 t*A (Hermitian, row-major)
   double2* X64 = nullptr;    // mixed: npad x cols_alloc
   double2* R64 = nullptr;    // mixed: npad x cols_alloc
+  double2* Rpart = nullptr;  // mixed: ir_kslices(npad) x npad x (2 PB min(mp_max, 64)) split-K partials
   ProblemDesc* d_descs = nullptr;  // G problem descriptors on the device (batched entry point)
   int device = 0;
 };
@@ -265,8 +277,8 @@ namespace {
 
 struct Sizes {
   int64_t npad, cols, w_elem;
-  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, consts, descs;
-  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + consts + descs; }
+  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, rpart, consts, descs;
+  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + rpart + consts + descs; }
 };
 
 Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision) {
@@ -285,6 +297,7 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
   s.ah = fp64 ? 0 : (size_t)G * npad * npad * 16;
   s.x64 = fp64 ? 0 : (size_t)npad * s.cols * 16;
   s.r64 = s.x64;
+  s.rpart = fp64 ? 0 : (size_t)ir_kslices(npad) * npad * (2 * PB * std::min<int64_t>(mp_max, CHAIN_MP_MAX)) * 16;
   s.consts = 2 * 64 * 16;
   s.descs = (size_t)G * sizeof(ProblemDesc);
   return s;
@@ -299,7 +312,7 @@ int check_opts(const expm_pfd_opts* o) {
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
   void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
-                  p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->d_descs};
+                  p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->Rpart, p->d_descs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -352,6 +365,7 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
     he(hipMalloc(&pl->Ah, sz.ah));
     he(hipMalloc(&pl->X64, sz.x64));
     he(hipMalloc(&pl->R64, sz.r64));
+    he(hipMalloc(&pl->Rpart, sz.rpart));
   }
   if (he.e == hipSuccess) {
     he(hipMemcpy(pl->d_theta, pl->h_theta.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
@@ -587,20 +601,35 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
         hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, PB, P,
                            descs, one);
       }
-      for (int half = 0; half < (full ? 1 : 2); ++half) {
-        const int64_t off = (int64_t)half * PB * mp;
-        gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, G, npad, P * mp, npad, opnd<double>(pl->Ah, nn, npad, false),
-                        opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS, pl->R64 + off,
-                        (int64_t)P * mp, ldS);
+      // up to 64 right-hand-side columns per pole: the product in K slices
+      // (partials in Rpart, too few output tiles otherwise); wider blocks and
+      // V = I: subtracted from R64 directly
+      const bool split = !full && mp <= CHAIN_MP_MAX;
+      const int S = split ? ir_kslices(npad) : 0;
+      const int64_t pstride = (int64_t)npad * ldS;
+      if (!split) {
+        for (int half = 0; half < (full ? 1 : 2); ++half) {
+          const int64_t off = (int64_t)half * PB * mp;
+          gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, G, npad, P * mp, npad, opnd<double>(pl->Ah, nn, npad, false),
+                          opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS, pl->R64 + off,
+                          (int64_t)P * mp, ldS);
+        }
+      } else {
+        const int Ks = npad / S;
+        const KSplit ksp{S, Ks, (int64_t)Ks * ldS, pstride};
+        // one launch covers both halves when the group holds one problem
+        const int nh = G == 1 ? 1 : 2, ncols = G == 1 ? 2 * P * mp : P * mp;
+        for (int half = 0; half < nh; ++half) {
+          const int64_t off = (int64_t)half * PB * mp;
+          gemm<double, 1>(st, EXPM_PFD_K_IR_GEMM, G, npad, ncols, Ks, opnd<double>(pl->Ah, nn, npad, false),
+                          opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS,
+                          pl->Rpart + off, (int64_t)P * mp, ldS, ksp);
+        }
       }
       {
-        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, 3 * e64 * count);
-        hipLaunchKernelGGL(k_shift_sub, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->X64, ldS, npad, mp, PB,
-                           P, pl->d_theta);
-      }
-      {
-        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
-        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, Xs, count);
+        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, (2.0 + S) * e64 * count + 8.0 * count);
+        hipLaunchKernelGGL(k_residual32, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->Rpart, S, pstride,
+                           pl->X64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
       }
       solves<float>(pl, Xs, ldS, mp, !full, st);
       {

@@ -371,9 +371,12 @@ __global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ 
 // K5: complex matrix products on the matrix cores, batched over blockIdx.y:
 //   MODE 0:  C -= op(A) B        MODE 1:  C = op(A) B
 // op(A) = A (row-major M x K) or, with conj, the conjugate transpose of a
-// row-major K x M array.  Batches b < split use operand a0 (at a0.p +
-// b*a0.stride), the others a1 (at a1.p + (b-split)*a1.stride), so a primal and
-// an adjoint sweep share one launch.  B row-major K x N, C row-major M x N.
+// row-major K x M array.  blockIdx.y = g*ks + s: product g of the batch, K
+// slice s of ks (split K: slice s starts at A + s*kA, B + s*kB and writes
+// C + s*kC, so each slice's partial product lands in its own array).  Products
+// g < split use operand a0 (at a0.p + g*a0.stride), the others a1 (at a1.p +
+// (g-split)*a1.stride), so a primal and an adjoint sweep share one launch.
+// B row-major K x N, C row-major M x N.
 // MODE 1 may overwrite B in place when one row tile covers M (BM >= M): every
 // workgroup reads all of its B columns before writing them.
 // Complex products from real 16x16x4 products: the K dimension is interleaved
@@ -383,6 +386,11 @@ __global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ 
 // Tiles BM x BN per 256-thread workgroup, waves WGM x WGN, K staged through LDS
 // in chunks of 16.
 // ---------------------------------------------------------------------------
+struct KSplit {
+  int ks;             // K slices per product (1: no split)
+  int64_t kA, kB, kC;  // element offsets of slice s: A + s*kA, B + s*kB, C + s*kC
+};
+
 template <typename R>
 struct GemmOperand {
   const cx<R>* p;
@@ -393,7 +401,7 @@ struct GemmOperand {
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
-                                              int64_t ldc) {
+                                              int64_t ldc, KSplit ksp) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
@@ -407,14 +415,14 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
 
   const int tiles_m = (M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int bb = blockIdx.y;
+  const int bb = (int)blockIdx.y / ksp.ks, ks = (int)blockIdx.y % ksp.ks;
   const bool second = bb >= split;
   const GemmOperand<R> op = second ? a1 : a0;
-  const T* A = op.p + (second ? bb - split : bb) * op.stride;
+  const T* A = op.p + (second ? bb - split : bb) * op.stride + ks * ksp.kA;
   const int64_t lda = op.ld;
   const bool conj = op.conj != 0;
-  B += bb * sB;
-  C += bb * sC;
+  B += bb * sB + ks * ksp.kB;
+  C += bb * sC + ks * ksp.kC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm0 = (w / WGN) * WM, wn0 = (w % WGN) * WN;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -996,6 +1004,39 @@ __global__ __launch_bounds__(256) void k_add_correction(double2* __restrict__ X,
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
     X[e].x += (double)D[e].x;
     X[e].y += (double)D[e].y;
+  }
+}
+
+// Refinement right-hand side in FP32:
+//   out = Rres - sum_{s < nparts} part[s*pstride + e] - shift_b * X
+// Rres holds the staged V (minus the product, when nparts = 0); part the split-K
+// partial products of (t A) X, summed in slice order.  Block b's shift: primal
+// blocks (b < GP) theta of pair b mod P, adjoint blocks its conjugate.
+__global__ __launch_bounds__(256) void k_residual32(const double2* __restrict__ Rres, const double2* __restrict__ part,
+                                                    int nparts, int64_t pstride, const double2* __restrict__ X,
+                                                    int64_t ldS, int npad, int mp, int GP, int P,
+                                                    const double2* __restrict__ theta, float2* __restrict__ out) {
+  const int64_t total = (int64_t)npad * ldS;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int blk = (int)((e % ldS) / mp);
+    double2 th = theta[(blk % GP) % P];
+    if (blk >= GP) th.y = -th.y;
+    double2 sum = {0.0, 0.0};
+    for (int s = 0; s < nparts; ++s) {
+      const double2 p = part[s * pstride + e];
+      sum.x += p.x;
+      sum.y += p.y;
+    }
+    const double2 x = X[e];
+    double2 r = Rres[e];
+    r.x -= sum.x;
+    r.y -= sum.y;
+    r.x -= th.x * x.x - th.y * x.y;
+    r.y -= th.x * x.y + th.y * x.x;
+    float2 o;
+    o.x = (float)r.x;
+    o.y = (float)r.y;
+    out[e] = o;
   }
 }
 
