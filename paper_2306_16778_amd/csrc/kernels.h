@@ -439,44 +439,51 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
       accI[i][j] = V{0, 0, 0, 0};
     }
 
-  // one K chunk of A (op applied, conjugated if needed) and B into registers
+  // one K chunk of A (op applied, conjugated if needed) and B into registers.
+  // Branch-free: out-of-range elements load from the operand's first element and
+  // are scaled by zero when stashed (a multiply, not a select, so every load of a
+  // chunk stays unconditional and in flight during the products of the current
+  // chunk; the scaling is consumed only after them).
   T ra[AE], rb[BE];
+  R fa[AE], fb[BE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
       const int e = tid + 256 * q;
-      T v = czero<T>();
-      if (!conj) {
-        const int i = e / KC, k = e % KC;
-        if (m0 + i < M && k0 + k < K) v = A[(int64_t)(m0 + i) * lda + k0 + k];
-      } else {
-        const int i = e % BM, k = e / BM;
-        if (m0 + i < M && k0 + k < K) v = cconj(A[(int64_t)(k0 + k) * lda + m0 + i]);
-      }
-      ra[q] = v;
+      const int i = conj ? e % BM : e / KC, k = conj ? e / BM : e % KC;
+      const bool ok = m0 + i < M && k0 + k < K;
+      const int64_t idx = !ok ? 0 : conj ? (int64_t)(k0 + k) * lda + m0 + i : (int64_t)(m0 + i) * lda + k0 + k;
+      ra[q] = A[idx];
+      fa[q] = ok ? R(1) : R(0);
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
       const int e = tid + 256 * q;
       const int j = e % BN, k = e / BN;
-      T v = czero<T>();
-      if (n0 + j < N && k0 + k < K) v = B[(int64_t)(k0 + k) * ldb + n0 + j];
-      rb[q] = v;
+      const bool ok = n0 + j < N && k0 + k < K;
+      rb[q] = B[ok ? (int64_t)(k0 + k) * ldb + n0 + j : 0];
+      fb[q] = ok ? R(1) : R(0);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
       const int e = tid + 256 * q;
+      T v;
+      v.x = ra[q].x * fa[q];
+      v.y = (conj ? -ra[q].y : ra[q].y) * fa[q];
       if (!conj)
-        As[buf][e / KC][e % KC] = ra[q];
+        As[buf][e / KC][e % KC] = v;
       else
-        As[buf][e % BM][e / BM] = ra[q];
+        As[buf][e % BM][e / BM] = v;
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
       const int e = tid + 256 * q;
-      Bs[buf][e / BN][e % BN] = rb[q];
+      T v;
+      v.x = rb[q].x * fb[q];
+      v.y = rb[q].y * fb[q];
+      Bs[buf][e / BN][e % BN] = v;
     }
   };
 
@@ -514,6 +521,21 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
     if (ch + 1 < nchunks) stash(cur ^ 1);
     __syncthreads();
   }
+  // epilogue: all C loads (clamped in range) first, then the guarded stores
+  T cold[MI][NJ][4];
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm0 + i * 16 + MF::row(kq, r);
+          const int col = n0 + wn0 + j * 16 + r16;
+          const bool ok = row < M && col < N;
+          cold[i][j][r] = C[ok ? (int64_t)row * ldc + col : 0];
+        }
+  }
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -522,18 +544,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + i * 16 + MF::row(kq, r);
         const int col = n0 + wn0 + j * 16 + r16;
-        if (row < M && col < N) {
-          T c;
-          if (MODE == 0) {
-            c = C[(int64_t)row * ldc + col];
-            c.x -= accR[i][j][r];
-            c.y -= accI[i][j][r];
-          } else {
-            c.x = accR[i][j][r];
-            c.y = accI[i][j][r];
-          }
-          C[(int64_t)row * ldc + col] = c;
+        T c;
+        if constexpr (MODE == 0) {
+          c = cold[i][j][r];
+          c.x -= accR[i][j][r];
+          c.y -= accI[i][j][r];
+        } else {
+          c.x = accR[i][j][r];
+          c.y = accI[i][j][r];
         }
+        if (row < M && col < N) C[(int64_t)row * ldc + col] = c;
       }
 }
 
