@@ -64,6 +64,30 @@ __device__ __forceinline__ T crecip(T a) {
   }
   return r;
 }
+// reciprocal from the hardware estimate refined by Newton steps (one in FP32,
+// two in FP64: the FP64 estimate is good to about 2^-22)
+__device__ __forceinline__ float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+// 1/a by the same scaling as crecip, with reciprocals instead of divisions
+template <typename T>
+__device__ __forceinline__ T crecip_fast(T a) {
+  const bool re_big = fabs(a.x) >= fabs(a.y);
+  const auto big = re_big ? a.x : a.y, small = re_big ? a.y : a.x;
+  const auto q = small * rcp_nr(big);
+  const auto rd = rcp_nr(big + small * q);
+  T r;
+  r.x = re_big ? rd : q * rd;
+  r.y = re_big ? -q * rd : -rd;
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ T cdiv(T a, T b) {
   return cmul(a, crecip(b));

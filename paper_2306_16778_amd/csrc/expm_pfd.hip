@@ -102,9 +102,9 @@ struct HipErr {
   }
 };
 
-// Inner panel width: the register panel holds IB columns of ceil(npad/1024)
-// rows per thread (<= 16 complex per thread in FP64, 32 in FP32) and is staged
-// through a 1024 x IB LDS buffer of 128 KB.
+// Inner panel width: the register panel holds IB columns of ceil(npad/PANEL_NT)
+// rows per thread (<= 32 complex per thread in FP64, 64 in FP32: 128 registers)
+// and is staged through a PANEL_NT x IB LDS buffer of 64 KB.
 int inner_width(int64_t npad, bool fp64) {
   if (fp64) return npad <= 2048 ? 8 : npad <= 4096 ? 4 : 2;
   return npad <= 2048 ? 16 : npad <= 4096 ? 8 : 4;
@@ -122,12 +122,13 @@ struct PanelArgs {
 template <typename R, int IB, int S>
 void panel_launch(hipStream_t st, const PanelArgs& g, cx<R>* W) {
   const int P = g.P;
-  constexpr int LIMIT = sizeof(R) == 8 ? 16 : 32;
-  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 || IB <= 8)) {
+  constexpr int LIMIT = sizeof(R) == 8 ? 32 : 64;
+  // widths inner_width can choose: FP32 16/8/4, FP64 8/4/2
+  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 ? IB >= 4 : IB <= 8)) {
     const double rows = g.npad - g.c0;
     trace::Scope ts(st, EXPM_PFD_K_PANEL, (double)P * 4.0 * rows * IB * IB,
                     (double)P * 2.0 * rows * IB * sizeof(cx<R>));
-    hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(1024), 0, st, W, g.ws, g.ld, g.npad, g.j0, g.c0, g.nbo,
+    hipLaunchKernelGGL((k_panel<R, IB, S>), dim3(P), dim3(PANEL_NT), 0, st, W, g.ws, g.ld, g.npad, g.j0, g.c0, g.nbo,
                        g.ipiv, g.ps, g.moves, g.ms, g.step, g.last);
   }
 }
@@ -147,6 +148,14 @@ void panel_dispatch(hipStream_t st, int S, const PanelArgs& g, cx<R>* W) {
     CASE(6)
     CASE(7)
     CASE(8)
+    CASE(9)
+    CASE(10)
+    CASE(11)
+    CASE(12)
+    CASE(13)
+    CASE(14)
+    CASE(15)
+    CASE(16)
 #undef CASE
     default:
       break;
@@ -419,7 +428,7 @@ void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one
       g.last = (c0 + IB >= j0 + nbo);
       g.ipiv = pl->ipiv;
       g.moves = pl->moves;
-      panel<R>(st, IB, (npad - c0 + 1023) / 1024, g, W);
+      panel<R>(st, IB, (npad - c0 + PANEL_NT - 1) / PANEL_NT, g, W);
       const int rest = j0 + nbo - c0 - IB;
       if (rest > 0) {
         const int64_t r1 = c0 + IB;

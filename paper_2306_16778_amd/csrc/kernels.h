@@ -82,24 +82,29 @@ __global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ de
 // ---------------------------------------------------------------------------
 // K2: panel factorization with partial pivoting (LAPACK getf2 order) of the
 // IB columns [c0, c0+IB) over rows [c0, npad), one shifted matrix per
-// workgroup.  The panel lives in registers: thread t owns rows c0+t+1024s.
-// Per column (one barrier): every wave finds its candidate row (largest
-// |Re|+|Im|, lowest row on ties) with DPP reductions and publishes value, row
-// index and row contents in LDS; after the barrier every wave reduces the 16
-// candidates the same way, swaps the pivot row in and applies the rank-1
-// update in registers.  The panel is loaded and stored through LDS so that
+// workgroup.  The panel lives in registers: thread t owns rows
+// c0 + t + PANEL_NT*s.  Per column (one barrier): every wave finds its
+// candidate row (largest |Re|+|Im|, lowest row on ties) with DPP reductions and
+// publishes value, row index and row contents in LDS; after the barrier every
+// wave reduces the PANEL_NT/64 candidates the same way, swaps the pivot row in
+// and applies the rank-1 update in registers.  Every wave repeats the per-column
+// bookkeeping (reductions, pivot reciprocal, swaps), so the workgroup is kept
+// at 8 waves with more rows per thread rather than 16.  The panel is loaded and stored through LDS so that
 // global accesses are coalesced.
 // Then, inside the enclosing outer panel [j0, j0+nbo): the IB interchanges are
 // applied to the other outer-panel columns and the IB x (rest) block of U is
 // solved with the unit lower IB x IB factor.  On the last inner step the net
 // row moves of the whole outer step are written for the later updates.
-// grid (batch), block 1024
+// grid (batch), block PANEL_NT
 // ---------------------------------------------------------------------------
+constexpr int PANEL_NT = 512;
+constexpr int PANEL_NW = PANEL_NT / 64;
+
 template <typename R, int IB>
 struct PanelShared {
-  R cand_v[2][16];
-  int cand_i[2][16];
-  cx<R> cand_row[2][16][IB];  // each wave's candidate row
+  R cand_v[2][PANEL_NW];
+  int cand_i[2][PANEL_NW];
+  cx<R> cand_row[2][PANEL_NW][IB];  // each wave's candidate row
   cx<R> crow[2][IB];          // row gc before the interchange
   int piv[NB_MAX];
 };
@@ -117,7 +122,7 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
     int bi = NONE;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
+      const int r = c0 + tid + PANEL_NT * s;
       if (r >= gc && r < npad) {
         const R v = fabs(a[s][C].x) + fabs(a[s][C].y);
         if (v > bv) {
@@ -137,7 +142,7 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
+      const int r = c0 + tid + PANEL_NT * s;
       if (r == wi) {
 #pragma unroll
         for (int cc = 0; cc < IB; ++cc) sh.cand_row[buf][wid][cc] = a[s][cc];
@@ -148,20 +153,21 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
       }
     }
     __syncthreads();
-    // global pivot: each row of 16 lanes reduces the 16 wave candidates
-    const R cv = sh.cand_v[buf][lane & 15];
-    const int ci = sh.cand_i[buf][lane & 15];
+    // global pivot: each row of 16 lanes reduces the wave candidates (each
+    // candidate held by 16 / PANEL_NW lanes of the row)
+    const R cv = sh.cand_v[buf][lane % PANEL_NW];
+    const int ci = sh.cand_i[buf][lane % PANEL_NW];
     const R gv = row16_max(cv);
     const int gi = __builtin_amdgcn_readlane(row16_min(cv == gv ? ci : NONE), 0);
     // no candidate compared greater (a column of NaNs): keep the diagonal row, so
     // every later row index stays inside the matrix
     const bool found = gi >= gc && gi < npad;
     const int p = found ? gi : gc;
-    const T* prow = found ? sh.cand_row[buf][((p - c0) & 1023) >> 6] : sh.crow[buf];
+    const T* prow = found ? sh.cand_row[buf][((p - c0) % PANEL_NT) >> 6] : sh.crow[buf];
     if (tid == 0) sh.piv[gc - j0] = p;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
+      const int r = c0 + tid + PANEL_NT * s;
       if (r == gc) {
 #pragma unroll
         for (int cc = 0; cc < IB; ++cc) a[s][cc] = prow[cc];
@@ -170,10 +176,10 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
         for (int cc = 0; cc < IB; ++cc) a[s][cc] = sh.crow[buf][cc];
       }
     }
-    const T inv = crecip(prow[C]);
+    const T inv = crecip_fast(prow[C]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + 1024 * s;
+      const int r = c0 + tid + PANEL_NT * s;
       if (r > gc && r < npad) {
         const T l = cmul(a[s][C], inv);
         a[s][C] = l;
@@ -185,7 +191,7 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
   }
 }
 
-// LDS staging slot of element (row, col) of a 1024 x IB block; the column is
+// LDS staging slot of element (row, col) of a PANEL_NT x IB block; the column is
 // XOR-swizzled with the row so that one-row-per-lane reads spread over banks.
 template <int IB>
 __device__ __forceinline__ int stage_slot(int row, int col) {
@@ -193,12 +199,12 @@ __device__ __forceinline__ int stage_slot(int row, int col) {
 }
 
 template <typename R, int IB, int S>
-__global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld, int npad, int j0,
+__global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld, int npad, int j0,
                                                 int c0, int nbo, int* __restrict__ ipivb, int64_t pstride,
                                                 int* __restrict__ movesb, int64_t mstride, int step, int last) {
   using T = cx<R>;
   __shared__ PanelShared<R, IB> sh;
-  __shared__ T stage[1024 * IB];  // panel staging; reused as the row-move buffer
+  __shared__ T stage[PANEL_NT * IB];  // panel staging; reused as the row-move buffer
   __shared__ T Lib[IB][IB + 1];
   __shared__ int mv_dst[MOVE_CAP], mv_src[MOVE_CAP];
   __shared__ int mv_cnt;
@@ -209,43 +215,57 @@ __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 
   if (tid < c0 - j0) sh.piv[tid] = ipiv[j0 + tid];  // pivots of the earlier inner steps
+  // all S*IB loads of the panel are issued before the first is used: element
+  // q of block s is row rbase + (tid + PANEL_NT*q) / IB, column (tid + ...) % IB
+  // (consecutive threads read consecutive columns of a row), held in a[s][q]
+  // until the LDS round trip turns it into row-per-thread order
+  // Addresses: a wave-uniform base (panel origin) plus one 32-bit byte offset
+  // per lane; the per-element parts (q, s) are uniform multiples of the row
+  // pitch.  Rows past npad read the panel origin instead (and are zeroed below).
   T a[S][IB];
+  static_assert(PANEL_NT % IB == 0, "whole rows per pass");
+  const char* pbase = (const char*)(W + (int64_t)c0 * ld + c0);
+  const unsigned pitch = (unsigned)ld * (unsigned)sizeof(T);
+  const unsigned lane_off = (unsigned)(tid / IB) * pitch + (unsigned)(tid % IB) * (unsigned)sizeof(T);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int rbase = c0 + 1024 * s;
-    const int nr = npad - rbase < 1024 ? npad - rbase : 1024;
-    if (nr > 0) {
-      for (int e = tid; e < nr * IB; e += 1024) {
-        const int row = e / IB, col = e % IB;
-        stage[stage_slot<IB>(row, col)] = W[(int64_t)(rbase + row) * ld + c0 + col];
-      }
-      __syncthreads();
 #pragma unroll
-      for (int c = 0; c < IB; ++c) a[s][c] = tid < nr ? stage[stage_slot<IB>(tid, c)] : czero<T>();
-      __syncthreads();
-    } else {
-#pragma unroll
-      for (int c = 0; c < IB; ++c) a[s][c] = czero<T>();
+    for (int q = 0; q < IB; ++q) {
+      const int rr = PANEL_NT * s + (PANEL_NT / IB) * q;  // row offset of this pass (uniform)
+      const bool ok = c0 + rr + tid / IB < npad;
+      a[s][q] = *(const T*)(pbase + (ok ? lane_off + (unsigned)rr * pitch : 0u));
     }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int rbase = c0 + PANEL_NT * s;
+    const int nr = npad - rbase < PANEL_NT ? npad - rbase : PANEL_NT;
+#pragma unroll
+    for (int q = 0; q < IB; ++q) {
+      const int e = tid + PANEL_NT * q;
+      stage[stage_slot<IB>(e / IB, e % IB)] = a[s][q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < IB; ++c) a[s][c] = tid < nr ? stage[stage_slot<IB>(tid, c)] : czero<T>();
+    __syncthreads();
   }
   panel_column<R, IB, S, 0>(a, sh, c0, j0, npad, tid);
 
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int rbase = c0 + 1024 * s;
-    const int nr = npad - rbase < 1024 ? npad - rbase : 1024;
-    if (nr > 0) {
-      if (tid < nr) {
+    const int rbase = c0 + PANEL_NT * s;
 #pragma unroll
-        for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(tid, c)] = a[s][c];
-      }
-      __syncthreads();
-      for (int e = tid; e < nr * IB; e += 1024) {
-        const int row = e / IB, col = e % IB;
-        W[(int64_t)(rbase + row) * ld + c0 + col] = stage[stage_slot<IB>(row, col)];
-      }
-      __syncthreads();
+    for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(tid, c)] = a[s][c];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < IB; ++q) {
+      const int e = tid + PANEL_NT * q;
+      const int rr = PANEL_NT * s + (PANEL_NT / IB) * q;
+      if (c0 + rr + tid / IB < npad)
+        *(T*)((char*)pbase + lane_off + (unsigned)rr * pitch) = stage[stage_slot<IB>(e / IB, e % IB)];
     }
+    __syncthreads();
   }
   if (tid < IB) {
 #pragma unroll
@@ -262,13 +282,13 @@ __global__ __launch_bounds__(1024) void k_panel(cx<R>* __restrict__ Wb, int64_t 
   T* mvbuf = stage;  // [2*IB][NB_MAX]
   const int nleft = c0 - j0, nright = j0 + nbo - c0 - IB, nother = nleft + nright;
   const int cnt = mv_cnt;
-  for (int e = tid; e < cnt * nother; e += 1024) {
+  for (int e = tid; e < cnt * nother; e += PANEL_NT) {
     const int i = e / nother, cc = e % nother;
     const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
     mvbuf[i * NB_MAX + cc] = W[(int64_t)mv_src[i] * ld + col];
   }
   __syncthreads();
-  for (int e = tid; e < cnt * nother; e += 1024) {
+  for (int e = tid; e < cnt * nother; e += PANEL_NT) {
     const int i = e / nother, cc = e % nother;
     const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
     W[(int64_t)mv_dst[i] * ld + col] = mvbuf[i * NB_MAX + cc];
