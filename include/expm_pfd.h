@@ -70,8 +70,14 @@ extern "C" {
 
 typedef struct expm_pfd_opts {
   int precision;   /* EXPM_PFD_FP64 (default) or EXPM_PFD_MIXED */
-  int ir_sweeps;   /* MIXED: refinement sweeps per solve; <= 0 selects the default (2) */
-  int reserved[6]; /* set to 0 */
+  int ir_sweeps;   /* MIXED: refinement sweeps per solve; <= 0 selects the default
+                      (2, or 3 for degree >= 32) */
+  int ir_extended; /* MIXED: how many of the last sweeps accumulate the residual
+                      V - (tA + theta I) X in double-double (error-free products and
+                      sums; needed when the shifted matrices are ill conditioned,
+                      e.g. degree 32 with spectra of width 4e4).  0: automatic (one
+                      such sweep for degree >= 32, none below); < 0: none */
+  int reserved[5]; /* set to 0 */
 } expm_pfd_opts;
 
 /* ---- constants (host only) ---------------------------------------------- */

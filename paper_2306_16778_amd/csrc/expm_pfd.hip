@@ -257,6 +257,7 @@ inline int grid_for(int64_t count) {
 struct expm_pfd_plan_s {
   int64_t n = 0, npad = 0, m_max = 0;  // n, m_max: the single-problem arguments
   int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
+  int ir_ext = 0;  // last sweeps with double-double residuals
   int Gcap = 1;  // problems the workspace was sized for; G <= Gcap is the active count
   double t = 1;
   bool full_ok = false;
@@ -336,7 +337,7 @@ int sweep_fault(expm_pfd_plan_t p) {
 }
 
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps) {
+                int ir_sweeps, int ir_extended) {
   auto* pl = new expm_pfd_plan_s();
   pl->G = G;
   pl->Gcap = G;
@@ -344,7 +345,9 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   pl->P = degree / 2;
   pl->PB = G * pl->P;
   pl->precision = precision;
-  pl->ir_sweeps = ir_sweeps > 0 ? ir_sweeps : 2;
+  // degree >= 32: one more sweep, the last with a double-double residual
+  pl->ir_sweeps = ir_sweeps > 0 ? ir_sweeps : degree >= 32 ? 3 : 2;
+  pl->ir_ext = std::min(pl->ir_sweeps, ir_extended < 0 ? 0 : ir_extended > 0 ? ir_extended : degree >= 32 ? 1 : 0);
   pl->full_ok = full_ok;
   pl->mp_max = mp_max;
   const Sizes sz = plan_sizes(npad, G, degree, mp_max, full_ok, precision);
@@ -610,6 +613,21 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
         hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, PB, P,
                            descs, one);
       }
+      if (it >= pl->ir_sweeps - pl->ir_ext) {
+        // the last sweeps: residual accumulated in double-double
+        {
+          trace::Scope ts(st, EXPM_PFD_K_IR_GEMM, 8.0 * (double)npad * npad * ldS,
+                          e64 * ((double)G * npad * npad + 3.0 * count) + 8.0 * count);
+          hipLaunchKernelGGL(k_residual_dd, dim3((unsigned)(npad / 64), (unsigned)(ldS / 16)), dim3(256), 0, st,
+                             pl->Ah, nn, pl->X64, pl->R64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
+        }
+        solves<float>(pl, Xs, ldS, mp, !full, st);
+        {
+          trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
+          hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
+        }
+        continue;
+      }
       // up to 64 right-hand-side columns per pole: the product in K slices
       // (partials in Rpart, too few output tiles otherwise); wider blocks and
       // V = I: subtracted from R64 directly
@@ -696,7 +714,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
   expm_pfd_plan_t pl = nullptr;
   int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64,
-                       opts ? opts->ir_sweeps : 0);
+                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0);
   if (rc) return rc;
   pl->n = n;
   pl->t = t;
@@ -774,7 +792,8 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
     const bool full = mpk == 0;
     const int G = (int)idx.size();
     expm_pfd_plan_t pl = nullptr;
-    rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0);
+    rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0,
+                     opts ? opts->ir_extended : 0);
     if (rc) break;
     std::vector<ProblemDesc> hd(G);
     int nmax = 0, mmax = 0;
@@ -846,7 +865,7 @@ struct expm_pfd_queue_s {
   std::thread worker;
   bool stop = false;
   size_t budget = 0, mat_bytes = 0, flight_bytes = 0, cached_bytes = 0, peak = 0;
-  int degree = 16, precision = EXPM_PFD_FP64, ir = 0, max_group = 64, device = 0;
+  int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
   std::vector<double> lat_ms;
@@ -946,7 +965,7 @@ struct expm_pfd_queue_s {
       cached_bytes -= bytes;
     } else {
       release_cached(bytes);
-      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir) != 0) {
+      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext) != 0) {
         (void)hipGetLastError();
         return false;
       }
@@ -1030,6 +1049,7 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   q->degree = degree;
   q->precision = opts ? opts->precision : EXPM_PFD_FP64;
   q->ir = opts ? opts->ir_sweeps : 0;
+  q->ir_ext = opts ? opts->ir_extended : 0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;

@@ -1080,6 +1080,89 @@ __global__ __launch_bounds__(256) void k_residual32(const double2* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Refinement residual with double-double accumulation (two FP64 words, error-
+// free products by FMA and error-free sums):
+//   out = fl32( V - (t A) X - shift_b X )
+// for every 16-column group of the npad x ldS right-hand-side array.  V is the
+// staged right-hand side (Rv), Ah the FP64 t*A of the group's problem
+// (row-major, problem g at Ah + g*nn), shift as in k_residual32.  The error of
+// the accumulated sum is of order u^2 * sum |terms| instead of u * sum |terms|,
+// so refinement converges past the FP64 residual's limit when the shifted
+// matrices are ill conditioned.
+// grid (npad/64, ldS/16), block 256: thread (tx, ty) = (tid % 16, tid / 16)
+// owns rows r0 + ty + 16a (a = 0..3) of column c0 + tx.
+// ---------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+// s += a*b exactly up to the final rounding of (hi, lo)
+__device__ __forceinline__ void dd_fma(DD& s, double a, double b) {
+  const double p = a * b;
+  const double e = fma(a, b, -p);
+  const double t = s.hi + p;
+  const double bp = t - s.hi;
+  const double err = (s.hi - (t - bp)) + (p - bp);
+  s.hi = t;
+  s.lo += err + e;
+}
+
+__global__ __launch_bounds__(256) void k_residual_dd(const double2* __restrict__ Ah, int64_t nn,
+                                                     const double2* __restrict__ X, const double2* __restrict__ Rv,
+                                                     int64_t ldS, int npad, int mp, int GP, int P,
+                                                     const double2* __restrict__ theta, float2* __restrict__ out) {
+  constexpr int KC = 16;
+  __shared__ double2 As[64][KC + 1];
+  __shared__ double2 Xs[KC][16];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int r0 = blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * 16;
+  const int blk = (int)(c0 / mp);
+  const int g = (blk % GP) / P;
+  const double2* A = Ah + (int64_t)g * nn;
+  DD re[4], im[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) re[a] = im[a] = DD{0.0, 0.0};
+  for (int k0 = 0; k0 < npad; k0 += KC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, i = e / KC, k = e % KC;
+      As[i][k] = A[(int64_t)(r0 + i) * npad + k0 + k];
+    }
+    Xs[ty][tx] = X[(int64_t)(k0 + ty) * ldS + c0 + tx];
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < KC; ++k) {
+      const double2 x = Xs[k][tx];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double2 av = As[ty + 16 * a][k];
+        dd_fma(re[a], av.x, x.x);
+        dd_fma(re[a], -av.y, x.y);
+        dd_fma(im[a], av.x, x.y);
+        dd_fma(im[a], av.y, x.x);
+      }
+    }
+    __syncthreads();
+  }
+  double2 th = theta[(blk % GP) % P];
+  if (blk >= GP) th.y = -th.y;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t e = (int64_t)(r0 + ty + 16 * a) * ldS + c0 + tx;
+    const double2 x = X[e];
+    dd_fma(re[a], th.x, x.x);
+    dd_fma(re[a], -th.y, x.y);
+    dd_fma(im[a], th.x, x.y);
+    dd_fma(im[a], th.y, x.x);
+    const double2 v = Rv[e];
+    float2 o;
+    o.x = (float)((v.x - re[a].hi) - re[a].lo);
+    o.y = (float)((v.y - im[a].hi) - im[a].lo);
+    out[e] = o;
+  }
+}
+
 // Rres -= shift_b * X for block b: primal blocks (b < GP) theta of pair b mod P,
 // adjoint blocks its conjugate.
 __global__ __launch_bounds__(256) void k_shift_sub(double2* __restrict__ Rres, const double2* __restrict__ X,

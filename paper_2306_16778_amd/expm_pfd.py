@@ -66,7 +66,8 @@ class _QueueStats(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+    _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("ir_extended", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 _lib = None
@@ -115,11 +116,12 @@ def _check(code: int, where: str):
         raise ExpmPfdError(code, where)
 
 
-def _opts(precision, ir_sweeps) -> _Opts:
+def _opts(precision, ir_sweeps, ir_extended=0) -> _Opts:
     p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
     o = _Opts()
     o.precision = int(p)
     o.ir_sweeps = int(ir_sweeps)
+    o.ir_extended = int(ir_extended)
     return o
 
 
@@ -160,10 +162,11 @@ class Plan:
             pass
 
 
-def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0) -> Plan:
+def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0,
+                  ir_extended: int = 0) -> Plan:
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps)
+    o = _opts(precision, ir_sweeps, ir_extended)
     _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
            "expm_pfd_plan")
     return Plan(h.value, n, degree, t, m_max, precision)
