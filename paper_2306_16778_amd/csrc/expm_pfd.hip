@@ -396,6 +396,64 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
 }
 
 // ---- factorization of all shifted matrices of the group --------------------------
+// Panel phase of outer step `step` (columns [j0, j0+nbo)): the inner register
+// panels and the updates inside the outer panel.
+template <typename R>
+void panel_phase(expm_pfd_plan_t pl, int step, hipStream_t st) {
+  const int PB = pl->PB, npad = (int)pl->npad, IB = pl->IB;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  cx<R>* W = (cx<R>*)pl->W;
+  const int j0 = step * NB, nbo = std::min(NB, npad - j0);
+  for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
+    PanelArgs g;
+    g.ws = ws;
+    g.ld = ld;
+    g.ps = npad;
+    g.ms = mstride;
+    g.P = PB;
+    g.npad = npad;
+    g.j0 = j0;
+    g.c0 = c0;
+    g.nbo = nbo;
+    g.step = step;
+    g.last = (c0 + IB >= j0 + nbo);
+    g.ipiv = pl->ipiv;
+    g.moves = pl->moves;
+    panel<R>(st, IB, (npad - c0 + PANEL_NT - 1) / PANEL_NT, g, W);
+    const int rest = j0 + nbo - c0 - IB;
+    if (rest > 0) {
+      const int64_t r1 = c0 + IB;
+      gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, npad - c0 - IB, rest, IB, opnd<R>(W + r1 * ld + c0, ws, ld, false),
+                 opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)c0 * ld + r1, ws, ld, W + r1 * ld + r1, ws, ld);
+    }
+  }
+}
+
+// After the panel phase of `step`: its interchanges on the other columns, the
+// L11 inverse, U12 = L11^{-1} A12 and the trailing update A22 -= L21 U12.
+template <typename R>
+void step_update(expm_pfd_plan_t pl, int step, hipStream_t st) {
+  const int PB = pl->PB, npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  cx<R>* W = (cx<R>*)pl->W;
+  cx<R>* dinv = (cx<R>*)pl->dinv;
+  const int j0 = step * NB, nbo = std::min(NB, npad - j0);
+  const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
+  const int ntr = npad - j0 - nbo;
+  moves_apply<R>(st, PB, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
+  if (ntr <= 0) return;
+  const int64_t c1 = j0 + nbo;
+  block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
+  const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
+  gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
+             PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
+  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+             opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
+}
+
 template <typename R>
 void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, hipStream_t st) {
   const int P = pl->P, PB = pl->PB;
@@ -409,55 +467,18 @@ void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one
                         (pl->Ah ? (double)pl->G * npad * npad * 16 : 0.0));
     hipLaunchKernelGGL((k_form<R>), g, b, 0, st, descs, one, npad, pl->d_theta, P, W, ws, ld, pl->Ah, (int64_t)npad);
   }
-  const int IB = pl->IB;
   cx<R>* dinv = (cx<R>*)pl->dinv;
   const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
-  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
-  int step = 0;
-  for (int j0 = 0; j0 < npad; j0 += NB, ++step) {
-    const int nbo = std::min(NB, npad - j0);
-    for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
-      PanelArgs g;
-      g.ws = ws;
-      g.ld = ld;
-      g.ps = npad;
-      g.ms = mstride;
-      g.P = PB;
-      g.npad = npad;
-      g.j0 = j0;
-      g.c0 = c0;
-      g.nbo = nbo;
-      g.step = step;
-      g.last = (c0 + IB >= j0 + nbo);
-      g.ipiv = pl->ipiv;
-      g.moves = pl->moves;
-      panel<R>(st, IB, (npad - c0 + PANEL_NT - 1) / PANEL_NT, g, W);
-      const int rest = j0 + nbo - c0 - IB;
-      if (rest > 0) {
-        const int64_t r1 = c0 + IB;
-        gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, npad - c0 - IB, rest, IB, opnd<R>(W + r1 * ld + c0, ws, ld, false),
-                   opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)c0 * ld + r1, ws, ld, W + r1 * ld + r1, ws, ld);
-      }
-    }
-    const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
-    const int ntr = npad - j0 - nbo;
-    // the step's interchanges on the columns left and right of the panel
-    moves_apply<R>(st, PB, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
-    if (ntr > 0) {
-      const int64_t c1 = j0 + nbo;
-      block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
-      const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
-      // U12 = L11^{-1} A12 (in place), then A22 -= L21 U12
-      gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false),
-                 opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws,
-                 ld);
-      gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
-                 opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
-    }
+  const int nsteps = pl->nsteps;
+  // (overlapping the panels of step j+1 with the update of step j on two streams,
+  // with or without CUs kept free for the panels, measured slower on gfx950)
+  for (int step = 0; step < nsteps; ++step) {
+    panel_phase<R>(pl, step, st);
+    step_update<R>(pl, step, st);
   }
   // diagonal-block inverses still missing for the sweeps: every U11, the last L11
-  block_inverse<R>(st, PB, W, ws, ld, 0, pl->nsteps, 1, dinv, ds);
-  block_inverse<R>(st, PB, W, ws, ld, pl->nsteps - 1, 1, 0, dinv, ds);
+  block_inverse<R>(st, PB, W, ws, ld, 0, nsteps, 1, dinv, ds);
+  block_inverse<R>(st, PB, W, ws, ld, nsteps - 1, 1, 0, dinv, ds);
 }
 
 // ---- solves on all right-hand-side blocks ----------------------------------------
