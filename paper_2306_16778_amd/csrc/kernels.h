@@ -342,9 +342,14 @@ __global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ 
   const T* W = Wb + b * wstride;
   const int j0 = step * NB;
   const int lane = threadIdx.x;
-  for (int e = lane; e < NB * NB; e += 64) {
-    const int i = e / NB, k = e % NB;
-    D[i][k] = W[(int64_t)(j0 + i) * ld + j0 + k];
+  // the 64 x 64 diagonal block into LDS, 16 loads in flight per lane at a time
+  // (lane = column, so each load instruction reads one row segment)
+  for (int i0 = 0; i0 < NB; i0 += 16) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = W[(int64_t)(j0 + i0 + u) * ld + j0 + lane];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) D[i0 + u][lane] = v[u];
   }
   __syncthreads();
   if (upper) rdiag[lane] = crecip(D[lane][lane]);
