@@ -196,6 +196,23 @@ __device__ __forceinline__ T lane_bcast2(T v, int k) {
   return r;
 }
 
+// ---- device-coherent 16-byte accesses ------------------------------------------
+// Raw buffer resource over [p, p + bytes): loads past the end return zero and
+// stores past it are dropped.  Accesses with the SC1 cache policy are coherent
+// across the device's CUs and XCDs without cache-wide maintenance (the same
+// policy the compiler gives relaxed agent-scope atomics).
+typedef unsigned int u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+constexpr int CPOL_SC1 = 16;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ u32x4 coherent_load16(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, CPOL_SC1);
+}
+__device__ __forceinline__ void coherent_store16(u32x4 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, CPOL_SC1);
+}
+
 // ---- problem descriptors ----------------------------------------------------
 // One exp(t A) V problem as the caller laid it out (column-major, FP64 complex).
 struct ProblemDesc {

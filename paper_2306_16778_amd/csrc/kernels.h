@@ -612,33 +612,6 @@ struct SweepOperand {
 constexpr int SWEEP_SPIN_CAP = 1 << 20;
 constexpr int FLAG_STRIDE = 32;  // one 128-byte line per ready flag
 
-// Complex loads and stores made coherent across the device per access
-// (relaxed agent-scope atomics: no cache-wide maintenance instructions).
-__device__ __forceinline__ float2 coherent_load(const float2* p) {
-  const unsigned long long v =
-      __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  float2 r;
-  r.x = __uint_as_float((unsigned)v);
-  r.y = __uint_as_float((unsigned)(v >> 32));
-  return r;
-}
-__device__ __forceinline__ double2 coherent_load(const double2* p) {
-  unsigned long long* q = (unsigned long long*)p;
-  double2 r;
-  r.x = __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  r.y = __longlong_as_double((long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  return r;
-}
-__device__ __forceinline__ void coherent_store(float2* p, float2 v) {
-  const unsigned long long u = (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
-  __hip_atomic_store((unsigned long long*)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void coherent_store(double2* p, double2 v) {
-  unsigned long long* q = (unsigned long long*)p;
-  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // eight consecutive complex values from a 16-byte aligned address
 template <typename T>
 __device__ __forceinline__ void load8(const T* p, T* a) {
@@ -701,19 +674,6 @@ __device__ __forceinline__ void load_chunk(const cx<R>* p, int64_t ld, int row0,
   }
 }
 
-// Eight elements of x (rows 32h + k8 + u, column r16) read with per-access
-// coherent loads: x was written by another workgroup of the same launch
-template <typename R>
-__device__ __forceinline__ void load_x_chunk(const cx<R>* x, int64_t ldx, int k8, cx<R>* bv) {
-  using T = cx<R>;
-  const int lane = threadIdx.x & 63;
-  const int r16 = lane & 15, h = (lane >> 4) >> 1;
-  const unsigned e = sizeof(T), ldxe = (unsigned)ldx * e;
-  const char* xb = (const char*)x + (32u * h + k8) * ldxe + (unsigned)r16 * e;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) bv[u] = coherent_load((const T*)(xb + u * ldxe));
-}
-
 // Wait until the chain's flag for block J carries this launch's epoch (one
 // wave polls, then the workgroup is released by a barrier).  Capped; a failed
 // wait anywhere ends every later wait at once.
@@ -734,40 +694,115 @@ __device__ __forceinline__ void chain_wait(const int* flag, int epoch, int* stat
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// acc = sum over the blocks J before I in sweep order of A_IJ x_J.  FP32
-// slices are loaded before each wait (their loads overlap it); FP64 slices are
-// loaded chunk by chunk after it, which keeps the registers for three
-// workgroups per CU.
+// x_J (64 rows x 16 columns at x, row pitch ldx) into LDS with coherent 16-byte
+// loads, one pass over the block by the whole workgroup (256 threads)
+template <typename R>
+__device__ __forceinline__ void chain_fill(const cx<R>* x, int64_t ldx, cx<R> (*Xs)[17]) {
+  using T = cx<R>;
+  constexpr int PER_ROW = 16 * sizeof(T) / 16;  // 16-byte pieces per row
+  constexpr int PIECES = 64 * PER_ROW / 256;    // per thread
+  const unsigned pitch = (unsigned)ldx * sizeof(T);
+  const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(x, 64u * pitch);
+  const int tid = threadIdx.x;
+  u32x4 v[PIECES];
+#pragma unroll
+  for (int q = 0; q < PIECES; ++q) {
+    const int id = tid + 256 * q, row = id / PER_ROW, seg = id % PER_ROW;
+    v[q] = coherent_load16(rs, (unsigned)row * pitch + (unsigned)seg * 16u);
+  }
+#pragma unroll
+  for (int q = 0; q < PIECES; ++q) {
+    const int id = tid + 256 * q, row = id / PER_ROW, seg = id % PER_ROW;
+    if constexpr (sizeof(T) == 8) {
+      T p0, p1;
+      p0.x = __uint_as_float(v[q][0]);
+      p0.y = __uint_as_float(v[q][1]);
+      p1.x = __uint_as_float(v[q][2]);
+      p1.y = __uint_as_float(v[q][3]);
+      Xs[row][2 * seg] = p0;
+      Xs[row][2 * seg + 1] = p1;
+    } else {
+      T p0;
+      p0.x = __longlong_as_double(((long long)v[q][1] << 32) | v[q][0]);
+      p0.y = __longlong_as_double(((long long)v[q][3] << 32) | v[q][2]);
+      Xs[row][seg] = p0;
+    }
+  }
+}
+
+// The 64 x 16 block in Xs to x (row pitch ldx) with coherent 16-byte stores
+template <typename R>
+__device__ __forceinline__ void chain_publish(cx<R> (*Xs)[17], cx<R>* x, int64_t ldx) {
+  using T = cx<R>;
+  constexpr int PER_ROW = 16 * sizeof(T) / 16;
+  constexpr int PIECES = 64 * PER_ROW / 256;
+  const unsigned pitch = (unsigned)ldx * sizeof(T);
+  const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(x, 64u * pitch);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PIECES; ++q) {
+    const int id = tid + 256 * q, row = id / PER_ROW, seg = id % PER_ROW;
+    u32x4 v;
+    if constexpr (sizeof(T) == 8) {
+      const T p0 = Xs[row][2 * seg], p1 = Xs[row][2 * seg + 1];
+      v[0] = __float_as_uint(p0.x);
+      v[1] = __float_as_uint(p0.y);
+      v[2] = __float_as_uint(p1.x);
+      v[3] = __float_as_uint(p1.y);
+    } else {
+      const T p0 = Xs[row][seg];
+      const unsigned long long a = (unsigned long long)__double_as_longlong(p0.x);
+      const unsigned long long c = (unsigned long long)__double_as_longlong(p0.y);
+      v[0] = (unsigned)a;
+      v[1] = (unsigned)(a >> 32);
+      v[2] = (unsigned)c;
+      v[3] = (unsigned)(c >> 32);
+    }
+    coherent_store16(v, rs, (unsigned)row * pitch + (unsigned)seg * 16u);
+  }
+}
+
+// acc = sum over the blocks J before I in sweep order of A_IJ x_J.  x_J is
+// brought into LDS once per workgroup after its flag is seen.  FP32 slices are
+// loaded before each wait (their loads overlap it); FP64 slices chunk by chunk
+// after it, which keeps the registers for three workgroups per CU.
 template <typename R, bool CONJ>
 __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nsteps, const cx<R>* W, int64_t ld,
                                                  const cx<R>* Xc, int64_t ldx, int row0, const int* fl, int epoch,
-                                                 int* status, typename Mfma<R>::V& accR,
+                                                 int* status, cx<R> (*Xs)[17], typename Mfma<R>::V& accR,
                                                  typename Mfma<R>::V& accI) {
   using T = cx<R>;
   constexpr int NB = NB_MAX;
-  const bool odd = (threadIdx.x >> 4) & 1;
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, h = (lane >> 4) >> 1;
+  const bool odd = (lane >> 4) & 1;
   for (int qq = 0; qq < q; ++qq) {
     const int J = fwd ? qq : nsteps - 1 - qq;
     const T* Ablk = CONJ ? W + (int64_t)(J * NB) * ld + I * NB : W + (int64_t)(I * NB) * ld + J * NB;
-    const T* xJ = Xc + (int64_t)(J * NB) * ldx;
     if constexpr (sizeof(R) == 4) {
       T a[32];
 #pragma unroll
       for (int k8 = 0; k8 < 32; k8 += 8) load_chunk<R, CONJ>(Ablk, ld, row0, k8, a + k8);
       chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      chain_fill<R>(Xc + (int64_t)(J * NB) * ldx, ldx, Xs);
+      __syncthreads();
 #pragma unroll
       for (int k8 = 0; k8 < 32; k8 += 8) {
         T bv[8];
-        load_x_chunk<R>(xJ, ldx, k8, bv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = Xs[32 * h + k8 + u][r16];
         mac8<R>(a + k8, bv, odd, accR, accI);
       }
     } else {
       chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      chain_fill<R>(Xc + (int64_t)(J * NB) * ldx, ldx, Xs);
+      __syncthreads();
 #pragma unroll
       for (int k8 = 0; k8 < 32; k8 += 8) {
         T a[8], bv[8];
         load_chunk<R, CONJ>(Ablk, ld, row0, k8, a);
-        load_x_chunk<R>(xJ, ldx, k8, bv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = Xs[32 * h + k8 + u][r16];
         mac8<R>(a, bv, odd, accR, accI);
       }
     }
@@ -790,6 +825,7 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
   constexpr bool DS_LDS = sizeof(R) == 4;  // FP32: D_I staged in LDS ahead of use
   __shared__ T Ds[DS_LDS ? NB : 1][NB + 1];
   __shared__ T Rs[NB][17];
+  __shared__ T Xs[NB][17];  // x_J of the current dependency; finally x_I
   __shared__ unsigned s_ticket;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
@@ -825,9 +861,9 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
   for (int r = 0; r < 4; ++r) b[r] = Xc[(int64_t)(I * NB + row0 + MF::row(kq, r)) * ldx + r16];
   V accR = V{0, 0, 0, 0}, accI = V{0, 0, 0, 0};
   if (aop.conj)
-    chain_accumulate<R, true>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, accR, accI);
+    chain_accumulate<R, true>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR, accI);
   else
-    chain_accumulate<R, false>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, accR, accI);
+    chain_accumulate<R, false>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR, accI);
   // r = b_I - acc, shared by the four waves for the diagonal-block product
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -862,8 +898,10 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
     T v;
     v.x = xR[r];
     v.y = xI[r];
-    coherent_store(Xc + (int64_t)(I * NB + row0 + MF::row(kq, r)) * ldx + r16, v);
+    Xs[row0 + MF::row(kq, r)][r16] = v;  // Xs is free: its last reads preceded the Rs barrier
   }
+  __syncthreads();
+  chain_publish<R>(Xs, Xc + (int64_t)(I * NB) * ldx, ldx);
   // publish x_I: every wave's stores have completed before the flag is set
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
