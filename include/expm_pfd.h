@@ -78,6 +78,12 @@ typedef struct expm_pfd_opts {
                       e.g. degree 32 with spectra of width 4e4).  0: automatic (one
                       such sweep for degree >= 32, none below); < 0: none */
   int reserved[5]; /* set to 0 */
+  double shift;    /* c of the shifting method (Remark rem:shift): the library
+                      computes e^c R_d(tA - cI) V, so spectra of tA up to c are
+                      covered by the negative-spectrum error bound of the
+                      Theorem of Sec. 3 (relative error controlled when c bounds
+                      the spectrum).  Default 0; e^c must be finite (c < 709),
+                      otherwise EXPM_PFD_ERR_ARG. */
 } expm_pfd_opts;
 
 /* ---- constants (host only) ---------------------------------------------- */

@@ -70,6 +70,18 @@ def expm_R(A, V, t: float, d: int, eig=None):
     return _apply_spectral(U, r, V)
 
 
+def expm_R_shifted(A, V, t: float, d: int, c: float, eig=None):
+    """e^c R_d(tA - cI) V, the shifting method of Remark rem:shift, by
+    eigendecomposition: r_i = e^c / exp_d(-(t w_i - c)) by Horner.  With c at or
+    above the largest eigenvalue of tA every argument is <= 0, where the error
+    bounds of Sec. 2.3 hold, and the relative error against exp(tA) is at most
+    e^{c - alpha} max_{x <= 0} |R_d(x) - e^x| (alpha the largest eigenvalue)."""
+    scalar.check_degree(d)
+    w, U = eig if eig is not None else _eig(A)
+    r = np.exp(c) * scalar.R_direct(t * w - c, d)
+    return _apply_spectral(U, r, V)
+
+
 def expm_exact(A, V, t: float, eig=None):
     """exp(tA) V = U diag(e^{t w_i}) U^H V (reported beside parity, never gated)."""
     w, U = eig if eig is not None else _eig(A)

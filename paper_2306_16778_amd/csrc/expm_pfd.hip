@@ -316,6 +316,7 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
 int check_opts(const expm_pfd_opts* o) {
   if (!o) return 0;
   if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
+  if (!std::isfinite(o->shift) || !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
   return 0;
 }
 
@@ -337,7 +338,7 @@ int sweep_fault(expm_pfd_plan_t p) {
 }
 
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps, int ir_extended) {
+                int ir_sweeps, int ir_extended, double shift) {
   auto* pl = new expm_pfd_plan_s();
   pl->G = G;
   pl->Gcap = G;
@@ -361,6 +362,15 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   if (rc) {
     delete pl;
     return rc;
+  }
+  // shifting method: e^c R_d(tA - cI) = sum_k (e^c a_k) (tA + (theta_k - c) I)^{-1}
+  if (shift != 0.0) {
+    const double ec = std::exp(shift);
+    for (int k = 0; k < pl->P; ++k) {
+      pl->h_theta[k].x -= shift;
+      pl->h_a[k].x *= ec;
+      pl->h_a[k].y *= ec;
+    }
   }
   (void)hipGetDevice(&pl->device);
   HipErr he;
@@ -735,7 +745,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
   expm_pfd_plan_t pl = nullptr;
   int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64,
-                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0);
+                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0);
   if (rc) return rc;
   pl->n = n;
   pl->t = t;
@@ -814,7 +824,7 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
     const int G = (int)idx.size();
     expm_pfd_plan_t pl = nullptr;
     rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0,
-                     opts ? opts->ir_extended : 0);
+                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0);
     if (rc) break;
     std::vector<ProblemDesc> hd(G);
     int nmax = 0, mmax = 0;
@@ -887,6 +897,7 @@ struct expm_pfd_queue_s {
   bool stop = false;
   size_t budget = 0, mat_bytes = 0, flight_bytes = 0, cached_bytes = 0, peak = 0;
   int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
+  double shift = 0.0;
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
   std::vector<double> lat_ms;
@@ -986,7 +997,7 @@ struct expm_pfd_queue_s {
       cached_bytes -= bytes;
     } else {
       release_cached(bytes);
-      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext) != 0) {
+      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift) != 0) {
         (void)hipGetLastError();
         return false;
       }
@@ -1071,6 +1082,7 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   q->precision = opts ? opts->precision : EXPM_PFD_FP64;
   q->ir = opts ? opts->ir_sweeps : 0;
   q->ir_ext = opts ? opts->ir_extended : 0;
+  q->shift = opts ? opts->shift : 0.0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;

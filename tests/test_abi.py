@@ -66,6 +66,12 @@ def test_argument_validation_without_device():
     assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, float("nan"), 0, ctypes.byref(o)) == -7
     o.precision = 7
     assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+    o.precision = 0
+    o.shift = 800.0  # e^c overflows
+    assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+    o.shift = float("nan")
+    assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+    o.shift = 0.0
     assert lib.expm_pfd_plan(None, 10, 16, 1.0, 0, None) == -3
     assert lib.expm_pfd_apply(None, None, 1, None, 1, 1, None, 1, None) == -3
     assert lib.expm_pfd_destroy(None) == -3

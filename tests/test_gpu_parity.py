@@ -42,11 +42,11 @@ def _dev(x):
     return torch.from_numpy(np.asfortranarray(x)).to("cuda")
 
 
-def _run(ep, A, V, t, d, precision="fp64", m_max=None):
+def _run(ep, A, V, t, d, precision="fp64", m_max=None, shift=0.0):
     import torch
     n = A.shape[0]
     mm = 0 if V is None else (V.shape[1] if m_max is None else m_max)
-    plan = ep.expm_pfd_plan(n, d, t, mm, precision)
+    plan = ep.expm_pfd_plan(n, d, t, mm, precision, shift=shift)
     X = ep.expm_pfd_apply(plan, _dev(A), None if V is None else _dev(V))
     torch.cuda.synchronize()
     ep.expm_pfd_plan_check(plan)  # every one-launch sweep kept its dependency order
@@ -210,3 +210,23 @@ def test_config3_precision_study(ep):
     print(f"[config3] rel err mixed {em:.3e} fp64 {e64:.3e}", file=sys.stderr, flush=True)
     assert em < TOLMX
     assert e64 < 1e-8
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOLMX)])
+def test_shifted_positive_spectrum(ep, precision, tol):
+    """Shifting method (Remark rem:shift): spectrum in [0, 30], c = 30, so the library
+    computes e^30 R_16(tA - 30 I) V; parity against the oracle's e^c R_d(tA - cI) V,
+    and the relative error against exp(tA)V stays within the negative-spectrum bound."""
+    A, V, t = _problem(300, 0.0, 30.0, 8, 4242)
+    c = 30.0
+    _announce(f"shift {precision} n=300 m=8 d=16 c={c}")
+    X = _run(ep, A, V, t, 16, precision, shift=c)
+    Y = matrix.expm_R_shifted(A, V, t, 16, c)
+    assert matrix.rel_fro(X, Y) < tol
+    E = matrix.expm_exact(A, V, t)
+    assert matrix.rel_fro(X, E) < 1e-5
+    # V = I with a negative shift (c below the spectrum is allowed; bounds then weaker)
+    B, _, _ = _problem(100, -10.0, 0.0, None, 4243)
+    _announce(f"shift {precision} n=100 V=I d=16 c=-2")
+    XB = _run(ep, B, None, 1.0, 16, precision, shift=-2.0)
+    assert matrix.rel_fro(XB, matrix.expm_R_shifted(B, None, 1.0, 16, -2.0)) < tol

@@ -143,3 +143,33 @@ def test_approximation_error_is_tiny_but_nonzero():
     E = matrix.expm_exact(P.A, None, 1.0)
     gap = np.linalg.norm(R - E, 2)
     assert 1e-8 < gap <= max(scalar.err_shape(16, np.linspace(-10, 0, 401)))
+
+
+def test_shifted_oracle_pins():
+    """Shifting method (Remark rem:shift): e^c R_d(tA - cI).
+    - c = 0 is R_d(tA) itself;
+    - a diagonal matrix maps entry-wise to e^c / exp_d(-(t D_ii - c)), written here as
+      the plain power sum of Sec. 2;
+    - for a positive spectrum with c = largest eigenvalue of tA, the relative 2-norm
+      error against exp(tA) is at most max_{x <= 0} |R_d(x) - e^x| <= 2^-d (Prop. pro:err),
+      while the unshifted R_d(tA) is far off there."""
+    A, lam, _ = _herm(30, -20, 0, 21)
+    assert matrix.rel_fro(matrix.expm_R_shifted(A, None, 0.7, 16, 0.0), matrix.expm_R(A, None, 0.7, 16)) == 0.0
+    D = np.diag(np.array([3.0, 0.5, -2.0, 10.0]) + 0j)
+    c = 10.0
+    Y = matrix.expm_R_shifted(D, None, 1.0, 16, c)
+    want = np.array([math.exp(c) / sum((-(x - c)) ** k / math.factorial(k) for k in range(17))
+                     for x in D.diagonal().real])
+    assert np.max(np.abs(Y - np.diag(np.diag(Y)))) == 0
+    assert np.allclose(np.diag(Y).real, want, rtol=1e-14, atol=0)
+    P, lamp, _ = _herm(40, 0, 30, 22)
+    for d in (16, 24):
+        c = float(lamp.max())
+        Ys = matrix.expm_R_shifted(P, None, 1.0, d, c)
+        E = matrix.expm_exact(P, None, 1.0)
+        rel2 = np.linalg.norm(Ys - E, 2) / np.linalg.norm(E, 2)
+        assert rel2 <= 2.0 ** -d
+        # the maximum lies in [-(d+2), -d/2] (Prop. pro:wxcv1); grid step 0.01
+        assert rel2 <= max(scalar.err_shape(d, np.arange(-(d + 2), -d / 2, 0.01))) * (1 + 1e-6)
+        R0 = matrix.expm_R(P, None, 1.0, d)
+        assert np.linalg.norm(R0 - E, 2) / np.linalg.norm(E, 2) > 1e-3
