@@ -44,16 +44,22 @@ KERNEL_SOURCES = ("device_common.h", "kernels.h", "expm_pfd.hip")
 # WRITE_SIZE counter pass, each scaled by what the counter reads for a plain
 # copy kernel of known size (read 0.50005 x, write 1.0 x the true bytes);
 # valid for the kernel sources with this digest only, otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 58.00e6 + 34.64e6, "sources_sha256": "6951b0309335459f102804c881181a1332b46c9aec87eada9feb790652c64097"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 58.01e6 + 34.64e6, "sources_sha256": "5f3ce0dbace2f501f479843cc94f71e57729ff7c9fb1161863cf4e9f9e07708a"}}
 
 
 def kernel_sources_digest():
+    """Digest of the kernels' source and of the launcher that picks the GEMM tiles
+    (the rest of the host code does not change what the kernel reads or writes)."""
     import hashlib
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2306_16778_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f.endswith(".hip"):
+            a = text.index(b"void gemm(")
+            text = text[a:text.index(b"\n}\n", a)]
+        h.update(text)
     return h.hexdigest()
 
 

@@ -18,6 +18,7 @@
 //   matrix-core product with the shared FP64 tA, a FP32 correction solve and an
 //   FP64 update; accumulation in FP64.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -74,20 +75,23 @@ void clear() {
   }
   recs.clear();
 }
-// Brackets one kernel launch with an event pair on its stream.
+// Brackets one kernel launch with an event pair on its stream.  With `in_launch`
+// the pair is handed to the launch itself (hipExtLaunchKernelGGL records it at the
+// kernel's own start and end), so the time excludes the separate event packets.
 struct Scope {
-  bool active;
+  bool active, in_launch;
   hipStream_t s;
   Rec r{};
-  Scope(hipStream_t st, int cls, double flops, double bytes) : active((mask >> cls) & 1u), s(st) {
+  Scope(hipStream_t st, int cls, double flops, double bytes, bool in_launch_ = false)
+      : active((mask >> cls) & 1u), in_launch(in_launch_), s(st) {
     if (active) {
       r = {get_event(), get_event(), cls, flops, bytes};
-      (void)hipEventRecord(r.a, s);
+      if (!in_launch) (void)hipEventRecord(r.a, s);
     }
   }
   ~Scope() {
     if (active) {
-      (void)hipEventRecord(r.b, s);
+      if (!in_launch) (void)hipEventRecord(r.b, s);
       std::lock_guard<std::mutex> lk(mu);
       recs.push_back(r);
     }
@@ -188,17 +192,19 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
   const double e = sizeof(cx<R>);
   const double Kt = (double)K * ksp.ks;
   trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * Kt,
-                  e * batch * ((double)M * Kt + Kt * N + (MODE == 0 ? 2.0 : (double)ksp.ks) * M * N));
+                  e * batch * ((double)M * Kt + Kt * N + (MODE == 0 ? 2.0 : (double)ksp.ks) * M * N), true);
   const unsigned gy = (unsigned)(batch * ksp.ks);
-  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM) {
-    const int tiles = (int)((M + 63) / 64);
-    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 16, 4, 1>), dim3(tiles, gy), dim3(256), 0, st, M, N, K, a0, a1, split, B,
-                       sB, ldb, C, sC, ldc, ksp);
-  } else {
-    const int tiles = (int)(((M + 63) / 64) * ((N + 63) / 64));
-    hipLaunchKernelGGL((k_gemm<R, MODE, 64, 64, 2, 2>), dim3(tiles, gy), dim3(256), 0, st, M, N, K, a0, a1, split, B,
-                       sB, ldb, C, sC, ldc, ksp);
-  }
+  auto launch = [&](auto kernel, dim3 grid) {
+    if (ts.active)
+      hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, st, ts.r.a, ts.r.b, 0, M, N, K, a0, a1, split, B, sB, ldb,
+                            C, sC, ldc, ksp);
+    else
+      hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
+  };
+  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM)
+    launch(k_gemm<R, MODE, 64, 16, 4, 1>, dim3((unsigned)((M + 63) / 64), gy));
+  else
+    launch(k_gemm<R, MODE, 64, 64, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
 }
 
 // K slices of the FP64 refinement product (t A) X for thin right-hand sides: a
