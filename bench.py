@@ -13,7 +13,8 @@ refinement, the reported value) and the plain FP64 path.  The oracle
 (eigendecomposition, FP64, host CPU) is timed once on the same input as the CPU
 baseline and provides the error check of both GPU results.
 
-Also reported (extra fields, not the headline value): the batched entry point on
+Also reported (extra fields, not the headline value): a real symmetric problem of
+the same size with the real-data option, the batched entry point on
 512 Hermitian matrices of orders log-uniform in [32, 512] (V n x 4, degree 16),
 and the queued serving path replaying a Poisson trace of requests with orders
 log-uniform in [64, 4096] (single vectors, 20% matrix reuse, degree 16) on both
@@ -203,6 +204,38 @@ def serving_section(requests, qps, matrix):
     return out
 
 
+def real_section(ep, torch, steps, matrix):
+    """Real symmetric A (n = 2048, spectrum U[-100, 0], real orthogonal eigenvectors)
+    and real V 2048 x 16, degree 24: the real-data option solves one pole per
+    conjugate pair; timed on both paths like the main workload."""
+    import numpy as np
+
+    rng = np.random.default_rng([20230629, 6])
+    n, m = 2048, 16
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(-100.0, 0.0, n)
+    A = (Q * lam) @ Q.T
+    A = (0.5 * (A + A.T)).astype(np.complex128)
+    V = rng.standard_normal((n, m)).astype(np.complex128)
+    Ad = torch.from_numpy(np.asfortranarray(A)).cuda()
+    Vd = torch.from_numpy(np.asfortranarray(V)).cuda()
+    Y = matrix.expm_R(A, V, 1.0, 24) if matrix is not None else None
+    out = {"workload": "real symmetric n=2048, spectrum U[-100,0], real V 2048x16, t=1, degree 24, real_data option"}
+    for prec in ("mixed", "fp64"):
+        plan = ep.expm_pfd_plan(n, 24, 1.0, m, prec, real_data=True)
+        X = torch.empty((m, n), dtype=torch.complex128, device="cuda").t()
+        ep.expm_pfd_apply(plan, Ad, Vd, X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ep.expm_pfd_apply(plan, Ad, Vd, X)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        err = matrix.rel_fro(X.cpu().numpy(), Y) if Y is not None else None
+        out[prec] = {"solves_per_s": 1e3 / ms, "ms_per_step": ms, "rel_err_vs_oracle": err}
+    return out
+
+
 def copy_calibration(torch):
     """A plain elementwise copy (y = 1.0 * x) of 256 MiB, three launches: the HBM
     counters of these launches give the bytes-per-count scale of FETCH_SIZE and
@@ -222,6 +255,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-real", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-qps", type=float, default=100.0)
     ap.add_argument("--paths", default="mixed,fp64", help="precision paths to time (mixed first: the reported value)")
@@ -269,6 +303,11 @@ def main():
         from oracle import matrix
         batched = batched_section(ep, torch, workloads, matrix)
         print("[bench] batched done", file=sys.stderr, flush=True)
+    real = None
+    if not args.no_real:
+        from oracle import matrix as rcheck
+        real = real_section(ep, torch, args.steps, None if args.no_cpu_baseline else rcheck)
+        print("[bench] real-data section done", file=sys.stderr, flush=True)
     served = None
     if args.serving_requests > 0:
         check = None
@@ -308,6 +347,7 @@ def main():
         "breakdown_ms_per_step": mx["breakdown_ms_per_step"],
         "roofline": mx["roofline"],
         "cpu_baseline": cpu,
+        "real_symmetric": real,
         "batched": batched,
         "serving": served,
     }

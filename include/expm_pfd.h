@@ -77,7 +77,11 @@ typedef struct expm_pfd_opts {
                       sums; needed when the shifted matrices are ill conditioned,
                       e.g. degree 32 with spectra of width 4e4).  0: automatic (one
                       such sweep for degree >= 32, none below); < 0: none */
-  int reserved[5]; /* set to 0 */
+  int real_data;   /* nonzero: A and V are real (imaginary parts are not read).
+                      Then the conjugate pole's solution is the conjugate of the
+                      primal one (Remark rem:two_time_real_part): solves and
+                      refinement run for one pole per pair only. */
+  int reserved[4]; /* set to 0 */
   double shift;    /* c of the shifting method (Remark rem:shift): the library
                       computes e^c R_d(tA - cI) V, so spectra of tA up to c are
                       covered by the negative-spectrum error bound of the

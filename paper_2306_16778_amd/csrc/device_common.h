@@ -224,6 +224,7 @@ struct ProblemDesc {
   int64_t ldx;
   double t;
   int n, m;
+  int real;  // 1: A and V are real; their imaginary parts are not read
 };
 // descriptor g of a group: from the device array, or the single inline one
 __device__ __forceinline__ ProblemDesc desc_of(const ProblemDesc* arr, const ProblemDesc& one, int g) {

@@ -264,6 +264,7 @@ struct expm_pfd_plan_s {
   int64_t n = 0, npad = 0, m_max = 0;  // n, m_max: the single-problem arguments
   int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
   int ir_ext = 0;  // last sweeps with double-double residuals
+  int real_data = 0;  // A and V real: conjugate poles need no solves of their own
   int Gcap = 1;  // problems the workspace was sized for; G <= Gcap is the active count
   double t = 1;
   bool full_ok = false;
@@ -344,7 +345,7 @@ int sweep_fault(expm_pfd_plan_t p) {
 }
 
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps, int ir_extended, double shift) {
+                int ir_sweeps, int ir_extended, double shift, int real_data) {
   auto* pl = new expm_pfd_plan_s();
   pl->G = G;
   pl->Gcap = G;
@@ -354,6 +355,7 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   pl->precision = precision;
   // degree >= 32: one more sweep, the last with a double-double residual
   pl->ir_sweeps = ir_sweeps > 0 ? ir_sweeps : degree >= 32 ? 3 : 2;
+  pl->real_data = real_data ? 1 : 0;
   pl->ir_ext = std::min(pl->ir_sweeps, ir_extended < 0 ? 0 : ir_extended > 0 ? ir_extended : degree >= 32 ? 1 : 0);
   pl->full_ok = full_ok;
   pl->mp_max = mp_max;
@@ -602,7 +604,10 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
         hipStream_t st) {
   const int P = pl->P, PB = pl->PB, G = pl->G;
   const int npad = (int)pl->npad;
-  const int nblk = full ? PB : 2 * PB;
+  // adjoint blocks: the conjugate pole's solves (not needed for V = I, where the
+  // conjugate term is the adjoint, nor for real data, where it is the conjugate)
+  const bool adj = !full && !pl->real_data;
+  const int nblk = adj ? 2 * PB : PB;
   const int64_t ldS = (int64_t)nblk * mp;
   const int64_t count = (int64_t)npad * ldS;
   if (ldS > pl->cols_alloc) return EXPM_PFD_ERR_DIM;
@@ -615,7 +620,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
       hipLaunchKernelGGL(k_accum_full, g, b, 0, st, Xsrc, ldS, npad, P, pl->d_a, descs, one);
     } else {
       dim3 g((unsigned)(((int64_t)nmax * mmax + 255) / 256), (unsigned)G);
-      hipLaunchKernelGGL(k_accum_thin, g, dim3(256), 0, st, Xsrc, ldS, mp, PB, P, pl->d_a, descs, one);
+      hipLaunchKernelGGL(k_accum_thin, g, dim3(256), 0, st, Xsrc, ldS, mp, PB, P, pl->d_a, descs, one, adj ? 1 : 0);
     }
   };
   if (pl->precision == EXPM_PFD_FP64) {
@@ -626,7 +631,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
       hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
                          one);
     }
-    solves<double>(pl, Xs, ldS, mp, !full, st);
+    solves<double>(pl, Xs, ldS, mp, adj, st);
     accumulate(Xs);
   } else {
     factor<float>(pl, descs, one, st);
@@ -636,7 +641,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
       hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
                          one);
     }
-    solves<float>(pl, Xs, ldS, mp, !full, st);
+    solves<float>(pl, Xs, ldS, mp, adj, st);
     {
       trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
       hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
@@ -658,7 +663,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
           hipLaunchKernelGGL(k_residual_dd, dim3((unsigned)(npad / 64), (unsigned)(ldS / 16)), dim3(256), 0, st,
                              pl->Ah, nn, pl->X64, pl->R64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
         }
-        solves<float>(pl, Xs, ldS, mp, !full, st);
+        solves<float>(pl, Xs, ldS, mp, adj, st);
         {
           trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
           hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
@@ -672,7 +677,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
       const int S = split ? ir_kslices(npad) : 0;
       const int64_t pstride = (int64_t)npad * ldS;
       if (!split) {
-        for (int half = 0; half < (full ? 1 : 2); ++half) {
+        for (int half = 0; half < (adj ? 2 : 1); ++half) {
           const int64_t off = (int64_t)half * PB * mp;
           gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, G, npad, P * mp, npad, opnd<double>(pl->Ah, nn, npad, false),
                           opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS, pl->R64 + off,
@@ -682,7 +687,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
         const int Ks = npad / S;
         const KSplit ksp{S, Ks, (int64_t)Ks * ldS, pstride};
         // one launch covers both halves when the group holds one problem
-        const int nh = G == 1 ? 1 : 2, ncols = G == 1 ? 2 * P * mp : P * mp;
+        const int nh = (G == 1 || !adj) ? 1 : 2, ncols = (G == 1 && adj) ? 2 * P * mp : P * mp;
         for (int half = 0; half < nh; ++half) {
           const int64_t off = (int64_t)half * PB * mp;
           gemm<double, 1>(st, EXPM_PFD_K_IR_GEMM, G, npad, ncols, Ks, opnd<double>(pl->Ah, nn, npad, false),
@@ -695,7 +700,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
         hipLaunchKernelGGL(k_residual32, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->Rpart, S, pstride,
                            pl->X64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
       }
-      solves<float>(pl, Xs, ldS, mp, !full, st);
+      solves<float>(pl, Xs, ldS, mp, adj, st);
       {
         trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
         hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
@@ -751,7 +756,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
   expm_pfd_plan_t pl = nullptr;
   int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64,
-                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0);
+                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, opts ? opts->real_data : 0);
   if (rc) return rc;
   pl->n = n;
   pl->t = t;
@@ -782,6 +787,7 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   one.t = pl->t;
   one.n = (int)pl->n;
   one.m = (int)m;
+  one.real = pl->real_data;
   (void)hipGetLastError();
   const int mp = full ? (int)pl->npad : (int)round_up(m, 16);
   if (int e = run(pl, nullptr, one, full, mp, (int)pl->n, (int)m, st)) return e;
@@ -830,7 +836,7 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
     const int G = (int)idx.size();
     expm_pfd_plan_t pl = nullptr;
     rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0,
-                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0);
+                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, opts ? opts->real_data : 0);
     if (rc) break;
     std::vector<ProblemDesc> hd(G);
     int nmax = 0, mmax = 0;
@@ -846,6 +852,7 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
       d.t = t[i];
       d.n = (int)n[i];
       d.m = (int)m[i];
+      d.real = opts ? opts->real_data : 0;
       nmax = std::max(nmax, d.n);
       mmax = std::max(mmax, d.m);
     }
@@ -904,6 +911,7 @@ struct expm_pfd_queue_s {
   size_t budget = 0, mat_bytes = 0, flight_bytes = 0, cached_bytes = 0, peak = 0;
   int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
   double shift = 0.0;
+  int real_data = 0;
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
   std::vector<double> lat_ms;
@@ -1003,7 +1011,7 @@ struct expm_pfd_queue_s {
       cached_bytes -= bytes;
     } else {
       release_cached(bytes);
-      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift) != 0) {
+      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift, real_data) != 0) {
         (void)hipGetLastError();
         return false;
       }
@@ -1029,6 +1037,7 @@ struct expm_pfd_queue_s {
       d.t = r.t;
       d.n = (int)mats[r.mat].n;
       d.m = (int)r.m;
+      d.real = real_data;
       nmax = std::max(nmax, d.n);
       mmax = std::max(mmax, d.m);
       f.descs.push_back(d);
@@ -1089,6 +1098,7 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   q->ir = opts ? opts->ir_sweeps : 0;
   q->ir_ext = opts ? opts->ir_extended : 0;
   q->shift = opts ? opts->shift : 0.0;
+  q->real_data = opts ? opts->real_data : 0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;

@@ -41,6 +41,7 @@ __global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ de
     const int r = R0 + threadIdx.x, c = C0 + cc;
     double2 v = czero<double2>();
     if (r < n && c < n) v = A[r + (int64_t)c * lda];
+    if (d.real) v.y = 0;
     tile[cc][threadIdx.x] = v;
   }
   __syncthreads();
@@ -974,6 +975,7 @@ __global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ld
     double2 v = czero<double2>();
     if (d.V) {
       if (i < d.n && j < d.m) v = d.V[i + (int64_t)j * d.ldv];
+      if (d.real) v.y = 0;
     } else if (i == j && i < d.n) {
       v.x = 1;
     }
@@ -993,7 +995,8 @@ __global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ld
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_accum_thin(const double2* __restrict__ Xs, int64_t ldS, int mp, int GP, int P,
                                                     const double2* __restrict__ a,
-                                                    const ProblemDesc* __restrict__ descs, ProblemDesc one) {
+                                                    const ProblemDesc* __restrict__ descs, ProblemDesc one,
+                                                    int adjoint_blocks) {
   const int g = blockIdx.y;
   const ProblemDesc d = desc_of(descs, one, g);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1004,7 +1007,8 @@ __global__ __launch_bounds__(256) void k_accum_thin(const double2* __restrict__ 
   for (int p = 0; p < P; ++p) {
     const double2 ap = a[p];
     const double2 y = row[(g * P + p) * mp + j];
-    const double2 z = row[(GP + g * P + p) * mp + j];
+    // real data: the conjugate pole's solution is the conjugate of the primal one
+    const double2 z = adjoint_blocks ? row[(GP + g * P + p) * mp + j] : cconj(y);
     sr += ap.x * y.x - ap.y * y.y + ap.x * z.x + ap.y * z.y;
     si += ap.x * y.y + ap.y * y.x + ap.x * z.y - ap.y * z.x;
   }

@@ -67,7 +67,7 @@ class _QueueStats(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("ir_extended", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5), ("shift", ctypes.c_double)]
+                ("real_data", ctypes.c_int), ("reserved", ctypes.c_int * 4), ("shift", ctypes.c_double)]
 
 
 _lib = None
@@ -116,13 +116,14 @@ def _check(code: int, where: str):
         raise ExpmPfdError(code, where)
 
 
-def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0) -> _Opts:
+def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False) -> _Opts:
     p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
     o = _Opts()
     o.precision = int(p)
     o.ir_sweeps = int(ir_sweeps)
     o.ir_extended = int(ir_extended)
     o.shift = float(shift)
+    o.real_data = 1 if real_data else 0
     return o
 
 
@@ -164,10 +165,10 @@ class Plan:
 
 
 def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0,
-                  ir_extended: int = 0, shift: float = 0.0) -> Plan:
+                  ir_extended: int = 0, shift: float = 0.0, real_data: bool = False) -> Plan:
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data)
     _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
            "expm_pfd_plan")
     return Plan(h.value, n, degree, t, m_max, precision)

@@ -42,11 +42,11 @@ def _dev(x):
     return torch.from_numpy(np.asfortranarray(x)).to("cuda")
 
 
-def _run(ep, A, V, t, d, precision="fp64", m_max=None, shift=0.0):
+def _run(ep, A, V, t, d, precision="fp64", m_max=None, shift=0.0, real_data=False):
     import torch
     n = A.shape[0]
     mm = 0 if V is None else (V.shape[1] if m_max is None else m_max)
-    plan = ep.expm_pfd_plan(n, d, t, mm, precision, shift=shift)
+    plan = ep.expm_pfd_plan(n, d, t, mm, precision, shift=shift, real_data=real_data)
     X = ep.expm_pfd_apply(plan, _dev(A), None if V is None else _dev(V))
     torch.cuda.synchronize()
     ep.expm_pfd_plan_check(plan)  # every one-launch sweep kept its dependency order
@@ -230,3 +230,31 @@ def test_shifted_positive_spectrum(ep, precision, tol):
     _announce(f"shift {precision} n=100 V=I d=16 c=-2")
     XB = _run(ep, B, None, 1.0, 16, precision, shift=-2.0)
     assert matrix.rel_fro(XB, matrix.expm_R_shifted(B, None, 1.0, 16, -2.0)) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOLMX)])
+def test_real_symmetric_fast_path(ep, precision, tol):
+    """Real symmetric A and real V (Remark rem:two_time_real_part): with real_data the
+    conjugate pole's solution is taken as the conjugate of the primal one, so only one
+    pole per pair is solved.  Parity against the oracle; the imaginary parts of the
+    inputs are not read in that mode."""
+    rng = np.random.default_rng(77)
+    n, m = 260, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(-80.0, 0.0, n)
+    A = ((Q * lam) @ Q.T).astype(np.complex128)
+    A = 0.5 * (A + A.T)
+    V = rng.standard_normal((n, m)).astype(np.complex128)
+    Y = matrix.expm_R(A, V, 1.0, 24)
+    _announce(f"real fast path {precision} n={n} m={m} d=24")
+    X = _run(ep, A, V, 1.0, 24, precision, real_data=True)
+    assert matrix.rel_fro(X, Y) < tol
+    # imaginary parts are ignored in this mode
+    Aj = A + 1j * rng.standard_normal((n, n))
+    Vj = V + 1j * rng.standard_normal((n, m))
+    _announce(f"real fast path {precision} ignores imaginary parts")
+    Xj = _run(ep, Aj, Vj, 1.0, 24, precision, real_data=True)
+    assert np.array_equal(X, Xj)
+    # the general path on the same data agrees to the tolerance
+    X2 = _run(ep, A, V, 1.0, 24, precision)
+    assert matrix.rel_fro(X2, Y) < tol
