@@ -110,6 +110,44 @@ struct PanelShared {
   int piv[NB_MAX];
 };
 
+// Maximum of non-negative search values (or -1 for "no row"), over the wave and
+// over each 16-lane row.  For FP32 the values are compared as signed integers:
+// for floats >= 0 the bit patterns order like the values and -1.0f is negative,
+// which saves the NaN canonicalisation a float maximum carries (no search value
+// is NaN: a NaN never compares greater than the running maximum).
+template <typename R>
+__device__ __forceinline__ R search_wave_max(R x) {
+  if constexpr (sizeof(R) == 4) {
+    int v = __float_as_int(x);
+    v = max(v, dpp_i32<0xB1, 0xF>(v));
+    v = max(v, dpp_i32<0x4E, 0xF>(v));
+    v = max(v, dpp_i32<0x141, 0xF>(v));
+    v = max(v, dpp_i32<0x140, 0xF>(v));
+    v = max(v, dpp_i32<0x142, 0xA>(v));
+    v = max(v, dpp_i32<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(v, 63));
+  } else {
+    return wave_max(x);
+  }
+}
+template <typename R>
+__device__ __forceinline__ R search_row16_max(R x) {
+  if constexpr (sizeof(R) == 4) {
+    int v = __float_as_int(x);
+    v = max(v, dpp_i32<0xB1, 0xF>(v));
+    v = max(v, dpp_i32<0x4E, 0xF>(v));
+    v = max(v, dpp_i32<0x141, 0xF>(v));
+    v = max(v, dpp_i32<0x140, 0xF>(v));
+    return __int_as_float(v);
+  } else {
+    return row16_max(x);
+  }
+}
+
+// One column C of the inner panel.  Thread tid holds rows c0 + tid + PANEL_NT*s
+// (s < S) in a[s][.].  Row gc = c0 + C is always lane C of wave 0 in block 0;
+// a row index that is uniform across the wave (the wave's candidate, the pivot)
+// names its block s and wave, so only that block's copy is issued.
 template <typename R, int IB, int S, int C>
 __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, IB>& sh, int c0, int j0, int npad,
                                              int tid) {
@@ -133,7 +171,7 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
       }
     }
     // wave candidate: maximum value, then the lowest row among the lanes holding it
-    const R wv = wave_max(bv);
+    const R wv = search_wave_max(bv);
     const unsigned long long m = __ballot(bv == wv);
     const int wi = (__popcll(m) == 1) ? __builtin_amdgcn_readlane(bi, __ffsll((long long)m) - 1)
                                        : wave_min(bv == wv ? bi : NONE);
@@ -141,24 +179,24 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
       sh.cand_v[buf][wid] = wv;
       sh.cand_i[buf][wid] = wi;
     }
+    const int wblk = (wi - c0) / PANEL_NT;  // block holding the candidate (none if wi == NONE)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + PANEL_NT * s;
-      if (r == wi) {
+      if (s == wblk && c0 + tid + PANEL_NT * s == wi) {
 #pragma unroll
         for (int cc = 0; cc < IB; ++cc) sh.cand_row[buf][wid][cc] = a[s][cc];
       }
-      if (r == gc) {
+    }
+    if (wid == 0 && lane == C) {
 #pragma unroll
-        for (int cc = 0; cc < IB; ++cc) sh.crow[buf][cc] = a[s][cc];
-      }
+      for (int cc = 0; cc < IB; ++cc) sh.crow[buf][cc] = a[0][cc];
     }
     __syncthreads();
     // global pivot: each row of 16 lanes reduces the wave candidates (each
     // candidate held by 16 / PANEL_NW lanes of the row)
     const R cv = sh.cand_v[buf][lane % PANEL_NW];
     const int ci = sh.cand_i[buf][lane % PANEL_NW];
-    const R gv = row16_max(cv);
+    const R gv = search_row16_max(cv);
     const int gi = __builtin_amdgcn_readlane(row16_min(cv == gv ? ci : NONE), 0);
     // no candidate compared greater (a column of NaNs): keep the diagonal row, so
     // every later row index stays inside the matrix
@@ -166,26 +204,35 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
     const int p = found ? gi : gc;
     const T* prow = found ? sh.cand_row[buf][((p - c0) % PANEL_NT) >> 6] : sh.crow[buf];
     if (tid == 0) sh.piv[gc - j0] = p;
+    // the part of the pivot row the update uses, read once into registers
+    T pr[IB];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + PANEL_NT * s;
-      if (r == gc) {
+    for (int cc = C; cc < IB; ++cc) pr[cc] = prow[cc];
+    // interchange rows gc and p
+    if (wid == 0 && lane == C) {
 #pragma unroll
-        for (int cc = 0; cc < IB; ++cc) a[s][cc] = prow[cc];
-      } else if (r == p) {
+      for (int cc = 0; cc < IB; ++cc) a[0][cc] = cc < C ? prow[cc] : pr[cc];
+    }
+    const int pblk = (p - c0) / PANEL_NT;
+    if (p != gc && wid == ((p - c0) % PANEL_NT) >> 6) {
 #pragma unroll
-        for (int cc = 0; cc < IB; ++cc) a[s][cc] = sh.crow[buf][cc];
+      for (int s = 0; s < S; ++s) {
+        if (s == pblk && c0 + tid + PANEL_NT * s == p) {
+#pragma unroll
+          for (int cc = 0; cc < IB; ++cc) a[s][cc] = sh.crow[buf][cc];
+        }
       }
     }
-    const T inv = crecip_fast(prow[C]);
+    const T inv = crecip_fast(pr[C]);
+    // rows at or above gc (lanes 0..C of wave 0, block 0) are rows of U and stay;
+    // rows past npad hold zeros here and are never searched or stored
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + PANEL_NT * s;
-      if (r > gc && r < npad) {
+      if (s > 0 || tid > C) {
         const T l = cmul(a[s][C], inv);
         a[s][C] = l;
 #pragma unroll
-        for (int cc = C + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, prow[cc]);
+        for (int cc = C + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, pr[cc]);
       }
     }
     panel_column<R, IB, S, C + 1>(a, sh, c0, j0, npad, tid);
