@@ -472,6 +472,54 @@ void step_update(expm_pfd_plan_t pl, int step, hipStream_t st) {
              opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
 }
 
+// Two steps j, j+1 with one trailing update of depth 2 NB.  Step j's update is
+// applied at once only where step j+1 needs it: the columns of panel j+1 (before
+// that panel is factored) and the rows of U12 of step j+1 (before it is formed).
+// The rest of the trailing matrix gets both steps' updates from one product,
+// A22 -= [L21_j L21_j+1] [U12_j; U12_j+1], which reads and writes A22 once per
+// two steps.  Step j+1's interchanges reach the rows still waiting for step j's
+// update together with the rows of L21_j (the left columns), so the deferred
+// product stays consistent; in exact arithmetic the factors are those of the
+// one-step order.
+template <typename R>
+void step_pair(expm_pfd_plan_t pl, int step, hipStream_t st) {
+  const int PB = pl->PB, npad = (int)pl->npad;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  const int64_t ds = (int64_t)pl->nsteps * 2 * NB * NB;
+  const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
+  cx<R>* W = (cx<R>*)pl->W;
+  cx<R>* dinv = (cx<R>*)pl->dinv;
+  const int64_t j0 = (int64_t)step * NB, c1 = j0 + NB;
+  const int nb2 = std::min<int>(NB, npad - (int)c1);
+  const int64_t c2 = c1 + nb2;
+  const int ntr1 = npad - (int)c1, ntr2 = npad - (int)c2;
+  // step j: panel, its interchanges elsewhere, L11^{-1}, U12 over every right column
+  panel_phase<R>(pl, step, st);
+  moves_apply<R>(st, PB, W, ws, ld, (int)j0 + ntr1, (int)j0, NB, pl->moves + (int64_t)step * MOVE_STRIDE, mstride,
+                 0, 1, 0);
+  block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
+  gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, NB, ntr1, NB, opnd<R>(dinv + (int64_t)step * 2 * NB * NB, ds, NB, false),
+             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c1, ws, ld, W + j0 * ld + c1, ws, ld);
+  // step j's update of the columns of panel j+1
+  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr1, nb2, NB, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
+  // step j+1: panel and its interchanges on the columns left and right of it
+  panel_phase<R>(pl, step + 1, st);
+  moves_apply<R>(st, PB, W, ws, ld, (int)c1 + ntr2, (int)c1, nb2,
+                 pl->moves + (int64_t)(step + 1) * MOVE_STRIDE, mstride, 0, 1, 0);
+  if (ntr2 <= 0) return;
+  block_inverse<R>(st, PB, W, ws, ld, step + 1, 1, 0, dinv, ds);
+  // step j's update of the rows of U12_j+1, then U12_j+1 = L11^{-1} A12
+  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, nb2, ntr2, NB, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c1 * ld + c2, ws, ld);
+  gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nb2, ntr2, nb2,
+             opnd<R>(dinv + (int64_t)(step + 1) * 2 * NB * NB, ds, NB, false), opnd<R>(nullptr, 0, 0, false), PB,
+             W + c1 * ld + c2, ws, ld, W + c1 * ld + c2, ws, ld);
+  // both steps' update of the trailing matrix
+  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr2, ntr2, NB + nb2, opnd<R>(W + c2 * ld + j0, ws, ld, false),
+             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c2 * ld + c2, ws, ld);
+}
+
 template <typename R>
 void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, hipStream_t st) {
   const int P = pl->P, PB = pl->PB;
@@ -490,7 +538,9 @@ void factor(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one
   const int nsteps = pl->nsteps;
   // (overlapping the panels of step j+1 with the update of step j on two streams,
   // with or without CUs kept free for the panels, measured slower on gfx950)
-  for (int step = 0; step < nsteps; ++step) {
+  int step = 0;
+  for (; step + 1 < nsteps; step += 2) step_pair<R>(pl, step, st);
+  if (step < nsteps) {
     panel_phase<R>(pl, step, st);
     step_update<R>(pl, step, st);
   }

@@ -471,8 +471,13 @@ struct GemmOperand {
   int conj;
 };
 
+// Waves per SIMD the register allocation of k_gemm is held to (the LDS of a
+// 64 x 64 tile allows four workgroups per CU).  Unconstrained, the FP32 kernel
+// takes 132 registers and runs three waves per SIMD.
+constexpr int GEMM_WAVES_F32 = 4, GEMM_WAVES_F64 = 2;
+
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
                                               int64_t ldc, KSplit ksp) {
   using T = cx<R>;
