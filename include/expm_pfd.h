@@ -81,7 +81,23 @@ typedef struct expm_pfd_opts {
                       Then the conjugate pole's solution is the conjugate of the
                       primal one (Remark rem:two_time_real_part): solves and
                       refinement run for one pole per pair only. */
-  int reserved[4]; /* set to 0 */
+  int graph;       /* nonzero: expm_pfd_apply and expm_pfd_batch_apply capture their
+                      launches into a HIP graph on first use (per plan and
+                      right-hand-side width, per batch schedule) and replay it
+                      afterwards.  The problem descriptors (A, V, X, t) are
+                      uploaded ahead of each replay, so new pointers and times
+                      need no recapture.  Launches run directly while tracing is on. */
+  int autotune;    /* nonzero: at plan creation, time each LU trailing-update tile
+                      shape on the plan's own workspace and keep the fastest
+                      (cached per padded order, precision and batch); a batch
+                      plan with several groups also times, at its first apply,
+                      running the groups one after another against 2 and 4
+                      concurrent branches.  Every candidate computes the same
+                      bits, so tuning changes speed only. */
+  int lu_tile;     /* 0: built-in (64 x 64) or autotuned; k = 1..3 forces tile shape
+                      k-1 of {64x64, 128x64, 64x128} (complex elements of C per
+                      workgroup).  Other values: EXPM_PFD_ERR_ARG. */
+  int reserved;    /* set to 0 */
   double shift;    /* c of the shifting method (Remark rem:shift): the library
                       computes e^c R_d(tA - cI) V, so spectra of tA up to c are
                       covered by the negative-spectrum error bound of the
@@ -167,14 +183,66 @@ int expm_pfd_plan_check(expm_pfd_plan_t plan);
  *           then m[i] must be n[i]).
  *   degree, opts  shared by all problems.
  * Problems are grouped by padded order; every group runs as one sequence of
- * launches whose grids cover all poles of all its problems.  Device workspace
- * is allocated inside the call and released before it returns; the call
- * synchronizes the stream before returning.
+ * launches whose grids cover all poles of all its problems.  One-shot form of
+ * expm_pfd_batch_plan + expm_pfd_batch_apply + expm_pfd_batch_check +
+ * expm_pfd_batch_destroy: device workspace is allocated inside the call and
+ * released before it returns; the call synchronizes before returning.
  */
 int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree,
                            const void* const* A, const int64_t* lda, const void* const* V,
                            const int64_t* ldv, const int64_t* m, void* const* X, const int64_t* ldx,
                            const expm_pfd_opts* opts, void* stream);
+
+/*
+ * Batch plans: the workspace of a fixed set of problem shapes, allocated once
+ * and reused by every apply, which then allocates nothing and does not wait
+ * for the device.
+ */
+typedef struct expm_pfd_batch_s* expm_pfd_batch_t;
+
+/*
+ * expm_pfd_batch_plan: prepare X_i = R_d(t_i A_i) V_i for count problems of
+ * orders n[i] (Sec. 3, eq. equ:expAx per problem; all poles of all problems are
+ * independent solves).
+ *   n, m    host arrays of length count: order of A_i (1..EXPM_PFD_MAX_N) and
+ *           columns of V_i (1..n[i]), or m[i] = 0 for V_i = I (the full
+ *           R_d(t_i A_i)).
+ *   degree, opts  shared by all problems (opts: see expm_pfd_opts; graph and
+ *           autotune apply to the whole batch).
+ * Problems with the same padded order (a multiple of 64) and right-hand-side
+ * kind form one group; every launch of a group covers all poles of all its
+ * problems.  Allocates each group's workspace on the current device.
+ * Errors: EXPM_PFD_ERR_DIM, _DEGREE, _ARG, _NULL, _OOM, _HIP.
+ */
+int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, const int64_t* m, int degree,
+                        const expm_pfd_opts* opts);
+
+/*
+ * expm_pfd_batch_apply: X_i = R_d(t_i A_i) V_i for every problem of the plan.
+ *   t, lda, ldv, ldx  host arrays of length count (t finite; lda, ldx >= n[i];
+ *           ldv >= n[i] where V[i] is given).
+ *   A, V, X host arrays of count device pointers, layouts as in expm_pfd_apply.
+ *           V[i] must be NULL exactly where the plan has m[i] = 0.
+ * Asynchronous on `stream`: uploads the problem descriptors (from pinned
+ * staging the plan owns; it waits only for the previous apply's upload) and
+ * enqueues or replays the groups.  Concurrent applies of one batch plan race.
+ * Sweep faults are reported by expm_pfd_batch_check.
+ */
+int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const void* const* A, const int64_t* lda,
+                         const void* const* V, const int64_t* ldv, void* const* X, const int64_t* ldx,
+                         void* stream);
+
+/* Synchronizes the device; then 0, or EXPM_PFD_ERR_SYNC if a triangular sweep of
+ * any group lost its dependency order (see expm_pfd_plan_check), or _HIP. */
+int expm_pfd_batch_check(expm_pfd_batch_t b);
+
+/* Shape of a batch plan: its number of groups, the schedule in use (number of
+ * concurrent group branches; 0 before the first apply) and the largest LU tile
+ * index among the groups.  Any output pointer may be NULL. */
+int expm_pfd_batch_info(expm_pfd_batch_t b, int* groups, int* schedule, int* lu_tile_max);
+
+/* Release a batch plan (synchronizes the device first). */
+int expm_pfd_batch_destroy(expm_pfd_batch_t b);
 
 /* ---- tracing ------------------------------------------------------------ */
 /* Kernel classes timed by the tracer (one HIP event pair per launch, recorded on

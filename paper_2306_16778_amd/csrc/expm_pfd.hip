@@ -31,6 +31,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -184,10 +185,20 @@ void panel(hipStream_t st, int IB, int S, const PanelArgs& g, cx<R>* W) {
   }
 }
 
+// Tile shapes of the LU trailing update (C -= L21 U12 over the whole trailing
+// matrix).  Every shape runs the same K loop per output element (same chunk
+// order, same matrix-core instruction), so the choice never changes a bit of
+// the result; it is a speed knob only (built-in: 64 x 64; the autotuner times
+// all of them).
+constexpr int LU_TILES = 3;
+const char* const LU_TILE_NAMES[LU_TILES] = {"64x64", "128x64", "64x128"};
+
 // MODE 0: C -= op(A) B;  MODE 1: C = op(A) B.  Batches < split use a0, others a1.
+// tile: LU trailing-update shape (index into LU_TILE_NAMES), MODE 0 only.
 template <typename R, int MODE>
 void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
-          const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp = {1, 0, 0, 0}) {
+          const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp = {1, 0, 0, 0},
+          int tile = 0) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
   const double e = sizeof(cx<R>);
   const double Kt = (double)K * ksp.ks;
@@ -201,10 +212,21 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
     else
       hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
   };
-  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM)
+  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM) {
     launch(k_gemm<R, MODE, 64, 16, 4, 1>, dim3((unsigned)((M + 63) / 64), gy));
-  else
-    launch(k_gemm<R, MODE, 64, 64, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
+    return;
+  }
+  if constexpr (MODE == 0) {
+    if (tile == 1) {
+      launch(k_gemm<R, MODE, 128, 64, 2, 2>, dim3((unsigned)(((M + 127) / 128) * ((N + 63) / 64)), gy));
+      return;
+    }
+    if (tile == 2) {
+      launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
+      return;
+    }
+  }
+  launch(k_gemm<R, MODE, 64, 64, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
 }
 
 // K slices of the FP64 refinement product (t A) X for thin right-hand sides: a
@@ -276,11 +298,10 @@ struct expm_pfd_plan_s {
   int* ipiv = nullptr;       // PB x npad
   int* moves = nullptr;      // PB x nsteps x MOVE_STRIDE
   void* dinv = nullptr;      // PB x nsteps x 2 x 64 x 64: inverses of the diagonal blocks of L and U
-  // one-launch sweeps: [0] ticket counter, [1] status, then from int FLAG_STRIDE on
-  // 2PB x chains x nsteps ready flags, FLAG_STRIDE ints apart
+  // one-launch sweeps: the control line (ticket and finish counters, status,
+  // epoch: SW_*), then from int FLAG_STRIDE on 2PB x chains x nsteps ready flags,
+  // FLAG_STRIDE ints apart.  Kept on the device only, so sweeps replay in graphs.
   int* sweep_sync = nullptr;
-  unsigned ticket_base = 0;  // counter value at the start of the next sweep launch
-  int epoch = 0;             // value the flags of the last sweep launch carry
   void* Xs = nullptr;        // npad x cols_alloc, working type
   double2* Ah = nullptr;     // mixed: G x npad x npad FP64 t*A (Hermitian, row-major)
   double2* X64 = nullptr;    // mixed: npad x cols_alloc
@@ -288,6 +309,10 @@ struct expm_pfd_plan_s {
   double2* Rpart = nullptr;  // mixed: ir_kslices(npad) x npad x (2 PB min(mp_max, 64)) split-K partials
   ProblemDesc* d_descs = nullptr;  // G problem descriptors on the device (batched entry point)
   int device = 0;
+  int lu_tile = 0;                 // LU trailing-update tile shape (LU_TILE_NAMES)
+  int use_graph = 0;               // expm_pfd_apply replays captured graphs
+  hipStream_t cap = nullptr;       // stream the graphs are captured on (plan-owned)
+  std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;  // (V = I, m) -> executable graph
 };
 
 namespace {
@@ -323,12 +348,15 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
 int check_opts(const expm_pfd_opts* o) {
   if (!o) return 0;
   if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
+  if (o->lu_tile < 0 || o->lu_tile > LU_TILES) return EXPM_PFD_ERR_ARG;
   if (!std::isfinite(o->shift) || !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
   return 0;
 }
 
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
   void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
                   p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->Rpart, p->d_descs};
   for (void* q : ptrs)
@@ -340,7 +368,7 @@ void free_plan(expm_pfd_plan_t p) {
 // call once the plan's work has completed
 int sweep_fault(expm_pfd_plan_t p) {
   int f = 0;
-  if (hipMemcpy(&f, p->sweep_sync + 1, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  if (hipMemcpy(&f, p->sweep_sync + SW_STATUS, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -1;
   return f;
 }
 
@@ -413,6 +441,103 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   return 0;
 }
 
+// ---- graphs ------------------------------------------------------------------------
+// Captures the work fn(stream) enqueues on `cap` into an executable graph.
+template <typename F>
+int capture_graph(hipStream_t cap, F&& fn, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  *out = nullptr;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  int rc = fn(cap);
+  if (hipStreamEndCapture(cap, &g) != hipSuccess && rc == 0) rc = EXPM_PFD_ERR_HIP;
+  if (rc == 0 && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) {
+    *out = nullptr;
+    rc = EXPM_PFD_ERR_HIP;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  return rc;
+}
+
+int ensure_capture_stream(expm_pfd_plan_t pl) {
+  if (pl->cap) return 0;
+  return hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) == hipSuccess ? 0 : EXPM_PFD_ERR_HIP;
+}
+
+// ---- autotuner -----------------------------------------------------------------------
+// Times every LU trailing-update tile shape on the plan's first two-step update
+// (M = N = npad - 128, K = 128, all PB shifted matrices) and returns the
+// fastest.  The shapes give bitwise-identical results, so the choice only
+// affects speed.  Choices are cached per (padded order, precision, batch).
+std::mutex tune_mu;
+std::map<std::tuple<int64_t, int, int>, int> tune_cache;
+
+template <typename R>
+int tune_lu_tile_t(expm_pfd_plan_t pl) {
+  const int npad = (int)pl->npad, PB = pl->PB;
+  const int K = pl->nsteps >= 2 ? 2 * NB : NB;
+  const int M = npad - K;
+  if (M < NB || ensure_capture_stream(pl)) return 0;
+  hipStream_t s = pl->cap;
+  const int64_t ld = npad, ws = (int64_t)npad * npad;
+  cx<R>* W = (cx<R>*)pl->W;
+  if (hipMemsetAsync(pl->W, 0, (size_t)PB * ws * sizeof(cx<R>), s) != hipSuccess) return 0;
+  const unsigned saved = trace::mask;
+  trace::mask = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  int best = 0;
+  float best_ms = 0.f;
+  for (int tile = 0; tile < LU_TILES; ++tile) {
+    auto once = [&] {
+      gemm<R, 0>(s, EXPM_PFD_K_LU_GEMM, PB, M, M, K, opnd<R>(W + (int64_t)K * ld, ws, ld, false),
+                 opnd<R>(nullptr, 0, 0, false), PB, W + K, ws, ld, W + (int64_t)K * ld + K, ws, ld, {1, 0, 0, 0},
+                 tile);
+    };
+    once();
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < 3; ++r) once();
+    (void)hipEventRecord(b, s);
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) break;
+    if (tile == 0 || ms < best_ms) {
+      best = tile;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  trace::mask = saved;
+  (void)hipGetLastError();
+  return best;
+}
+
+int tune_lu_tile(expm_pfd_plan_t pl) {
+  const auto key = std::make_tuple(pl->npad, pl->precision, pl->PB);
+  {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    auto it = tune_cache.find(key);
+    if (it != tune_cache.end()) return it->second;
+  }
+  const int t = pl->precision == EXPM_PFD_FP64 ? tune_lu_tile_t<double>(pl) : tune_lu_tile_t<float>(pl);
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_cache[key] = t;
+  return t;
+}
+
+// Options that do not change the workspace: tile shape and graph replay.
+int configure_plan(expm_pfd_plan_t pl, const expm_pfd_opts* o) {
+  if (!o) return 0;
+  pl->use_graph = o->graph ? 1 : 0;
+  if (o->lu_tile > 0)
+    pl->lu_tile = o->lu_tile - 1;
+  else if (o->autotune)
+    pl->lu_tile = tune_lu_tile(pl);
+  if (pl->use_graph) return ensure_capture_stream(pl);
+  return 0;
+}
+
 // ---- factorization of all shifted matrices of the group --------------------------
 // Panel phase of outer step `step` (columns [j0, j0+nbo)): the inner register
 // panels and the updates inside the outer panel.
@@ -469,7 +594,8 @@ void step_update(expm_pfd_plan_t pl, int step, hipStream_t st) {
   gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
              PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
   gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
-             opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
+             opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld,
+             {1, 0, 0, 0}, pl->lu_tile);
 }
 
 // Two steps j, j+1 with one trailing update of depth 2 NB.  Step j's update is
@@ -517,7 +643,8 @@ void step_pair(expm_pfd_plan_t pl, int step, hipStream_t st) {
              W + c1 * ld + c2, ws, ld, W + c1 * ld + c2, ws, ld);
   // both steps' update of the trailing matrix
   gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr2, ntr2, NB + nb2, opnd<R>(W + c2 * ld + j0, ws, ld, false),
-             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c2 * ld + c2, ws, ld);
+             opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c2 * ld + c2, ws, ld, {1, 0, 0, 0},
+             pl->lu_tile);
 }
 
 template <typename R>
@@ -590,12 +717,8 @@ void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoin
     trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nchain * tiles * NB * NB * 16,
                     e * nblk * tiles * NB * NB + 2.0 * e * nchain * npad * 16);
     const unsigned nwg = (unsigned)nchain * (unsigned)nsteps;
-    pl->epoch = pl->epoch == INT32_MAX ? 1 : pl->epoch + 1;
-    int* sync = pl->sweep_sync;
     hipLaunchKernelGGL((k_sweep_chain<R>), dim3(nwg), dim3(256), 0, st, fwd ? 1 : 0, nsteps, nchain, cpb, d0, d1, a0,
-                       a1, PB, X, (int64_t)mp, ldS, (unsigned*)sync, pl->ticket_base, sync + FLAG_STRIDE, pl->epoch,
-                       sync + 1);
-    pl->ticket_base += nwg;
+                       a1, PB, X, (int64_t)mp, ldS, pl->sweep_sync);
   }
   if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
 }
@@ -811,6 +934,10 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   pl->n = n;
   pl->t = t;
   pl->m_max = m_max;
+  if ((rc = configure_plan(pl, opts)) != 0) {
+    free_plan(pl);
+    return rc;
+  }
   *out = pl;
   return 0;
 }
@@ -840,7 +967,24 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   one.real = pl->real_data;
   (void)hipGetLastError();
   const int mp = full ? (int)pl->npad : (int)round_up(m, 16);
-  if (int e = run(pl, nullptr, one, full, mp, (int)pl->n, (int)m, st)) return e;
+  if (pl->use_graph && trace::mask == 0) {
+    // the graph's kernels read the descriptor from the plan's device copy
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(1), 0, st, pl->d_descs, one);
+    const std::pair<int, int64_t> key{full ? 1 : 0, m};
+    auto it = pl->graphs.find(key);
+    if (it == pl->graphs.end()) {
+      hipGraphExec_t ex = nullptr;
+      ProblemDesc none{};
+      if (int e = capture_graph(
+              pl->cap, [&](hipStream_t cs) { return run(pl, pl->d_descs, none, full, mp, (int)pl->n, (int)m, cs); },
+              &ex))
+        return e;
+      it = pl->graphs.emplace(key, ex).first;
+    }
+    if (hipGraphLaunch(it->second, st) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  } else if (int e = run(pl, nullptr, one, full, mp, (int)pl->n, (int)m, st)) {
+    return e;
+  }
   if (hipGetLastError() != hipSuccess) return EXPM_PFD_ERR_HIP;
   return 0;
 }
@@ -852,70 +996,300 @@ extern "C" int expm_pfd_plan_check(expm_pfd_plan_t pl) {
   return f < 0 ? EXPM_PFD_ERR_HIP : (f ? EXPM_PFD_ERR_SYNC : 0);
 }
 
+// ============================================================================
+// batch plans: problems grouped by (padded order, right-hand-side kind), one
+// group plan each, all allocated once; every apply uploads the descriptors and
+// runs (or replays) the groups without allocating or synchronizing.
+// ============================================================================
+struct expm_pfd_batch_s {
+  struct Group {
+    expm_pfd_plan_t pl = nullptr;
+    std::vector<int> idx;  // problems of the group, in input order
+    bool full = false;
+    int mp = 0, nmax = 0, mmax = 0;
+    double work = 0;  // G * npad^3: the schedule's load estimate
+  };
+  int count = 0, degree = 0, real_data = 0, use_graph = 0, autotune = 0;
+  int schedule = 0;  // concurrent branches the groups run on (0: not chosen yet)
+  std::vector<int64_t> n, m;  // m[i] = 0: V_i = I
+  std::vector<Group> groups;
+  ProblemDesc* h_descs = nullptr;  // pinned staging of the descriptors, in group order
+  hipEvent_t uploaded = nullptr;   // the last upload has read h_descs
+  hipStream_t cap = nullptr;       // capture stream
+  std::vector<hipStream_t> br;     // branch streams (schedules with more than one branch)
+  std::vector<hipEvent_t> ev;      // fork and join events
+  std::map<int, hipGraphExec_t> graphs;  // schedule -> executable graph
+};
+
+namespace {
+
+constexpr int BATCH_MAX_BRANCHES = 4;
+
+void free_batch(expm_pfd_batch_t b) {
+  if (!b) return;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& g : b->groups) free_plan(g.pl);
+  if (b->h_descs) (void)hipHostFree(b->h_descs);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipStream_t s : b->br) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  delete b;
+}
+
+// Every group's work on `st` (S = 1) or forked over S branch streams, largest
+// groups first onto the least loaded branch, joined back into `st`.
+int run_groups(expm_pfd_batch_t b, hipStream_t st, int S) {
+  ProblemDesc none{};
+  S = std::min<int>(S, (int)b->groups.size());
+  if (S <= 1) {
+    for (auto& g : b->groups)
+      if (int e = run(g.pl, g.pl->d_descs, none, g.full, g.mp, g.nmax, g.mmax, st)) return e;
+    return 0;
+  }
+  if (hipEventRecord(b->ev[0], st) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  for (int i = 0; i < S; ++i)
+    if (hipStreamWaitEvent(b->br[i], b->ev[0], 0) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  std::vector<int> order(b->groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->groups[x].work > b->groups[y].work; });
+  std::vector<double> load(S, 0.0);
+  for (int gi : order) {
+    auto& g = b->groups[gi];
+    const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[s] += g.work;
+    if (int e = run(g.pl, g.pl->d_descs, none, g.full, g.mp, g.nmax, g.mmax, b->br[s])) return e;
+  }
+  for (int i = 0; i < S; ++i) {
+    if (hipEventRecord(b->ev[1 + i], b->br[i]) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    if (hipStreamWaitEvent(st, b->ev[1 + i], 0) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  }
+  return 0;
+}
+
+// One pass over all groups with schedule S: a graph replay, or direct launches
+// (no graph requested, or tracing on).
+int launch_batch(expm_pfd_batch_t b, hipStream_t st, int S) {
+  if (!b->use_graph || trace::mask != 0) return run_groups(b, st, S);
+  auto it = b->graphs.find(S);
+  if (it == b->graphs.end()) {
+    hipGraphExec_t ex = nullptr;
+    if (int e = capture_graph(b->cap, [&](hipStream_t cs) { return run_groups(b, cs, S); }, &ex)) return e;
+    it = b->graphs.emplace(S, ex).first;
+  }
+  return hipGraphLaunch(it->second, st) == hipSuccess ? 0 : EXPM_PFD_ERR_HIP;
+}
+
+// First apply: picks the schedule and leaves the batch's result in X.  With
+// autotune, each candidate branch count runs the caller's batch once to warm up
+// (and capture), then once timed; the fastest is kept.  All candidates compute
+// the same bits, so the caller's X is the same whichever ran last.
+int choose_schedule(expm_pfd_batch_t b, hipStream_t st) {
+  const int G = (int)b->groups.size();
+  if (!b->autotune || G == 1) {
+    b->schedule = 1;
+    return launch_batch(b, st, 1);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = 1, rc = 0;
+  float best_ms = 0.f;
+  for (int S = 1; S <= std::min(G, BATCH_MAX_BRANCHES) && rc == 0; S *= 2) {
+    if ((rc = launch_batch(b, st, S)) != 0) break;
+    (void)hipEventRecord(e0, st);
+    if ((rc = launch_batch(b, st, S)) != 0) break;
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = EXPM_PFD_ERR_HIP;
+      break;
+    }
+    if (S == 1 || ms < best_ms) {
+      best = S;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // keep only the chosen schedule's graph
+  for (auto it = b->graphs.begin(); it != b->graphs.end();) {
+    if (it->first != best) {
+      (void)hipGraphExecDestroy(it->second);
+      it = b->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  b->schedule = best;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, const int64_t* m, int degree,
+                                   const expm_pfd_opts* opts) {
+  if (!out) return EXPM_PFD_ERR_NULL;
+  *out = nullptr;
+  if (count < 1) return EXPM_PFD_ERR_DIM;
+  if (!n || !m) return EXPM_PFD_ERR_NULL;
+  if (int e = check_degree(degree)) return e;
+  if (int e = check_opts(opts)) return e;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
+    if (m[i] < 0 || m[i] > n[i]) return EXPM_PFD_ERR_DIM;
+  }
+  const int precision = opts ? opts->precision : EXPM_PFD_FP64;
+  auto* b = new expm_pfd_batch_s();
+  b->count = count;
+  b->degree = degree;
+  b->real_data = opts ? (opts->real_data ? 1 : 0) : 0;
+  b->use_graph = opts ? (opts->graph ? 1 : 0) : 0;
+  b->autotune = opts ? (opts->autotune ? 1 : 0) : 0;
+  b->n.assign(n, n + count);
+  b->m.assign(m, m + count);
+  // groups: same padded order and same kind (V = I, or 16-column-rounded width)
+  std::map<std::pair<int64_t, int64_t>, std::vector<int>> keyed;
+  for (int i = 0; i < count; ++i) keyed[{round_up(n[i], NB), m[i] ? round_up(m[i], 16) : 0}].push_back(i);
+  int rc = 0;
+  for (auto& kv : keyed) {
+    expm_pfd_batch_s::Group g;
+    const int64_t npad = kv.first.first, mpk = kv.first.second;
+    g.idx = kv.second;
+    g.full = mpk == 0;
+    g.mp = g.full ? (int)npad : (int)mpk;
+    const int G = (int)g.idx.size();
+    for (int i : g.idx) {
+      g.nmax = std::max<int>(g.nmax, (int)n[i]);
+      g.mmax = std::max<int>(g.mmax, (int)(m[i] ? m[i] : n[i]));
+    }
+    g.work = (double)G * npad * npad * npad;
+    rc = create_plan(&g.pl, npad, G, degree, g.full ? 16 : mpk, g.full, precision, opts ? opts->ir_sweeps : 0,
+                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, b->real_data);
+    if (rc) break;
+    b->groups.push_back(std::move(g));
+    expm_pfd_plan_t pl = b->groups.back().pl;
+    if (opts && (opts->lu_tile > 0 || opts->autotune)) {
+      expm_pfd_opts o = *opts;
+      o.graph = 0;  // graphs are the batch's, not the group plans'
+      if ((rc = configure_plan(pl, &o)) != 0) break;
+    }
+  }
+  HipErr he;
+  if (!rc) {
+    he(hipHostMalloc((void**)&b->h_descs, (size_t)count * sizeof(ProblemDesc), hipHostMallocDefault));
+    he(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
+    he(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    const int nb = std::min<int>((int)b->groups.size(), BATCH_MAX_BRANCHES);
+    if (nb > 1) {
+      b->br.resize(nb, nullptr);
+      b->ev.resize(1 + nb, nullptr);
+      for (auto& s : b->br) he(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      for (auto& e : b->ev) he(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    if (he.e != hipSuccess) rc = he.e == hipErrorOutOfMemory ? EXPM_PFD_ERR_OOM : EXPM_PFD_ERR_HIP;
+  }
+  if (rc) {
+    (void)hipGetLastError();
+    free_batch(b);
+    return rc;
+  }
+  *out = b;
+  return 0;
+}
+
+extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const void* const* A, const int64_t* lda,
+                                    const void* const* V, const int64_t* ldv, void* const* X, const int64_t* ldx,
+                                    void* stream) {
+  if (!b) return EXPM_PFD_ERR_NULL;
+  if (!t || !A || !lda || !V || !ldv || !X || !ldx) return EXPM_PFD_ERR_NULL;
+  for (int i = 0; i < b->count; ++i) {
+    if (!A[i] || !X[i]) return EXPM_PFD_ERR_NULL;
+    if ((V[i] == nullptr) != (b->m[i] == 0)) return EXPM_PFD_ERR_ARG;
+    if (lda[i] < b->n[i] || ldx[i] < b->n[i] || (V[i] && ldv[i] < b->n[i])) return EXPM_PFD_ERR_LD;
+    if (!std::isfinite(t[i])) return EXPM_PFD_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  // the previous apply's uploads have finished reading the staging buffer
+  if (hipEventSynchronize(b->uploaded) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  int off = 0;
+  for (auto& g : b->groups) {
+    ProblemDesc* hd = b->h_descs + off;
+    for (size_t k = 0; k < g.idx.size(); ++k) {
+      const int i = g.idx[k];
+      ProblemDesc& d = hd[k];
+      d.A = (const double2*)A[i];
+      d.lda = lda[i];
+      d.V = (const double2*)V[i];
+      d.ldv = V[i] ? ldv[i] : b->n[i];
+      d.X = (double2*)X[i];
+      d.ldx = ldx[i];
+      d.t = t[i];
+      d.n = (int)b->n[i];
+      d.m = (int)(b->m[i] ? b->m[i] : b->n[i]);
+      d.real = b->real_data;
+    }
+    if (hipMemcpyAsync(g.pl->d_descs, hd, g.idx.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return EXPM_PFD_ERR_HIP;
+    off += (int)g.idx.size();
+  }
+  if (hipEventRecord(b->uploaded, st) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  int rc = b->schedule == 0 ? choose_schedule(b, st) : launch_batch(b, st, b->schedule);
+  if (!rc && hipGetLastError() != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+  return rc;
+}
+
+extern "C" int expm_pfd_batch_check(expm_pfd_batch_t b) {
+  if (!b) return EXPM_PFD_ERR_NULL;
+  if (hipDeviceSynchronize() != hipSuccess) return EXPM_PFD_ERR_HIP;
+  for (auto& g : b->groups) {
+    const int f = sweep_fault(g.pl);
+    if (f < 0) return EXPM_PFD_ERR_HIP;
+    if (f) return EXPM_PFD_ERR_SYNC;
+  }
+  return 0;
+}
+
+extern "C" int expm_pfd_batch_info(expm_pfd_batch_t b, int* groups, int* schedule, int* lu_tile_max) {
+  if (!b) return EXPM_PFD_ERR_NULL;
+  if (groups) *groups = (int)b->groups.size();
+  if (schedule) *schedule = b->schedule;
+  if (lu_tile_max) {
+    int t = 0;
+    for (auto& g : b->groups) t = std::max(t, g.pl->lu_tile);
+    *lu_tile_max = t;
+  }
+  return 0;
+}
+
+extern "C" int expm_pfd_batch_destroy(expm_pfd_batch_t b) {
+  if (!b) return EXPM_PFD_ERR_NULL;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+  return 0;
+}
+
 extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree, const void* const* A,
                                       const int64_t* lda, const void* const* V, const int64_t* ldv,
                                       const int64_t* m, void* const* X, const int64_t* ldx,
                                       const expm_pfd_opts* opts, void* stream) {
   if (count < 1) return EXPM_PFD_ERR_DIM;
   if (!n || !t || !A || !lda || !V || !ldv || !m || !X || !ldx) return EXPM_PFD_ERR_NULL;
-  if (int e = check_degree(degree)) return e;
-  if (int e = check_opts(opts)) return e;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
-    if (!A[i] || !X[i]) return EXPM_PFD_ERR_NULL;
-    if (lda[i] < n[i] || ldx[i] < n[i]) return EXPM_PFD_ERR_LD;
-    if (V[i] && ldv[i] < n[i]) return EXPM_PFD_ERR_LD;
     if (V[i] ? (m[i] < 1 || m[i] > n[i]) : (m[i] != n[i])) return EXPM_PFD_ERR_DIM;
-    if (!std::isfinite(t[i])) return EXPM_PFD_ERR_ARG;
   }
-  const int precision = opts ? opts->precision : EXPM_PFD_FP64;
-  hipStream_t st = (hipStream_t)stream;
-  // groups: same padded order and same kind (V = I, or 16-column-rounded width)
-  std::map<std::pair<int64_t, int64_t>, std::vector<int>> groups;
-  for (int i = 0; i < count; ++i) {
-    const int64_t npad = round_up(n[i], NB);
-    const int64_t mp = V[i] ? round_up(m[i], 16) : 0;
-    groups[{npad, mp}].push_back(i);
-  }
-  (void)hipGetLastError();
-  int rc = 0;
-  for (auto& kv : groups) {
-    const int64_t npad = kv.first.first, mpk = kv.first.second;
-    const std::vector<int>& idx = kv.second;
-    const bool full = mpk == 0;
-    const int G = (int)idx.size();
-    expm_pfd_plan_t pl = nullptr;
-    rc = create_plan(&pl, npad, G, degree, full ? 16 : mpk, full, precision, opts ? opts->ir_sweeps : 0,
-                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, opts ? opts->real_data : 0);
-    if (rc) break;
-    std::vector<ProblemDesc> hd(G);
-    int nmax = 0, mmax = 0;
-    for (int g = 0; g < G; ++g) {
-      const int i = idx[g];
-      ProblemDesc& d = hd[g];
-      d.A = (const double2*)A[i];
-      d.lda = lda[i];
-      d.V = (const double2*)V[i];
-      d.ldv = ldv[i];
-      d.X = (double2*)X[i];
-      d.ldx = ldx[i];
-      d.t = t[i];
-      d.n = (int)n[i];
-      d.m = (int)m[i];
-      d.real = opts ? opts->real_data : 0;
-      nmax = std::max(nmax, d.n);
-      mmax = std::max(mmax, d.m);
-    }
-    if (hipMemcpyAsync(pl->d_descs, hd.data(), G * sizeof(ProblemDesc), hipMemcpyHostToDevice, st) != hipSuccess)
-      rc = EXPM_PFD_ERR_HIP;
-    ProblemDesc none{};
-    if (!rc) rc = run(pl, pl->d_descs, none, full, full ? (int)npad : (int)mpk, nmax, mmax, st);
-    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
-    if (!rc && sweep_fault(pl) != 0) rc = EXPM_PFD_ERR_SYNC;
-    free_plan(pl);
-    if (rc) break;
-  }
-  if (!rc && hipGetLastError() != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+  std::vector<int64_t> mk(count);
+  for (int i = 0; i < count; ++i) mk[i] = V[i] ? m[i] : 0;
+  expm_pfd_batch_t b = nullptr;
+  if (int e = expm_pfd_batch_plan(&b, count, n, mk.data(), degree, opts)) return e;
+  int rc = expm_pfd_batch_apply(b, t, A, lda, V, ldv, X, ldx, stream);
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+  if (!rc) rc = expm_pfd_batch_check(b);
+  expm_pfd_batch_destroy(b);
   return rc;
 }
 
@@ -962,6 +1336,7 @@ struct expm_pfd_queue_s {
   int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
   double shift = 0.0;
   int real_data = 0;
+  int lu_tile = 0;  // LU trailing-update tile shape of every plan the queue creates
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
   std::vector<double> lat_ms;
@@ -1065,6 +1440,7 @@ struct expm_pfd_queue_s {
         (void)hipGetLastError();
         return false;
       }
+      pl->lu_tile = lu_tile;
     }
     Flight f;
     f.stream = s;
@@ -1149,6 +1525,7 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   q->ir_ext = opts ? opts->ir_extended : 0;
   q->shift = opts ? opts->shift : 0.0;
   q->real_data = opts ? opts->real_data : 0;
+  q->lu_tile = opts && opts->lu_tile > 0 ? opts->lu_tile - 1 : 0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;

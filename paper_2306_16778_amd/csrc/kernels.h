@@ -13,6 +13,14 @@
 namespace expm {
 
 // ---------------------------------------------------------------------------
+// Stores one problem descriptor into device memory (the single-problem path
+// when it replays a captured graph: the graph's kernels read the descriptor
+// from memory, so new A, V, X and t need no change to the graph).
+// grid 1, block 1
+// ---------------------------------------------------------------------------
+__global__ void k_put_desc(ProblemDesc* dst, ProblemDesc d) { *dst = d; }
+
+// ---------------------------------------------------------------------------
 // K1: form the shifted matrices  W_p = t*A + theta_p I  (paper Sec. 3,
 // eqs. equ:ExpoMatRat and equ:expAx: one shifted matrix per pole; with the
 // conjugate pairs of Remark rem:two_time_real_part one per pair suffices).
@@ -473,11 +481,16 @@ struct GemmOperand {
 
 // Waves per SIMD the register allocation of k_gemm is held to (the LDS of a
 // 64 x 64 tile allows four workgroups per CU).  Unconstrained, the FP32 kernel
-// takes 132 registers and runs three waves per SIMD.
+// takes 132 registers and runs three waves per SIMD.  Tiles of twice the area
+// hold twice the accumulators and are given half the waves.
 constexpr int GEMM_WAVES_F32 = 4, GEMM_WAVES_F64 = 2;
+template <typename R, int BM, int BN>
+constexpr int gemm_waves() {
+  return (sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64) / (BM * BN > 64 * 64 ? 2 : 1);
+}
 
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
                                               int64_t ldc, KSplit ksp) {
   using T = cx<R>;
@@ -647,12 +660,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 // the off-diagonal block W[I rows][J cols] or, with conj, the conjugate
 // transpose of W[J rows][I cols].  Blocks bb < split use operands *0, the
 // others *1.
-// Scheduling: a workgroup takes a ticket from `counter` when it starts; ticket
-// t = q*nchain + c handles tile position q of chain c.  Its waits are on
+// Scheduling: a workgroup takes a ticket from ctl[SW_TICKET] when it starts;
+// ticket t = q*nchain + c handles tile position q of chain c.  Its waits are on
 // x_J of the same chain at positions < q, i.e. on smaller tickets, which were
 // taken by workgroups already running: every wait ends.  x_J is announced by
-// flags[(c*nsteps + J) * FLAG_STRIDE] == epoch.  Each wait is also capped; a
-// capped wait records 1 in *status and the sweep result is then invalid.
+// flags[(c*nsteps + J) * FLAG_STRIDE] == epoch, where the launch's epoch is one
+// more than ctl[SW_EPOCH].  The workgroup that finishes last (ctl[SW_DONE]
+// counts them) resets the ticket and finish counters and stores the epoch, so
+// the next launch on the stream starts from ticket 0 with a new epoch: no
+// launch argument changes between sweeps, and a captured graph replays them.
+// Each wait is also capped; a capped wait records 1 in ctl[SW_STATUS] and the
+// sweep result is then invalid.
 // grid (nchain * nsteps), block 256: wave w owns rows 16w..16w+15 of the tile.
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -664,6 +682,9 @@ struct SweepOperand {
 
 constexpr int SWEEP_SPIN_CAP = 1 << 20;
 constexpr int FLAG_STRIDE = 32;  // one 128-byte line per ready flag
+// words of the sweep control line (the first FLAG_STRIDE ints of the plan's
+// sweep area; the ready flags follow it)
+constexpr int SW_TICKET = 0, SW_STATUS = 1, SW_DONE = 2, SW_EPOCH = 3;
 
 // eight consecutive complex values from a 16-byte aligned address
 template <typename T>
@@ -862,15 +883,13 @@ __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nste
   }
 }
 
-// Solution blocks are handed between workgroups without cache maintenance:
-// they are written and read with per-access coherent atomics, and a block's
-// flag is set only after its stores have completed.
+// One tile position of one chain of k_sweep_chain (all 256 threads of the
+// workgroup): wait for and accumulate the earlier blocks, apply D_I, publish x_I.
 template <typename R>
-__global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nchain, int cpb, SweepOperand<R> d0,
-                                                     SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
-                                                     int split, cx<R>* X, int64_t sX, int64_t ldx,
-                                                     unsigned* counter, unsigned base, int* flags, int epoch,
-                                                     int* status) {
+__device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps, int nchain, int cpb,
+                                           SweepOperand<R> d0, SweepOperand<R> d1, SweepOperand<R> a0,
+                                           SweepOperand<R> a1, int split, cx<R>* X, int64_t sX, int64_t ldx,
+                                           int* flags, int epoch, int* status) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
@@ -879,16 +898,8 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
   __shared__ T Ds[DS_LDS ? NB : 1][NB + 1];
   __shared__ T Rs[NB][17];
   __shared__ T Xs[NB][17];  // x_J of the current dependency; finally x_I
-  __shared__ unsigned s_ticket;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  if (tid == 0) s_ticket = atomicAdd(counter, 1u) - base;
-  __syncthreads();
-  const unsigned ticket = (unsigned)__builtin_amdgcn_readfirstlane((int)s_ticket);
-  if (ticket >= (unsigned)(nchain * nsteps)) {
-    if (tid == 0) atomicOr(status, 2);
-    return;
-  }
   const int q = (int)(ticket / (unsigned)nchain), c = (int)(ticket % (unsigned)nchain);
   const int bb = c / cpb, c16 = c % cpb;
   const bool second = bb >= split;
@@ -960,6 +971,41 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) __hip_atomic_store((int*)fl + I * FLAG_STRIDE, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Solution blocks are handed between workgroups without cache maintenance:
+// they are written and read with per-access coherent atomics, and a block's
+// flag is set only after its stores have completed.
+template <typename R>
+__global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nchain, int cpb, SweepOperand<R> d0,
+                                                     SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
+                                                     int split, cx<R>* X, int64_t sX, int64_t ldx,
+                                                     int* ctl) {
+  __shared__ unsigned s_ticket;
+  __shared__ int s_epoch;
+  const int tid = threadIdx.x;
+  int* status = ctl + SW_STATUS;
+  int* flags = ctl + FLAG_STRIDE;
+  const unsigned total = (unsigned)(nchain * nsteps);  // == gridDim.x
+  if (tid == 0) {
+    s_ticket = atomicAdd((unsigned*)ctl + SW_TICKET, 1u);
+    const int e = __hip_atomic_load(ctl + SW_EPOCH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_epoch = e == INT32_MAX ? 1 : e + 1;
+  }
+  __syncthreads();
+  const unsigned ticket = (unsigned)__builtin_amdgcn_readfirstlane((int)s_ticket);
+  const int epoch = __builtin_amdgcn_readfirstlane(s_epoch);
+  if (ticket < total) sweep_tile<R>(ticket, fwd, nsteps, nchain, cpb, d0, d1, a0, a1, split, X, sX, ldx, flags, epoch,
+                                    status);
+  else if (tid == 0)
+    atomicOr(status, 2);
+  // the last workgroup to finish re-arms the control line for the next launch
+  __syncthreads();
+  if (tid == 0 && atomicAdd((unsigned*)ctl + SW_DONE, 1u) == total - 1u) {
+    __hip_atomic_store(ctl + SW_TICKET, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctl + SW_DONE, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(ctl + SW_EPOCH, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -34,6 +34,11 @@ EXPORTED = (
     "expm_pfd_destroy",
     "expm_pfd_plan_check",
     "expm_pfd_apply_batched",
+    "expm_pfd_batch_plan",
+    "expm_pfd_batch_apply",
+    "expm_pfd_batch_check",
+    "expm_pfd_batch_info",
+    "expm_pfd_batch_destroy",
     "expm_pfd_strerror",
     "expm_pfd_trace",
     "expm_pfd_trace_summary",
@@ -67,7 +72,11 @@ class _QueueStats(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("ir_extended", ctypes.c_int),
-                ("real_data", ctypes.c_int), ("reserved", ctypes.c_int * 4), ("shift", ctypes.c_double)]
+                ("real_data", ctypes.c_int), ("graph", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("lu_tile", ctypes.c_int), ("reserved", ctypes.c_int), ("shift", ctypes.c_double)]
+
+# tile shapes of the LU trailing update, in the order of expm_pfd_opts.lu_tile - 1
+LU_TILES = ("64x64", "128x64", "64x128")
 
 
 _lib = None
@@ -90,6 +99,11 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_plan_check.argtypes = [vp]
     lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(_Opts), vp]
+    lib.expm_pfd_batch_plan.argtypes = [ctypes.POINTER(vp), c_int, vp, vp, c_int, ctypes.POINTER(_Opts)]
+    lib.expm_pfd_batch_apply.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.expm_pfd_batch_check.argtypes = [vp]
+    lib.expm_pfd_batch_info.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    lib.expm_pfd_batch_destroy.argtypes = [vp]
     lib.expm_pfd_trace.argtypes = [c_int]
     lib.expm_pfd_trace_summary.argtypes = [c_int, ctypes.POINTER(c_double), ctypes.POINTER(i64),
                                            ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
@@ -116,7 +130,8 @@ def _check(code: int, where: str):
         raise ExpmPfdError(code, where)
 
 
-def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False) -> _Opts:
+def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False, graph=False, autotune=False,
+          lu_tile=None) -> _Opts:
     p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
     o = _Opts()
     o.precision = int(p)
@@ -124,6 +139,9 @@ def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False) -> _O
     o.ir_extended = int(ir_extended)
     o.shift = float(shift)
     o.real_data = 1 if real_data else 0
+    o.graph = 1 if graph else 0
+    o.autotune = 1 if autotune else 0
+    o.lu_tile = 0 if lu_tile is None else (LU_TILES.index(lu_tile) + 1 if isinstance(lu_tile, str) else int(lu_tile))
     return o
 
 
@@ -165,10 +183,12 @@ class Plan:
 
 
 def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0,
-                  ir_extended: int = 0, shift: float = 0.0, real_data: bool = False) -> Plan:
+                  ir_extended: int = 0, shift: float = 0.0, real_data: bool = False, graph: bool = False,
+                  autotune: bool = False, lu_tile=None) -> Plan:
+    """lu_tile: None (built-in or autotuned), a name from LU_TILES, or the C option value (1..3)."""
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile)
     _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
            "expm_pfd_plan")
     return Plan(h.value, n, degree, t, m_max, precision)
@@ -262,6 +282,101 @@ def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degr
                                       ldv.ctypes.data, m.ctypes.data, px, ldx.ctypes.data, ctypes.byref(o),
                                       _stream_ptr(stream, torch)), "expm_pfd_apply_batched")
     return Xs
+
+
+class BatchPlan:
+    """Owns an expm_pfd_batch_t and the host arrays of its problem shapes."""
+
+    def __init__(self, handle, n, m):
+        self.handle = handle
+        self.n, self.m = n, m
+        self._keep = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                expm_pfd_batch_destroy(self)
+        except Exception:
+            pass
+
+
+def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precision="fp64", ir_sweeps: int = 0,
+                        graph: bool = False, autotune: bool = False, lu_tile=None,
+                        real_data: bool = False) -> BatchPlan:
+    """Batch plan for problems of orders n[i] with m[i] right-hand-side columns (0: V_i = I)."""
+    lib = load_library()
+    nn = np.ascontiguousarray(n, dtype=np.int64)
+    mm = np.ascontiguousarray(m, dtype=np.int64)
+    if nn.shape != mm.shape:
+        raise ValueError("n and m must have the same length")
+    h = ctypes.c_void_p()
+    o = _opts(precision, ir_sweeps, 0, 0.0, real_data, graph, autotune, lu_tile)
+    _check(lib.expm_pfd_batch_plan(ctypes.byref(h), len(nn), nn.ctypes.data, mm.ctypes.data, int(degree),
+                                   ctypes.byref(o)), "expm_pfd_batch_plan")
+    return BatchPlan(h.value, nn, mm)
+
+
+def expm_pfd_batch_apply(b: BatchPlan, As: Sequence, Vs: Sequence, ts: Sequence[float], Xs=None, stream=None):
+    """X_i = R_d(t_i A_i) V_i on the plan's problems (V_i None where m[i] = 0).  Returns the list of X_i.
+
+    The inputs (and any column-major copies made here) are kept alive on the plan
+    until its next apply, so the asynchronous launches can read them."""
+    import torch
+
+    lib = load_library()
+    count = len(b.n)
+    if len(As) != count or len(Vs) != count or len(ts) != count:
+        raise ValueError("one A, V and t per problem of the plan")
+    Ac, Vc, out = [], [], []
+    lda = np.zeros(count, np.int64)
+    ldv = np.zeros(count, np.int64)
+    ldx = np.zeros(count, np.int64)
+    t = np.asarray(ts, dtype=np.float64)
+    pa = (ctypes.c_void_p * count)()
+    pv = (ctypes.c_void_p * count)()
+    px = (ctypes.c_void_p * count)()
+    for i in range(count):
+        a, la = _colmajor(As[i], torch)
+        if a.shape[0] != b.n[i]:
+            raise ValueError(f"A[{i}] has order {a.shape[0]}, the plan {b.n[i]}")
+        Ac.append(a)
+        lda[i], pa[i] = la, a.data_ptr()
+        cols = int(b.m[i]) if b.m[i] else int(b.n[i])
+        if Vs[i] is None:
+            Vc.append(None)
+            ldv[i], pv[i] = b.n[i], None
+        else:
+            v, lv = _colmajor(Vs[i], torch)
+            Vc.append(v)
+            ldv[i], pv[i] = lv, v.data_ptr()
+        x = Xs[i] if Xs is not None else torch.empty((cols, int(b.n[i])), dtype=torch.complex128,
+                                                      device=a.device).t()
+        if not (x.stride(0) == 1 and tuple(x.shape) == (int(b.n[i]), cols)):
+            raise ValueError("X must be column-major (n, m) complex128")
+        out.append(x)
+        ldx[i], px[i] = x.stride(1), x.data_ptr()
+    _check(lib.expm_pfd_batch_apply(b.handle, t.ctypes.data, pa, lda.ctypes.data, pv, ldv.ctypes.data, px,
+                                    ldx.ctypes.data, _stream_ptr(stream, torch)), "expm_pfd_batch_apply")
+    b._keep = (Ac, Vc, out)
+    return out
+
+
+def expm_pfd_batch_check(b: BatchPlan):
+    _check(load_library().expm_pfd_batch_check(b.handle), "expm_pfd_batch_check")
+
+
+def expm_pfd_batch_info(b: BatchPlan) -> dict:
+    g, s, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().expm_pfd_batch_info(b.handle, ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)),
+           "expm_pfd_batch_info")
+    return {"groups": g.value, "schedule": s.value, "lu_tile_max": LU_TILES[t.value]}
+
+
+def expm_pfd_batch_destroy(b: BatchPlan):
+    if b.handle:
+        _check(load_library().expm_pfd_batch_destroy(b.handle), "expm_pfd_batch_destroy")
+        b.handle = None
+        b._keep = None
 
 
 def expm_pfd_trace(classes=()):
