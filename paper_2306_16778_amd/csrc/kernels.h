@@ -373,42 +373,55 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
 // ---------------------------------------------------------------------------
 // Inverses of the nb x nb diagonal blocks of the LU factors: L11^{-1} (unit
 // lower) and U11^{-1} (upper), so that the triangular solves of the update and
-// the sweeps run as matrix-core products.  One wave per column of an inverse:
-// lane i holds row i; forward (L) or backward (U) substitution with the
-// current pivot value broadcast by readlane.  Four columns per wave are
-// carried together to overlap the dependency chains.
-// grid (16 * nsteps_range * (1 or 2), batch), block 64; blockIdx.x encodes
-// (step, L or U, group of 4 columns).
+// the sweeps run as matrix-core products.  One wave per group of four columns
+// of an inverse: lane i holds row i; forward (L) or backward (U) substitution
+// with the current pivot value broadcast by readlane, the four columns carried
+// together to overlap their dependency chains.  A workgroup of BI_WAVES waves
+// loads the diagonal block into LDS once (coalesced rows) and covers
+// 4*BI_WAVES columns; the result is staged back through LDS and written as
+// whole rows.
+// grid (16/BI_WAVES * nsteps_range * (1 or 2), batch), block 64*BI_WAVES;
+// blockIdx.x encodes (step, L or U, group of 4*BI_WAVES columns).
 // ---------------------------------------------------------------------------
+constexpr int BI_WAVES = 4;
+
 template <typename R>
-__global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld,
-                                                      int step0, int which, cx<R>* __restrict__ dinvb,
-                                                      int64_t dstride) {
+__global__ __launch_bounds__(64 * BI_WAVES) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride,
+                                                                 int64_t ld, int step0, int which,
+                                                                 cx<R>* __restrict__ dinvb, int64_t dstride) {
   using T = cx<R>;
-  constexpr int NB = NB_MAX;
+  constexpr int NB = NB_MAX, NT = 64 * BI_WAVES, GROUPS = 16 / BI_WAVES;
   __shared__ T D[NB][NB + 1];
   __shared__ T rdiag[NB];
   const int nmat = which == 2 ? 2 : 1;  // which: 0 = L only, 1 = U only, 2 = both
   const int g = blockIdx.x;
-  const int cgrp = g % 16;
-  const int mat = (g / 16) % nmat;
-  const int step = step0 + g / (16 * nmat);
+  const int wg = g % GROUPS;
+  const int mat = (g / GROUPS) % nmat;
+  const int step = step0 + g / (GROUPS * nmat);
   const bool upper = which == 1 || (which == 2 && mat == 1);
   const int b = blockIdx.y;
   const T* W = Wb + b * wstride;
   const int j0 = step * NB;
-  const int lane = threadIdx.x;
-  // the 64 x 64 diagonal block into LDS, 16 loads in flight per lane at a time
-  // (lane = column, so each load instruction reads one row segment)
-  for (int i0 = 0; i0 < NB; i0 += 16) {
-    T v[16];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int cgrp = wg * BI_WAVES + (tid >> 6);  // this wave's four columns: 4*cgrp ..
+  // the 64 x 64 diagonal block into LDS: every load issued before the first
+  // store (consecutive threads read consecutive columns of a row)
+  {
+    constexpr int PER = NB * NB / NT;
+    T v[PER];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = W[(int64_t)(j0 + i0 + u) * ld + j0 + lane];
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + NT * u;
+      v[u] = W[(int64_t)(j0 + e / NB) * ld + j0 + e % NB];
+    }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) D[i0 + u][lane] = v[u];
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + NT * u;
+      D[e / NB][e % NB] = v[u];
+    }
   }
   __syncthreads();
-  if (upper) rdiag[lane] = crecip(D[lane][lane]);
+  if (upper && tid < NB) rdiag[tid] = crecip(D[tid][tid]);
   __syncthreads();
   T one = czero<T>();
   one.x = 1;
@@ -439,12 +452,22 @@ __global__ __launch_bounds__(64) void k_block_inverse(const cx<R>* __restrict__ 
       }
     }
   }
-  T* out = dinvb + b * dstride + (int64_t)step * 2 * NB * NB + (upper ? NB * NB : 0);
+  __syncthreads();  // every wave is done reading the block: D takes the result
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = cgrp * 4 + q;
     const bool keep = upper ? (i <= c) : (i >= c);
-    out[i * NB + c] = keep ? x[q] : czero<T>();
+    D[i][c] = keep ? x[q] : czero<T>();
+  }
+  __syncthreads();
+  // the workgroup's 4*BI_WAVES columns of every row, written as row segments
+  T* out = dinvb + b * dstride + (int64_t)step * 2 * NB * NB + (upper ? NB * NB : 0);
+  constexpr int CW = 4 * BI_WAVES;
+#pragma unroll
+  for (int u = 0; u < NB * CW / NT; ++u) {
+    const int e = tid + NT * u;
+    const int r = e / CW, c = wg * CW + e % CW;
+    out[r * NB + c] = D[r][c];
   }
 }
 
