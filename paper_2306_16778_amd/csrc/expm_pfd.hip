@@ -44,6 +44,9 @@ namespace {
 
 constexpr int NB = 64;  // outer panel width (also the padding granularity)
 constexpr int CHAIN_MP_MAX = 64;  // widest right-hand-side block solved by one-launch sweeps
+// from this many 16-column chains on, a sweep runs one workgroup per chain
+// (k_sweep_whole) instead of one per tile position (k_sweep_chain)
+constexpr int WHOLE_CHAIN_MIN = 256;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -717,8 +720,12 @@ void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoin
     trace::Scope ts(st, EXPM_PFD_K_SOLVE_GEMM, 8.0 * nchain * tiles * NB * NB * 16,
                     e * nblk * tiles * NB * NB + 2.0 * e * nchain * npad * 16);
     const unsigned nwg = (unsigned)nchain * (unsigned)nsteps;
-    hipLaunchKernelGGL((k_sweep_chain<R>), dim3(nwg), dim3(256), 0, st, fwd ? 1 : 0, nsteps, nchain, cpb, d0, d1, a0,
-                       a1, PB, X, (int64_t)mp, ldS, pl->sweep_sync);
+    if (nchain >= WHOLE_CHAIN_MIN)
+      hipLaunchKernelGGL((k_sweep_whole<R>), dim3((unsigned)nchain), dim3(256), 0, st, fwd ? 1 : 0, nsteps, cpb, d0,
+                         d1, a0, a1, PB, X, (int64_t)mp, ldS);
+    else
+      hipLaunchKernelGGL((k_sweep_chain<R>), dim3(nwg), dim3(256), 0, st, fwd ? 1 : 0, nsteps, nchain, cpb, d0, d1,
+                         a0, a1, PB, X, (int64_t)mp, ldS, pl->sweep_sync);
   }
   if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
 }

@@ -863,7 +863,10 @@ __device__ __forceinline__ void chain_publish(cx<R> (*Xs)[17], cx<R>* x, int64_t
 // brought into LDS once per workgroup after its flag is seen.  FP32 slices are
 // loaded before each wait (their loads overlap it); FP64 slices chunk by chunk
 // after it, which keeps the registers for three workgroups per CU.
-template <typename R, bool CONJ>
+// Without WAIT (one workgroup walks the whole chain and wrote every x_J
+// itself) a barrier replaces the wait: the previous block's LDS reads end
+// before x_J is filled in.
+template <typename R, bool CONJ, bool WAIT>
 __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nsteps, const cx<R>* W, int64_t ld,
                                                  const cx<R>* Xc, int64_t ldx, int row0, const int* fl, int epoch,
                                                  int* status, cx<R> (*Xs)[17], typename Mfma<R>::V& accR,
@@ -880,7 +883,10 @@ __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nste
       T a[32];
 #pragma unroll
       for (int k8 = 0; k8 < 32; k8 += 8) load_chunk<R, CONJ>(Ablk, ld, row0, k8, a + k8);
-      chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      if constexpr (WAIT)
+        chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      else
+        __syncthreads();
       chain_fill<R>(Xc + (int64_t)(J * NB) * ldx, ldx, Xs);
       __syncthreads();
 #pragma unroll
@@ -891,7 +897,10 @@ __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nste
         mac8<R>(a + k8, bv, odd, accR, accI);
       }
     } else {
-      chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      if constexpr (WAIT)
+        chain_wait(fl + J * FLAG_STRIDE, epoch, status);
+      else
+        __syncthreads();
       chain_fill<R>(Xc + (int64_t)(J * NB) * ldx, ldx, Xs);
       __syncthreads();
 #pragma unroll
@@ -906,13 +915,14 @@ __device__ __forceinline__ void chain_accumulate(int q, int I, int fwd, int nste
   }
 }
 
-// One tile position of one chain of k_sweep_chain (all 256 threads of the
-// workgroup): wait for and accumulate the earlier blocks, apply D_I, publish x_I.
-template <typename R>
-__device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps, int nchain, int cpb,
-                                           SweepOperand<R> d0, SweepOperand<R> d1, SweepOperand<R> a0,
-                                           SweepOperand<R> a1, int split, cx<R>* X, int64_t sX, int64_t ldx,
-                                           int* flags, int epoch, int* status) {
+// Tile position q of chain c (all 256 threads of the workgroup): wait for (or,
+// without WAIT, read back) and accumulate the earlier blocks, apply D_I,
+// publish x_I.  Every store of x_I has completed when it returns.
+template <typename R, bool WAIT>
+__device__ __forceinline__ void sweep_tile(int q, int c, int fwd, int nsteps, int cpb, SweepOperand<R> d0,
+                                           SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1, int split,
+                                           cx<R>* X, int64_t sX, int64_t ldx, int* flags, int epoch,
+                                           int* status) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
@@ -923,7 +933,6 @@ __device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps,
   __shared__ T Xs[NB][17];  // x_J of the current dependency; finally x_I
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const int q = (int)(ticket / (unsigned)nchain), c = (int)(ticket % (unsigned)nchain);
   const int bb = c / cpb, c16 = c % cpb;
   const bool second = bb >= split;
   const int hb = second ? bb - split : bb;
@@ -931,7 +940,7 @@ __device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps,
   const SweepOperand<R> aop = second ? a1 : a0;
   const T* W = aop.p + hb * aop.stride;
   T* Xc = X + bb * sX + c16 * 16;
-  const int* fl = flags + (int64_t)c * nsteps * FLAG_STRIDE;
+  const int* fl = WAIT ? flags + (int64_t)c * nsteps * FLAG_STRIDE : nullptr;
   const int I = fwd ? q : nsteps - 1 - q;
   const int row0 = 16 * w;
   const T* D = dop.p + hb * dop.stride + (int64_t)I * 2 * NB * NB;
@@ -948,9 +957,10 @@ __device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps,
   for (int r = 0; r < 4; ++r) b[r] = Xc[(int64_t)(I * NB + row0 + MF::row(kq, r)) * ldx + r16];
   V accR = V{0, 0, 0, 0}, accI = V{0, 0, 0, 0};
   if (aop.conj)
-    chain_accumulate<R, true>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR, accI);
+    chain_accumulate<R, true, WAIT>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR, accI);
   else
-    chain_accumulate<R, false>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR, accI);
+    chain_accumulate<R, false, WAIT>(q, I, fwd, nsteps, W, aop.ld, Xc, ldx, row0, fl, epoch, status, Xs, accR,
+                                     accI);
   // r = b_I - acc, shared by the four waves for the diagonal-block product
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -993,7 +1003,8 @@ __device__ __forceinline__ void sweep_tile(unsigned ticket, int fwd, int nsteps,
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (tid == 0) __hip_atomic_store((int*)fl + I * FLAG_STRIDE, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (WAIT)
+    if (tid == 0) __hip_atomic_store((int*)fl + I * FLAG_STRIDE, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Solution blocks are handed between workgroups without cache maintenance:
@@ -1018,8 +1029,9 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
   __syncthreads();
   const unsigned ticket = (unsigned)__builtin_amdgcn_readfirstlane((int)s_ticket);
   const int epoch = __builtin_amdgcn_readfirstlane(s_epoch);
-  if (ticket < total) sweep_tile<R>(ticket, fwd, nsteps, nchain, cpb, d0, d1, a0, a1, split, X, sX, ldx, flags, epoch,
-                                    status);
+  if (ticket < total)
+    sweep_tile<R, true>((int)(ticket / (unsigned)nchain), (int)(ticket % (unsigned)nchain), fwd, nsteps, cpb, d0, d1,
+                        a0, a1, split, X, sX, ldx, flags, epoch, status);
   else if (tid == 0)
     atomicOr(status, 2);
   // the last workgroup to finish re-arms the control line for the next launch
@@ -1029,6 +1041,23 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
     __hip_atomic_store(ctl + SW_DONE, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(ctl + SW_EPOCH, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// ---------------------------------------------------------------------------
+// The same sweep with one workgroup per chain walking all of its tile
+// positions in order: no tickets, flags or waits.  The arithmetic of every
+// tile is that of k_sweep_chain (same blocks, same order), so both give the
+// same bits; this form wins when there are enough chains to fill the device
+// (many shifted matrices, short chains), the ticketed one when there are few.
+// grid (nchain), block 256.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_sweep_whole(int fwd, int nsteps, int cpb, SweepOperand<R> d0,
+                                                     SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
+                                                     int split, cx<R>* X, int64_t sX, int64_t ldx) {
+  const int c = blockIdx.x;
+  for (int q = 0; q < nsteps; ++q)
+    sweep_tile<R, false>(q, c, fwd, nsteps, cpb, d0, d1, a0, a1, split, X, sX, ldx, nullptr, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -74,3 +74,30 @@ def test_batched_equals_alone(ep, precision):
         X1 = ep.expm_pfd_apply(plan, _dev(A), None if V is None else _dev(V))
         torch.cuda.synchronize()
         assert np.array_equal(X1.cpu().numpy(), Xb.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_many_chains_sweep_equals_alone(ep, precision, tol):
+    """24 problems of one padded order: 384 sixteen-column chains per sweep, so the
+    sweeps run one workgroup per chain; alone, a problem has 16 chains and runs
+    the ticketed one-launch sweep.  Both give the same bits and match the oracle."""
+    import torch
+    rng = np.random.default_rng(9)
+    probs = []
+    for k in range(24):
+        n = 130 + 5 * (k % 12)
+        A = wl.hermitian_with_spectrum(rng, rng.uniform(-50.0, 0.0, n))
+        probs.append((A, wl.complex_gaussian(rng, n, 4), float(rng.uniform(0.1, 1.0))))
+    _announce(f"many-chains batch {precision} {len(probs)} problems")
+    Xs = ep.expm_pfd_apply_batched([_dev(A) for A, _, _ in probs], [_dev(V) for _, V, _ in probs],
+                                   [t for _, _, t in probs], 16, precision)
+    torch.cuda.synchronize()
+    for k, ((A, V, t), Xb) in enumerate(zip(probs, Xs)):
+        Xb = Xb.cpu().numpy()
+        if k % 6 == 0:
+            assert matrix.rel_fro(Xb, matrix.expm_R(A, V, t, 16)) < tol
+        if k % 8 == 0:
+            plan = ep.expm_pfd_plan(A.shape[0], 16, t, 4, precision)
+            X1 = ep.expm_pfd_apply(plan, _dev(A), _dev(V))
+            torch.cuda.synchronize()
+            assert np.array_equal(X1.cpu().numpy(), Xb)
