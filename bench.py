@@ -40,33 +40,43 @@ METRIC = "exp(tA)V solves/s at rel err<=1e-10, mixed vs FP64 GPU path; p50/p99 l
 PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 
 
-KERNEL_SOURCES = ("device_common.h", "kernels.h", "expm_pfd.hip")
 # HBM bytes per launch of the dominant kernel, from one FETCH_SIZE and one
 # WRITE_SIZE counter pass, each scaled by what the counter reads for a plain
-# copy kernel of known size (read 0.50005 x, write 1.0 x the true bytes);
-# valid for the kernel sources with this digest only, otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 58.01e6 + 34.64e6, "sources_sha256": "5f3ce0dbace2f501f479843cc94f71e57729ff7c9fb1161863cf4e9f9e07708a"}}
+# copy kernel of known size; valid only while the sources that decide what the
+# kernel reads and writes per launch hash to the digest below (the kernel, its
+# device helpers, the launcher and the factorization steps that choose the
+# launch shapes), otherwise reported null
+TRAFFIC = {"mixed": {"bytes_per_launch": 35.84e6 + 17.25e6,
+                     "sources_sha256": "bfc2ed5aa4cf5821d33c3fe63527a413b47bf2a66f0e8ba37ab870c7f068cbf9"}}
+
+# (file, first marker, end marker) of each source span in the digest
+TRAFFIC_SPANS = (
+    ("device_common.h", None, None),
+    ("kernels.h", b"struct KSplit {", b"// A whole block triangular sweep"),
+    ("expm_pfd.hip", b"void gemm(", b"\n}\n"),
+    ("expm_pfd.hip", b"void panel_phase(", b"// ---- solves on all right-hand-side blocks"),
+)
 
 
 def kernel_sources_digest():
-    """Digest of the kernels' source and of the launcher that picks the GEMM tiles
-    (the rest of the host code does not change what the kernel reads or writes)."""
+    """Digest of the source spans that decide the dominant kernel's per-launch
+    traffic (TRAFFIC_SPANS)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f, a, b in TRAFFIC_SPANS:
         with open(os.path.join(ROOT, "paper_2306_16778_amd", "csrc", f), "rb") as fh:
             text = fh.read()
-        if f.endswith(".hip"):
-            a = text.index(b"void gemm(")
-            text = text[a:text.index(b"\n}\n", a)]
+        if a is not None:
+            i = text.index(a)
+            text = text[i:text.index(b, i)]
         h.update(text)
     return h.hexdigest()
 
 
 def measured_traffic(precision):
     t = TRAFFIC.get(precision)
-    if t is None or t["sources_sha256"] != kernel_sources_digest():
+    if t is None or t["bytes_per_launch"] is None or t["sources_sha256"] != kernel_sources_digest():
         return None
     return t["bytes_per_launch"]
 
@@ -78,7 +88,7 @@ def algorithmic_flops(n, m, degree):
     return P * (8.0 / 3.0) * n ** 3 + 2 * P * 8.0 * n * n * m
 
 
-def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
+def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup, graph=True):
     n, m, d = prob.A.shape[0], prob.V.shape[1], prob.degree
     plan = ep.expm_pfd_plan(n, d, prob.t, m, precision)
     X = torch.empty((m, n), dtype=torch.complex128, device="cuda").t()
@@ -106,6 +116,8 @@ def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
     breakdown = {c: ep.expm_pfd_trace_summary(c) for c in ep.KERNEL_CLASSES}
     ep.expm_pfd_trace([])
     Xh = X.cpu().numpy()
+    if not graph:
+        return finish_path(Xh, steps, wall, dom, lat, breakdown, n, m, d, precision, None)
     # the same steps replayed from a captured graph, LU tile autotuned (extra field)
     gplan = ep.expm_pfd_plan(n, d, prob.t, m, precision, graph=True, autotune=True)
     Xg = torch.empty((m, n), dtype=torch.complex128, device="cuda").t()
@@ -119,7 +131,11 @@ def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
     graph_ms = (time.perf_counter() - t0) * 1e3 / steps
     graph_same_bits = bool(torch.equal(Xg, X))
     del gplan
+    return finish_path(Xh, steps, wall, dom, lat, breakdown, n, m, d, precision,
+                       {"ms_per_step": graph_ms, "same_bits_as_direct": graph_same_bits})
 
+
+def finish_path(Xh, steps, wall, dom, lat, breakdown, n, m, d, precision, graph):
     def pct(q):
         i = min(len(lat) - 1, max(0, int(round(q * (len(lat) - 1)))))
         return lat[i]
@@ -147,7 +163,7 @@ def run_path(ep, torch, prob, Ad, Vd, precision, steps, warmup):
             "flops_per_launch": dom["flops"] / max(dom["launches"], 1),
         },
         "breakdown_ms_per_step": {c: round(v["ms"], 4) for c, v in breakdown.items() if v["launches"]},
-        "graph_replay_autotuned": {"ms_per_step": graph_ms, "same_bits_as_direct": graph_same_bits},
+        "graph_replay_autotuned": graph,
     }
 
 
@@ -307,6 +323,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-qps", type=float, default=100.0)
     ap.add_argument("--paths", default="mixed,fp64", help="precision paths to time (mixed first: the reported value)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replayed, autotuned variant of the main paths")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched workload (prints its JSON object; for kernel profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB copy kernel first (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -328,6 +348,10 @@ def main():
     if "mixed" not in paths or any(p not in ("mixed", "fp64") for p in paths):
         print("--paths must include mixed (the reported value) and may add fp64", file=sys.stderr)
         sys.exit(2)
+    if args.batched_only:
+        from oracle import matrix
+        print(json.dumps({"batched": batched_section(ep, torch, workloads, matrix)}), flush=True)
+        return
     prob = workloads.config2_fp64_at_scale()
     n, m = prob.V.shape
     Ad = torch.from_numpy(np.asfortranarray(prob.A)).to("cuda")
@@ -335,7 +359,7 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] workload n={n} m={m} degree={prob.degree}; timing {' then '.join(paths)} "
           f"({args.warmup} warmup + {args.steps} steps each)", file=sys.stderr, flush=True)
-    res = {p: run_path(ep, torch, prob, Ad, Vd, p, args.steps, args.warmup) for p in paths}
+    res = {p: run_path(ep, torch, prob, Ad, Vd, p, args.steps, args.warmup, not args.no_graph) for p in paths}
     print("[bench] GPU timing done", file=sys.stderr, flush=True)
 
     cpu = None
