@@ -249,7 +249,8 @@ int expm_pfd_batch_destroy(expm_pfd_batch_t b);
  * the stream the kernel is launched on). */
 #define EXPM_PFD_K_FORM        0  /* shifted-matrix formation */
 #define EXPM_PFD_K_PANEL       1  /* register-resident panel factorization */
-#define EXPM_PFD_K_LU_GEMM     2  /* LU updates C -= L21 U12 (in-panel and trailing), 64x64 complex tiles */
+#define EXPM_PFD_K_LU_GEMM     2  /* LU updates C -= L21 U12 inside the outer panels and the narrow
+                                      ones a step applies early (64x64 complex tiles) */
 #define EXPM_PFD_K_LU_TRSM     3  /* LU U12 = L11^{-1} A12 as a product with the block inverse */
 #define EXPM_PFD_K_MOVES       4  /* row moves (left columns, right-hand sides) */
 #define EXPM_PFD_K_SOLVE_TRSM  5  /* (unused; diagonal blocks are applied inside the sweeps) */
@@ -257,7 +258,9 @@ int expm_pfd_batch_destroy(expm_pfd_batch_t b);
 #define EXPM_PFD_K_ACCUM       7  /* residue-weighted accumulation */
 #define EXPM_PFD_K_IR_GEMM     8  /* refinement residual product (FP64) */
 #define EXPM_PFD_K_ELEMENTWISE 9  /* staging, conversions, shift, correction */
-#define EXPM_PFD_K_COUNT      10
+#define EXPM_PFD_K_LU_TRAIL   10  /* LU trailing updates A22 -= L21 U12 over the whole trailing
+                                     matrix (two steps at a time: K = 128) */
+#define EXPM_PFD_K_COUNT      11
 
 /*
  * expm_pfd_trace: time every later launch of the kernel classes whose bit is set

@@ -215,7 +215,7 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
     else
       hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
   };
-  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRSM) {
+  if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRAIL && cls != EXPM_PFD_K_LU_TRSM) {
     launch(k_gemm<R, MODE, 64, 16, 4, 1>, dim3((unsigned)((M + 63) / 64), gy));
     return;
   }
@@ -226,6 +226,10 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
     }
     if (tile == 2) {
       launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
+      return;
+    }
+    if (cls == EXPM_PFD_K_LU_TRAIL) {
+      launch(k_gemm<R, MODE, 64, 64, 2, 2, 1>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
       return;
     }
   }
@@ -494,7 +498,7 @@ int tune_lu_tile_t(expm_pfd_plan_t pl) {
   float best_ms = 0.f;
   for (int tile = 0; tile < LU_TILES; ++tile) {
     auto once = [&] {
-      gemm<R, 0>(s, EXPM_PFD_K_LU_GEMM, PB, M, M, K, opnd<R>(W + (int64_t)K * ld, ws, ld, false),
+      gemm<R, 0>(s, EXPM_PFD_K_LU_TRAIL, PB, M, M, K, opnd<R>(W + (int64_t)K * ld, ws, ld, false),
                  opnd<R>(nullptr, 0, 0, false), PB, W + K, ws, ld, W + (int64_t)K * ld + K, ws, ld, {1, 0, 0, 0},
                  tile);
     };
@@ -596,7 +600,7 @@ void step_update(expm_pfd_plan_t pl, int step, hipStream_t st) {
   const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
   gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
              PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
-  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
+  gemm<R, 0>(st, EXPM_PFD_K_LU_TRAIL, PB, ntr, ntr, nbo, opnd<R>(W + c1 * ld + j0, ws, ld, false),
              opnd<R>(nullptr, 0, 0, false), PB, W + (int64_t)j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld,
              {1, 0, 0, 0}, pl->lu_tile);
 }
@@ -645,7 +649,7 @@ void step_pair(expm_pfd_plan_t pl, int step, hipStream_t st) {
              opnd<R>(dinv + (int64_t)(step + 1) * 2 * NB * NB, ds, NB, false), opnd<R>(nullptr, 0, 0, false), PB,
              W + c1 * ld + c2, ws, ld, W + c1 * ld + c2, ws, ld);
   // both steps' update of the trailing matrix
-  gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, ntr2, ntr2, NB + nb2, opnd<R>(W + c2 * ld + j0, ws, ld, false),
+  gemm<R, 0>(st, EXPM_PFD_K_LU_TRAIL, PB, ntr2, ntr2, NB + nb2, opnd<R>(W + c2 * ld + j0, ws, ld, false),
              opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c2 * ld + c2, ws, ld, {1, 0, 0, 0},
              pl->lu_tile);
 }

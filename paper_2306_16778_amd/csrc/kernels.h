@@ -512,7 +512,9 @@ constexpr int gemm_waves() {
   return (sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64) / (BM * BN > 64 * 64 ? 2 : 1);
 }
 
-template <typename R, int MODE, int BM, int BN, int WGM, int WGN>
+// TAG only names a separate instantiation of the same code (the LU trailing
+// update uses TAG 1), so kernel traces and counters tell it apart.
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
                                               int64_t ldc, KSplit ksp) {

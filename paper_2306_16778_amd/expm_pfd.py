@@ -54,7 +54,7 @@ EXPORTED = (
 
 # kernel classes of the tracer (EXPM_PFD_K_*)
 KERNEL_CLASSES = ("form", "panel", "lu_gemm", "lu_trsm", "moves", "solve_trsm", "solve_gemm", "accum",
-                  "ir_gemm", "elementwise")
+                  "ir_gemm", "elementwise", "lu_trail")
 
 
 class ExpmPfdError(RuntimeError):
