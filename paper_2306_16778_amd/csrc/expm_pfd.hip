@@ -228,7 +228,9 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
       launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
       return;
     }
-    if (cls == EXPM_PFD_K_LU_TRAIL) {
+    // the trailing update's own instantiation needs whole tiles and chunks (always
+    // so: padded orders and panel widths are multiples of 64); otherwise the general one
+    if (cls == EXPM_PFD_K_LU_TRAIL && M % 64 == 0 && N % 64 == 0 && K % 16 == 0 && a0.conj == 0) {
       launch(k_gemm<R, MODE, 64, 64, 2, 2, 1>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
       return;
     }

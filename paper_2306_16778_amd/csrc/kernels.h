@@ -512,8 +512,11 @@ constexpr int gemm_waves() {
   return (sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64) / (BM * BN > 64 * 64 ? 2 : 1);
 }
 
-// TAG only names a separate instantiation of the same code (the LU trailing
-// update uses TAG 1), so kernel traces and counters tell it apart.
+// TAG 1 is the LU trailing update: a separate instantiation (so kernel traces
+// and counters tell it apart) compiled for whole tiles and chunks (M, N
+// multiples of 64, K of 16: no bounds checks or zero scaling) and an operand
+// that is never conjugated, which keeps the operand fetch free of branches.
+// The launcher uses it only for shapes that satisfy this.
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
@@ -522,6 +525,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
   using MF = Mfma<R>;
   using V = typename MF::V;
   constexpr int KC = 16;
+  constexpr bool FULL = TAG == 1;  // whole tiles and chunks, no conjugation (checked by the launcher)
   constexpr int WM = BM / WGM, WN = BN / WGN, MI = WM / 16, NJ = WN / 16;
   constexpr int AE = BM * KC / 256, BE = KC * BN / 256;  // chunk elements per thread
   static_assert(WGM * WGN == 4, "four waves");
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
   const GemmOperand<R> op = second ? a1 : a0;
   const T* A = op.p + (second ? bb - split : bb) * op.stride + ks * ksp.kA;
   const int64_t lda = op.ld;
-  const bool conj = op.conj != 0;
+  const bool conj = !FULL && op.conj != 0;
   B += bb * sB + ks * ksp.kB;
   C += bb * sC + ks * ksp.kC;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -567,7 +571,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
     for (int q = 0; q < AE; ++q) {
       const int e = tid + 256 * q;
       const int i = conj ? e % BM : e / KC, k = conj ? e / BM : e % KC;
-      const bool ok = m0 + i < M && k0 + k < K;
+      const bool ok = FULL || (m0 + i < M && k0 + k < K);
       const int64_t idx = !ok ? 0 : conj ? (int64_t)(k0 + k) * lda + m0 + i : (int64_t)(m0 + i) * lda + k0 + k;
       ra[q] = A[idx];
       fa[q] = ok ? R(1) : R(0);
@@ -576,7 +580,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
     for (int q = 0; q < BE; ++q) {
       const int e = tid + 256 * q;
       const int j = e % BN, k = e / BN;
-      const bool ok = n0 + j < N && k0 + k < K;
+      const bool ok = FULL || (n0 + j < N && k0 + k < K);
       rb[q] = B[ok ? (int64_t)(k0 + k) * ldb + n0 + j : 0];
       fb[q] = ok ? R(1) : R(0);
     }
@@ -586,8 +590,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
     for (int q = 0; q < AE; ++q) {
       const int e = tid + 256 * q;
       T v;
-      v.x = ra[q].x * fa[q];
-      v.y = (conj ? -ra[q].y : ra[q].y) * fa[q];
+      v.x = FULL ? ra[q].x : ra[q].x * fa[q];
+      v.y = FULL ? ra[q].y : (conj ? -ra[q].y : ra[q].y) * fa[q];
       if (!conj)
         As[buf][e / KC][e % KC] = v;
       else
@@ -597,8 +601,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
     for (int q = 0; q < BE; ++q) {
       const int e = tid + 256 * q;
       T v;
-      v.x = rb[q].x * fb[q];
-      v.y = rb[q].y * fb[q];
+      v.x = FULL ? rb[q].x : rb[q].x * fb[q];
+      v.y = FULL ? rb[q].y : rb[q].y * fb[q];
       Bs[buf][e / BN][e % BN] = v;
     }
   };
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
         for (int r = 0; r < 4; ++r) {
           const int row = m0 + wm0 + i * 16 + MF::row(kq, r);
           const int col = n0 + wn0 + j * 16 + r16;
-          const bool ok = row < M && col < N;
+          const bool ok = FULL || (row < M && col < N);
           cold[i][j][r] = C[ok ? (int64_t)row * ldc + col : 0];
         }
   }
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
           c.x = accR[i][j][r];
           c.y = accI[i][j][r];
         }
-        if (row < M && col < N) C[(int64_t)row * ldc + col] = c;
+        if (FULL || (row < M && col < N)) C[(int64_t)row * ldc + col] = c;
       }
 }
 
