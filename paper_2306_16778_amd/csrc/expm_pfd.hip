@@ -220,12 +220,19 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
     return;
   }
   if constexpr (MODE == 0) {
+    const bool trail = cls == EXPM_PFD_K_LU_TRAIL && K % 16 == 0 && a0.conj == 0;
     if (tile == 1) {
-      launch(k_gemm<R, MODE, 128, 64, 2, 2>, dim3((unsigned)(((M + 127) / 128) * ((N + 63) / 64)), gy));
+      if (trail && M % 128 == 0 && N % 64 == 0)
+        launch(k_gemm<R, MODE, 128, 64, 2, 2, 1>, dim3((unsigned)((M / 128) * (N / 64)), gy));
+      else
+        launch(k_gemm<R, MODE, 128, 64, 2, 2>, dim3((unsigned)(((M + 127) / 128) * ((N + 63) / 64)), gy));
       return;
     }
     if (tile == 2) {
-      launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
+      if (trail && M % 64 == 0 && N % 128 == 0)
+        launch(k_gemm<R, MODE, 64, 128, 2, 2, 1>, dim3((unsigned)((M / 64) * (N / 128)), gy));
+      else
+        launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
       return;
     }
     // the trailing update's own instantiation needs whole tiles and chunks (always

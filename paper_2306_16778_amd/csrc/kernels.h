@@ -513,8 +513,8 @@ constexpr int gemm_waves() {
 }
 
 // TAG 1 is the LU trailing update: a separate instantiation (so kernel traces
-// and counters tell it apart) compiled for whole tiles and chunks (M, N
-// multiples of 64, K of 16: no bounds checks or zero scaling) and an operand
+// and counters tell it apart) compiled for whole tiles and chunks (M a multiple
+// of BM, N of BN, K of 16: no bounds checks or zero scaling) and an operand
 // that is never conjugated, which keeps the operand fetch free of branches.
 // The launcher uses it only for shapes that satisfy this.
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
