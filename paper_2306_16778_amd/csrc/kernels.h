@@ -512,11 +512,13 @@ constexpr int gemm_waves() {
   return (sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64) / (BM * BN > 64 * 64 ? 2 : 1);
 }
 
-// TAG 1 is the LU trailing update: a separate instantiation (so kernel traces
-// and counters tell it apart) compiled for whole tiles and chunks (M a multiple
-// of BM, N of BN, K of 16: no bounds checks or zero scaling) and an operand
-// that is never conjugated, which keeps the operand fetch free of branches.
-// The launcher uses it only for shapes that satisfy this.
+// TAG 1 (the LU trailing update) and TAG 2 (the other LU products with whole
+// tiles: the narrow K = 64 updates and U12 = L11^-1 A12) are instantiations
+// compiled for whole tiles and chunks (M a multiple of BM, N of BN, K of 16: no
+// bounds checks or zero scaling) and an operand that is never conjugated, which
+// keeps the operand fetch free of branches; separate instantiations so kernel
+// traces and counters tell them apart.  The launcher uses them only for shapes
+// that satisfy this.
 template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
                                               const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
   using MF = Mfma<R>;
   using V = typename MF::V;
   constexpr int KC = 16;
-  constexpr bool FULL = TAG == 1;  // whole tiles and chunks, no conjugation (checked by the launcher)
+  constexpr bool FULL = TAG >= 1;  // whole tiles and chunks, no conjugation (checked by the launcher)
   constexpr int WM = BM / WGM, WN = BN / WGN, MI = WM / 16, NJ = WN / 16;
   constexpr int AE = BM * KC / 256, BE = KC * BN / 256;  // chunk elements per thread
   static_assert(WGM * WGN == 4, "four waves");
