@@ -46,8 +46,8 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 # kernel reads and writes per launch hash to the digest below (the kernel, its
 # device helpers, the launcher and the factorization steps that choose the
 # launch shapes), otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 272.29e6 + 130.02e6,
-                     "sources_sha256": "011d26c2b4aba4d86746f101181ef3582ca457f9f92a8f63bd748d629b1662d4"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 272.28e6 + 130.02e6,
+                     "sources_sha256": "4a2031d2dc0f7ad1a8b131aa1874d09c973d25c6e9d800fa95eba3f69978ded1"}}
 
 # (file, first marker, end marker) of each source span in the digest
 TRAFFIC_SPANS = (
