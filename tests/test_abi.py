@@ -90,3 +90,32 @@ def test_workspace_bytes():
     # 12 shifted matrices dominate: 12 * 2048^2 * 16 bytes (FP64) or 8 bytes (FP32)
     assert 12 * n * n * 16 <= b64 < 12 * n * n * 16 * 1.1
     assert 12 * n * n * 8 + n * n * 16 <= bmx < b64
+
+
+def test_batch_and_option_validation_without_device():
+    """Batch plans and the speed options reject bad arguments before any device work."""
+    mod, lib = _lib()
+    h = ctypes.c_void_p()
+    o = mod._Opts()
+    n = np.array([64, 100, 33], dtype=np.int64)
+    m = np.array([4, 0, 1], dtype=np.int64)
+    assert lib.expm_pfd_batch_plan(None, 3, n.ctypes.data, m.ctypes.data, 16, None) == -3
+    assert lib.expm_pfd_batch_plan(ctypes.byref(h), 0, n.ctypes.data, m.ctypes.data, 16, None) == -2
+    assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, None, m.ctypes.data, 16, None) == -3
+    assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, n.ctypes.data, m.ctypes.data, 15, None) == -1
+    bad_m = np.array([4, 101, 1], dtype=np.int64)  # more columns than rows
+    assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, n.ctypes.data, bad_m.ctypes.data, 16, None) == -2
+    bad_n = np.array([64, 0, 33], dtype=np.int64)
+    assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, bad_n.ctypes.data, m.ctypes.data, 16, None) == -2
+    for tile in (-1, 4):
+        o.lu_tile = tile
+        assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+        assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, n.ctypes.data, m.ctypes.data, 16, ctypes.byref(o)) == -7
+    o.lu_tile = 0
+    assert lib.expm_pfd_batch_apply(None, None, None, None, None, None, None, None, None) == -3
+    assert lib.expm_pfd_batch_check(None) == -3
+    assert lib.expm_pfd_batch_destroy(None) == -3
+    assert lib.expm_pfd_batch_info(None, None, None, None) == -3
+    # option names of the binding map onto the C struct
+    assert mod._opts("mixed", 0, graph=True, autotune=True, lu_tile="64x128").lu_tile == 3
+    assert ctypes.sizeof(mod._Opts) == 4 * 8 + 8
