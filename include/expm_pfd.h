@@ -20,7 +20,8 @@
  *   - Matrices are column-major with a leading dimension (LAPACK convention):
  *     element (i, j) of A is A[i + j*lda].
  *   - A is Hermitian and only its LOWER triangle is read (the strictly upper
- *     part is never accessed; the imaginary part of the diagonal is ignored).
+ *     part is never accessed; the imaginary part of the diagonal is ignored),
+ *     or only its UPPER triangle with the option uplo = EXPM_PFD_UPPER.
  *   - Device pointers are HIP device (or managed) memory on the current device.
  *     The caller owns A, V and X; the library never writes A or V and never
  *     keeps a pointer to them after the call returns.
@@ -63,6 +64,8 @@ extern "C" {
 #define EXPM_PFD_MAX_N      8192
 
 /* ---- options ------------------------------------------------------------ */
+#define EXPM_PFD_LOWER 0  /* triangle of A that is read (expm_pfd_opts.uplo) */
+#define EXPM_PFD_UPPER 1
 #define EXPM_PFD_FP64  0  /* LU, solves and accumulation in complex FP64 */
 #define EXPM_PFD_MIXED 1  /* complex FP32 LU and solves on the matrix cores, FP64
                              iterative refinement of every shifted solve and FP64
@@ -97,7 +100,9 @@ typedef struct expm_pfd_opts {
   int lu_tile;     /* 0: built-in (64 x 64) or autotuned; k = 1..3 forces tile shape
                       k-1 of {64x64, 128x64, 64x128} (complex elements of C per
                       workgroup).  Other values: EXPM_PFD_ERR_ARG. */
-  int reserved;    /* set to 0 */
+  int uplo;        /* EXPM_PFD_LOWER (0, default): the lower triangle of A is read;
+                      EXPM_PFD_UPPER (1): the upper one.  The other triangle is
+                      never accessed.  Other values: EXPM_PFD_ERR_ARG. */
   double shift;    /* c of the shifting method (Remark rem:shift): the library
                       computes e^c R_d(tA - cI) V, so spectra of tA up to c are
                       covered by the negative-spectrum error bound of the
@@ -187,11 +192,15 @@ int expm_pfd_plan_check(expm_pfd_plan_t plan);
  * expm_pfd_batch_plan + expm_pfd_batch_apply + expm_pfd_batch_check +
  * expm_pfd_batch_destroy: device workspace is allocated inside the call and
  * released before it returns; the call synchronizes before returning.
+ *   info    host array of count ints, or NULL: per-problem status on return,
+ *           0 = result finite, 2 = X_i holds a non-finite value (non-finite
+ *           input; a zero pivot cannot occur for finite Hermitian A, since
+ *           |lambda + theta_k| >= |Im theta_k| > 0).
  */
 int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree,
                            const void* const* A, const int64_t* lda, const void* const* V,
                            const int64_t* ldv, const int64_t* m, void* const* X, const int64_t* ldx,
-                           const expm_pfd_opts* opts, void* stream);
+                           const expm_pfd_opts* opts, void* stream, int* info);
 
 /*
  * Batch plans: the workspace of a fixed set of problem shapes, allocated once
@@ -223,6 +232,9 @@ int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, cons
  *           ldv >= n[i] where V[i] is given).
  *   A, V, X host arrays of count device pointers, layouts as in expm_pfd_apply.
  *           V[i] must be NULL exactly where the plan has m[i] = 0.
+ *   info    device array of count ints, or NULL: per-problem status written
+ *           when the work completes (0 = finite result, 2 = non-finite values
+ *           in X_i, as for expm_pfd_apply_batched).
  * Asynchronous on `stream`: uploads the problem descriptors (from pinned
  * staging the plan owns; it waits only for the previous apply's upload) and
  * enqueues or replays the groups.  Concurrent applies of one batch plan race.
@@ -230,7 +242,7 @@ int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, cons
  */
 int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const void* const* A, const int64_t* lda,
                          const void* const* V, const int64_t* ldv, void* const* X, const int64_t* ldx,
-                         void* stream);
+                         int* info, void* stream);
 
 /* Synchronizes the device; then 0, or EXPM_PFD_ERR_SYNC if a triangular sweep of
  * any group lost its dependency order (see expm_pfd_plan_check), or _HIP. */

@@ -224,7 +224,9 @@ struct ProblemDesc {
   int64_t ldx;
   double t;
   int n, m;
-  int real;  // 1: A and V are real; their imaginary parts are not read
+  int real;   // 1: A and V are real; their imaginary parts are not read
+  int upper;  // 1: the upper triangle of A is read instead of the lower one
+  int* info;  // device word for this problem's status (0, or 2: non-finite result); may be null
 };
 // descriptor g of a group: from the device array, or the single inline one
 __device__ __forceinline__ ProblemDesc desc_of(const ProblemDesc* arr, const ProblemDesc& one, int g) {

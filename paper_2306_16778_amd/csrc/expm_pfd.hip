@@ -309,6 +309,7 @@ struct expm_pfd_plan_s {
   int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
   int ir_ext = 0;  // last sweeps with double-double residuals
   int real_data = 0;  // A and V real: conjugate poles need no solves of their own
+  int upper = 0;      // the upper triangle of A is read
   int Gcap = 1;  // problems the workspace was sized for; G <= Gcap is the active count
   double t = 1;
   bool full_ok = false;
@@ -371,6 +372,7 @@ int check_opts(const expm_pfd_opts* o) {
   if (!o) return 0;
   if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
   if (o->lu_tile < 0 || o->lu_tile > LU_TILES) return EXPM_PFD_ERR_ARG;
+  if (o->uplo != EXPM_PFD_LOWER && o->uplo != EXPM_PFD_UPPER) return EXPM_PFD_ERR_ARG;
   if (!std::isfinite(o->shift) || !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
   return 0;
 }
@@ -907,6 +909,8 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
     }
     accumulate(pl->X64);
   }
+  // per-problem status words (only written where the descriptor names one)
+  if (descs) hipLaunchKernelGGL(k_status, dim3((unsigned)G), dim3(256), 0, st, descs, one);
   return 0;
 }
 
@@ -960,6 +964,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   pl->n = n;
   pl->t = t;
   pl->m_max = m_max;
+  pl->upper = opts ? opts->uplo : 0;
   if ((rc = configure_plan(pl, opts)) != 0) {
     free_plan(pl);
     return rc;
@@ -991,6 +996,8 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   one.n = (int)pl->n;
   one.m = (int)m;
   one.real = pl->real_data;
+  one.upper = pl->upper;
+  one.info = nullptr;
   (void)hipGetLastError();
   const int mp = full ? (int)pl->npad : (int)round_up(m, 16);
   if (pl->use_graph && trace::mask == 0) {
@@ -1035,7 +1042,7 @@ struct expm_pfd_batch_s {
     int mp = 0, nmax = 0, mmax = 0;
     double work = 0;  // G * npad^3: the schedule's load estimate
   };
-  int count = 0, degree = 0, real_data = 0, use_graph = 0, autotune = 0;
+  int count = 0, degree = 0, real_data = 0, upper = 0, use_graph = 0, autotune = 0;
   int schedule = 0;  // concurrent branches the groups run on (0: not chosen yet)
   std::vector<int64_t> n, m;  // m[i] = 0: V_i = I
   std::vector<Group> groups;
@@ -1171,6 +1178,7 @@ extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64
   b->count = count;
   b->degree = degree;
   b->real_data = opts ? (opts->real_data ? 1 : 0) : 0;
+  b->upper = opts ? opts->uplo : 0;
   b->use_graph = opts ? (opts->graph ? 1 : 0) : 0;
   b->autotune = opts ? (opts->autotune ? 1 : 0) : 0;
   b->n.assign(n, n + count);
@@ -1227,7 +1235,7 @@ extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64
 
 extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const void* const* A, const int64_t* lda,
                                     const void* const* V, const int64_t* ldv, void* const* X, const int64_t* ldx,
-                                    void* stream) {
+                                    int* info, void* stream) {
   if (!b) return EXPM_PFD_ERR_NULL;
   if (!t || !A || !lda || !V || !ldv || !X || !ldx) return EXPM_PFD_ERR_NULL;
   for (int i = 0; i < b->count; ++i) {
@@ -1256,6 +1264,8 @@ extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const v
       d.n = (int)b->n[i];
       d.m = (int)(b->m[i] ? b->m[i] : b->n[i]);
       d.real = b->real_data;
+      d.upper = b->upper;
+      d.info = info ? info + i : nullptr;
     }
     if (hipMemcpyAsync(g.pl->d_descs, hd, g.idx.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice, st) !=
         hipSuccess)
@@ -1301,7 +1311,7 @@ extern "C" int expm_pfd_batch_destroy(expm_pfd_batch_t b) {
 extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree, const void* const* A,
                                       const int64_t* lda, const void* const* V, const int64_t* ldv,
                                       const int64_t* m, void* const* X, const int64_t* ldx,
-                                      const expm_pfd_opts* opts, void* stream) {
+                                      const expm_pfd_opts* opts, void* stream, int* info) {
   if (count < 1) return EXPM_PFD_ERR_DIM;
   if (!n || !t || !A || !lda || !V || !ldv || !m || !X || !ldx) return EXPM_PFD_ERR_NULL;
   for (int i = 0; i < count; ++i) {
@@ -1312,9 +1322,15 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
   for (int i = 0; i < count; ++i) mk[i] = V[i] ? m[i] : 0;
   expm_pfd_batch_t b = nullptr;
   if (int e = expm_pfd_batch_plan(&b, count, n, mk.data(), degree, opts)) return e;
-  int rc = expm_pfd_batch_apply(b, t, A, lda, V, ldv, X, ldx, stream);
+  int* dinfo = nullptr;
+  int rc = 0;
+  if (info && hipMalloc((void**)&dinfo, (size_t)count * sizeof(int)) != hipSuccess) rc = EXPM_PFD_ERR_OOM;
+  if (!rc) rc = expm_pfd_batch_apply(b, t, A, lda, V, ldv, X, ldx, dinfo, stream);
   if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
   if (!rc) rc = expm_pfd_batch_check(b);
+  if (!rc && info && hipMemcpy(info, dinfo, (size_t)count * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = EXPM_PFD_ERR_HIP;
+  if (dinfo) (void)hipFree(dinfo);
   expm_pfd_batch_destroy(b);
   return rc;
 }
@@ -1362,6 +1378,7 @@ struct expm_pfd_queue_s {
   int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
   double shift = 0.0;
   int real_data = 0;
+  int upper = 0;    // registered matrices: upper triangle read
   int lu_tile = 0;  // LU trailing-update tile shape of every plan the queue creates
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
@@ -1490,6 +1507,8 @@ struct expm_pfd_queue_s {
       d.n = (int)mats[r.mat].n;
       d.m = (int)r.m;
       d.real = real_data;
+      d.upper = upper;
+      d.info = nullptr;
       nmax = std::max(nmax, d.n);
       mmax = std::max(mmax, d.m);
       f.descs.push_back(d);
@@ -1552,6 +1571,7 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   q->shift = opts ? opts->shift : 0.0;
   q->real_data = opts ? opts->real_data : 0;
   q->lu_tile = opts && opts->lu_tile > 0 ? opts->lu_tile - 1 : 0;
+  q->upper = opts ? opts->uplo : 0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;

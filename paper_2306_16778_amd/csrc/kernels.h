@@ -21,11 +21,32 @@ namespace expm {
 __global__ void k_put_desc(ProblemDesc* dst, ProblemDesc d) { *dst = d; }
 
 // ---------------------------------------------------------------------------
+// Per-problem status: *d.info = 2 if the result X (n x m, column-major) holds a
+// non-finite value (non-finite input; a zero pivot cannot occur for finite
+// Hermitian A, since |lambda + theta_k| >= |Im theta_k| > 0), else 0.  Problems
+// without a status word are skipped.
+// grid (G), block 256
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_status(const ProblemDesc* __restrict__ descs, ProblemDesc one) {
+  const ProblemDesc d = desc_of(descs, one, blockIdx.x);
+  if (d.info == nullptr) return;
+  int bad = 0;
+  const int64_t count = (int64_t)d.n * d.m;
+  for (int64_t e = threadIdx.x; e < count; e += 256) {
+    const double2 v = d.X[(e % d.n) + (e / d.n) * d.ldx];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) *d.info = bad ? 2 : 0;
+}
+
+// ---------------------------------------------------------------------------
 // K1: form the shifted matrices  W_p = t*A + theta_p I  (paper Sec. 3,
 // eqs. equ:ExpoMatRat and equ:expAx: one shifted matrix per pole; with the
 // conjugate pairs of Remark rem:two_time_real_part one per pair suffices).
-// A is column-major, lower triangle read; the Hermitian operand is built here
-// so that W_p for conj(theta_p) would be exactly W_p^H.  The shift is added in
+// A is column-major, lower (or, with d.upper, upper) triangle read; the
+// Hermitian operand is built here so that W_p for conj(theta_p) would be
+// exactly W_p^H.  The shift is added in
 // FP64 before any rounding to the working type.  Optionally also writes
 // Ah = t*A (full Hermitian, FP64, row-major) for the refinement residuals.
 // grid (npad/32, npad/32), block (32, 8)
@@ -45,12 +66,23 @@ __global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ de
   double2* Ah = Ahb ? Ahb + (int64_t)g * npad * ldh : nullptr;
   const int bi = blockIdx.y, bj = blockIdx.x;
   const int R0 = (bi > bj ? bi : bj) * 32, C0 = (bi < bj ? bi : bj) * 32;
+  // tile[cc][x] = lower-triangle element (R0 + x, C0 + cc): read directly, or as
+  // the conjugate of the upper element (C0 + cc, R0 + x), read along its column
+  // and transposed through the tile
   for (int cc = threadIdx.y; cc < 32; cc += 8) {
-    const int r = R0 + threadIdx.x, c = C0 + cc;
-    double2 v = czero<double2>();
-    if (r < n && c < n) v = A[r + (int64_t)c * lda];
-    if (d.real) v.y = 0;
-    tile[cc][threadIdx.x] = v;
+    if (!d.upper) {
+      const int r = R0 + threadIdx.x, c = C0 + cc;
+      double2 v = czero<double2>();
+      if (r < n && c < n) v = A[r + (int64_t)c * lda];
+      if (d.real) v.y = 0;
+      tile[cc][threadIdx.x] = v;
+    } else {
+      const int r = C0 + threadIdx.x, c = R0 + cc;
+      double2 v = czero<double2>();
+      if (r < n && c < n) v = cconj(A[r + (int64_t)c * lda]);
+      if (d.real) v.y = 0;
+      tile[threadIdx.x][cc] = v;
+    }
   }
   __syncthreads();
   for (int ry = threadIdx.y; ry < 32; ry += 8) {

@@ -73,7 +73,7 @@ class _QueueStats(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("ir_extended", ctypes.c_int),
                 ("real_data", ctypes.c_int), ("graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("lu_tile", ctypes.c_int), ("reserved", ctypes.c_int), ("shift", ctypes.c_double)]
+                ("lu_tile", ctypes.c_int), ("uplo", ctypes.c_int), ("shift", ctypes.c_double)]
 
 # tile shapes of the LU trailing update, in the order of expm_pfd_opts.lu_tile - 1
 LU_TILES = ("64x64", "128x64", "64x128")
@@ -98,9 +98,9 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_destroy.argtypes = [vp]
     lib.expm_pfd_plan_check.argtypes = [vp]
     lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
-                                           ctypes.POINTER(_Opts), vp]
+                                           ctypes.POINTER(_Opts), vp, vp]
     lib.expm_pfd_batch_plan.argtypes = [ctypes.POINTER(vp), c_int, vp, vp, c_int, ctypes.POINTER(_Opts)]
-    lib.expm_pfd_batch_apply.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.expm_pfd_batch_apply.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.expm_pfd_batch_check.argtypes = [vp]
     lib.expm_pfd_batch_info.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.expm_pfd_batch_destroy.argtypes = [vp]
@@ -131,7 +131,7 @@ def _check(code: int, where: str):
 
 
 def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False, graph=False, autotune=False,
-          lu_tile=None) -> _Opts:
+          lu_tile=None, uplo="L") -> _Opts:
     p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
     o = _Opts()
     o.precision = int(p)
@@ -142,6 +142,7 @@ def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False, graph
     o.graph = 1 if graph else 0
     o.autotune = 1 if autotune else 0
     o.lu_tile = 0 if lu_tile is None else (LU_TILES.index(lu_tile) + 1 if isinstance(lu_tile, str) else int(lu_tile))
+    o.uplo = {"L": 0, "U": 1}.get(uplo, uplo)
     return o
 
 
@@ -184,11 +185,12 @@ class Plan:
 
 def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0,
                   ir_extended: int = 0, shift: float = 0.0, real_data: bool = False, graph: bool = False,
-                  autotune: bool = False, lu_tile=None) -> Plan:
-    """lu_tile: None (built-in or autotuned), a name from LU_TILES, or the C option value (1..3)."""
+                  autotune: bool = False, lu_tile=None, uplo="L") -> Plan:
+    """lu_tile: None (built-in or autotuned), a name from LU_TILES, or the C option value (1..3).
+    uplo: "L" (lower triangle of A read) or "U"."""
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo)
     _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
            "expm_pfd_plan")
     return Plan(h.value, n, degree, t, m_max, precision)
@@ -247,8 +249,10 @@ def expm_pfd_apply(plan: Plan, A, V=None, X=None, stream=None):
 
 
 def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degree: int, precision="fp64",
-                           ir_sweeps: int = 0, stream=None):
-    """X_i = R_d(t_i A_i) V_i for every i (V_i None: V_i = I).  Returns the list of X_i."""
+                           ir_sweeps: int = 0, stream=None, info=None, uplo="L"):
+    """X_i = R_d(t_i A_i) V_i for every i (V_i None: V_i = I).  Returns the list of X_i.
+
+    info: optional host int32 numpy array of len(As), filled with each problem's status."""
     import torch
 
     lib = load_library()
@@ -277,10 +281,13 @@ def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degr
         x = torch.empty((int(m[i]), int(n[i])), dtype=torch.complex128, device=a.device).t()
         Xs.append(x)
         ldx[i], px[i] = n[i], x.data_ptr()
-    o = _opts(precision, ir_sweeps)
+    o = _opts(precision, ir_sweeps, uplo=uplo)
+    if info is not None and (info.dtype != np.int32 or info.size != count or not info.flags.c_contiguous):
+        raise ValueError("info must be a contiguous int32 array with one entry per problem")
     _check(lib.expm_pfd_apply_batched(count, n.ctypes.data, t.ctypes.data, int(degree), pa, lda.ctypes.data, pv,
                                       ldv.ctypes.data, m.ctypes.data, px, ldx.ctypes.data, ctypes.byref(o),
-                                      _stream_ptr(stream, torch)), "expm_pfd_apply_batched")
+                                      _stream_ptr(stream, torch), None if info is None else info.ctypes.data),
+           "expm_pfd_apply_batched")
     return Xs
 
 
@@ -302,7 +309,7 @@ class BatchPlan:
 
 def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precision="fp64", ir_sweeps: int = 0,
                         graph: bool = False, autotune: bool = False, lu_tile=None,
-                        real_data: bool = False) -> BatchPlan:
+                        real_data: bool = False, uplo="L") -> BatchPlan:
     """Batch plan for problems of orders n[i] with m[i] right-hand-side columns (0: V_i = I)."""
     lib = load_library()
     nn = np.ascontiguousarray(n, dtype=np.int64)
@@ -310,15 +317,17 @@ def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precisi
     if nn.shape != mm.shape:
         raise ValueError("n and m must have the same length")
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, 0, 0.0, real_data, graph, autotune, lu_tile)
+    o = _opts(precision, ir_sweeps, 0, 0.0, real_data, graph, autotune, lu_tile, uplo)
     _check(lib.expm_pfd_batch_plan(ctypes.byref(h), len(nn), nn.ctypes.data, mm.ctypes.data, int(degree),
                                    ctypes.byref(o)), "expm_pfd_batch_plan")
     return BatchPlan(h.value, nn, mm)
 
 
-def expm_pfd_batch_apply(b: BatchPlan, As: Sequence, Vs: Sequence, ts: Sequence[float], Xs=None, stream=None):
+def expm_pfd_batch_apply(b: BatchPlan, As: Sequence, Vs: Sequence, ts: Sequence[float], Xs=None, stream=None,
+                         info=None):
     """X_i = R_d(t_i A_i) V_i on the plan's problems (V_i None where m[i] = 0).  Returns the list of X_i.
 
+    info: optional int32 device tensor with one entry per problem, written with each status.
     The inputs (and any column-major copies made here) are kept alive on the plan
     until its next apply, so the asynchronous launches can read them."""
     import torch
@@ -355,9 +364,13 @@ def expm_pfd_batch_apply(b: BatchPlan, As: Sequence, Vs: Sequence, ts: Sequence[
             raise ValueError("X must be column-major (n, m) complex128")
         out.append(x)
         ldx[i], px[i] = x.stride(1), x.data_ptr()
+    if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() != count
+                             or not info.is_contiguous()):
+        raise ValueError("info must be a contiguous int32 device tensor with one entry per problem")
     _check(lib.expm_pfd_batch_apply(b.handle, t.ctypes.data, pa, lda.ctypes.data, pv, ldv.ctypes.data, px,
-                                    ldx.ctypes.data, _stream_ptr(stream, torch)), "expm_pfd_batch_apply")
-    b._keep = (Ac, Vc, out)
+                                    ldx.ctypes.data, None if info is None else info.data_ptr(),
+                                    _stream_ptr(stream, torch)), "expm_pfd_batch_apply")
+    b._keep = (Ac, Vc, out, info)
     return out
 
 

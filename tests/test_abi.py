@@ -112,7 +112,10 @@ def test_batch_and_option_validation_without_device():
         assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
         assert lib.expm_pfd_batch_plan(ctypes.byref(h), 3, n.ctypes.data, m.ctypes.data, 16, ctypes.byref(o)) == -7
     o.lu_tile = 0
-    assert lib.expm_pfd_batch_apply(None, None, None, None, None, None, None, None, None) == -3
+    assert lib.expm_pfd_batch_apply(None, None, None, None, None, None, None, None, None, None) == -3
+    o.uplo = 2
+    assert lib.expm_pfd_plan(ctypes.byref(h), 10, 16, 1.0, 0, ctypes.byref(o)) == -7
+    o.uplo = 0
     assert lib.expm_pfd_batch_check(None) == -3
     assert lib.expm_pfd_batch_destroy(None) == -3
     assert lib.expm_pfd_batch_info(None, None, None, None) == -3

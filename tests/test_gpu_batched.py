@@ -101,3 +101,58 @@ def test_many_chains_sweep_equals_alone(ep, precision, tol):
             X1 = ep.expm_pfd_apply(plan, _dev(A), _dev(V))
             torch.cuda.synchronize()
             assert np.array_equal(X1.cpu().numpy(), Xb)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_upper_triangle_equals_lower(ep, precision):
+    """uplo = "U" reads only the upper triangle: with the other triangle of each input
+    set to NaN, both give the same bits, and match the oracle."""
+    import torch
+    rng = np.random.default_rng(12)
+    n, m, t = 150, 3, 0.6
+    A = wl.hermitian_with_spectrum(rng, rng.uniform(-40.0, 0.0, n))
+    V = wl.complex_gaussian(rng, n, m)
+    AL, AU = A.copy(), A.copy()
+    AL[np.triu_indices(n, 1)] = np.nan
+    AU[np.tril_indices(n, -1)] = np.nan
+    _announce(f"uplo {precision} n={n}")
+    XL = ep.expm_pfd_apply(ep.expm_pfd_plan(n, 16, t, m, precision), _dev(AL), _dev(V))
+    XU = ep.expm_pfd_apply(ep.expm_pfd_plan(n, 16, t, m, precision, uplo="U"), _dev(AU), _dev(V))
+    torch.cuda.synchronize()
+    XL, XU = XL.cpu().numpy(), XU.cpu().numpy()
+    assert np.array_equal(XL, XU)
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    assert matrix.rel_fro(XU, matrix.expm_R(A, V, t, 16)) < tol
+
+
+def test_batched_status(ep):
+    """Per-problem status of the batched entry points: 0 for finite results, 2 for a
+    problem whose input holds a NaN (it propagates to its result; the others are
+    unaffected and match the same batch without it)."""
+    import torch
+    probs = _batch(13)[:6]
+    bad = [(A.copy(), V, t) for A, V, t in probs]
+    bad[2][0][5, 1] = np.nan  # lower triangle: read
+    bad[2][0][1, 5] = np.nan
+    _announce("batched status with one NaN input")
+    info = np.full(len(bad), -1, dtype=np.int32)
+    Xs = ep.expm_pfd_apply_batched([_dev(A) for A, _, _ in bad], [None if V is None else _dev(V) for _, V, _ in bad],
+                                   [t for _, _, t in bad], 16, "fp64", info=info)
+    torch.cuda.synchronize()
+    assert list(info) == [0, 0, 2, 0, 0, 0]
+    assert not np.all(np.isfinite(Xs[2].cpu().numpy()))
+    for i, ((A, V, t), X) in enumerate(zip(probs, Xs)):
+        if i != 2:
+            assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16)) < 1e-12
+    # the asynchronous form writes the status into device memory
+    n = [A.shape[0] for A, _, _ in bad]
+    m = [0 if V is None else V.shape[1] for _, V, _ in bad]
+    bp = ep.expm_pfd_batch_plan(n, m, 16, "mixed", graph=True)
+    dinfo = torch.full((len(bad),), -1, dtype=torch.int32, device="cuda")
+    for _ in range(2):  # capture, then replay
+        dinfo.fill_(-1)
+        ep.expm_pfd_batch_apply(bp, [_dev(A) for A, _, _ in bad], [None if V is None else _dev(V) for _, V, _ in bad],
+                                [t for _, _, t in bad], info=dinfo)
+        torch.cuda.synchronize()
+        assert dinfo.cpu().tolist() == [0, 0, 2, 0, 0, 0]
+    ep.expm_pfd_batch_check(bp)
