@@ -332,6 +332,8 @@ struct expm_pfd_plan_s {
   double2* Rpart = nullptr;  // mixed: ir_kslices(npad) x npad x (2 PB min(mp_max, 64)) split-K partials
   ProblemDesc* d_descs = nullptr;  // G problem descriptors on the device (batched entry point)
   int device = 0;
+  bool pooled = false;             // workspace from the stream-ordered pool (freed on `pool`)
+  hipStream_t pool = nullptr;
   int lu_tile = 0;                 // LU trailing-update tile shape (LU_TILE_NAMES)
   int use_graph = 0;               // expm_pfd_apply replays captured graphs
   hipStream_t cap = nullptr;       // stream the graphs are captured on (plan-owned)
@@ -384,7 +386,7 @@ void free_plan(expm_pfd_plan_t p) {
   void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
                   p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->Rpart, p->d_descs};
   for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) (void)(p->pooled ? hipFreeAsync(q, p->pool) : hipFree(q));
   delete p;
 }
 
@@ -396,9 +398,30 @@ int sweep_fault(expm_pfd_plan_t p) {
   return f;
 }
 
+// Where a plan's workspace comes from: hipMalloc (pool == nullptr), or the
+// device's stream-ordered pool on stream pool->s (fast once the pool holds
+// memory: the serving queue and one-shot batches create plans while other
+// work runs).
+struct PoolArg {
+  hipStream_t s;
+};
+
+// Freed blocks of the default stream-ordered pool stay in it for reuse (once
+// per device; idempotent).
+void keep_pool_memory(int device) {
+  hipMemPool_t mpool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&mpool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(mpool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
+}
+
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps, int ir_extended, double shift, int real_data) {
+                int ir_sweeps, int ir_extended, double shift, int real_data, const PoolArg* pool = nullptr) {
   auto* pl = new expm_pfd_plan_s();
+  pl->pooled = pool != nullptr;
+  pl->pool = pool ? pool->s : nullptr;
   pl->G = G;
   pl->Gcap = G;
   pl->degree = degree;
@@ -434,22 +457,31 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   }
   (void)hipGetDevice(&pl->device);
   HipErr he;
-  he(hipMalloc(&pl->d_theta, 64 * sizeof(double2)));
-  he(hipMalloc(&pl->d_a, 64 * sizeof(double2)));
-  he(hipMalloc(&pl->W, sz.w));
-  he(hipMalloc(&pl->ipiv, sz.ipiv));
-  he(hipMalloc(&pl->moves, sz.moves));
-  he(hipMalloc(&pl->dinv, sz.dinv));
-  he(hipMalloc(&pl->sweep_sync, sz.sweep));
-  he(hipMalloc(&pl->Xs, sz.xs));
-  he(hipMalloc(&pl->d_descs, sz.descs));
+  auto dmalloc = [&](auto** p, size_t bytes) {
+    he(pool ? hipMallocAsync((void**)p, bytes, pool->s) : hipMalloc((void**)p, bytes));
+  };
+  dmalloc(&pl->d_theta, 64 * sizeof(double2));
+  dmalloc(&pl->d_a, 64 * sizeof(double2));
+  dmalloc(&pl->W, sz.w);
+  dmalloc(&pl->ipiv, sz.ipiv);
+  dmalloc(&pl->moves, sz.moves);
+  dmalloc(&pl->dinv, sz.dinv);
+  dmalloc(&pl->sweep_sync, sz.sweep);
+  dmalloc(&pl->Xs, sz.xs);
+  dmalloc(&pl->d_descs, sz.descs);
   if (precision == EXPM_PFD_MIXED) {
-    he(hipMalloc(&pl->Ah, sz.ah));
-    he(hipMalloc(&pl->X64, sz.x64));
-    he(hipMalloc(&pl->R64, sz.r64));
-    he(hipMalloc(&pl->Rpart, sz.rpart));
+    dmalloc(&pl->Ah, sz.ah);
+    dmalloc(&pl->X64, sz.x64);
+    dmalloc(&pl->R64, sz.r64);
+    dmalloc(&pl->Rpart, sz.rpart);
   }
-  if (he.e == hipSuccess) {
+  if (he.e == hipSuccess && pool) {
+    // the constants' host copies live in the plan, so the copies may complete later
+    he(hipMemcpyAsync(pl->d_theta, pl->h_theta.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice, pool->s));
+    he(hipMemcpyAsync(pl->d_a, pl->h_a.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice, pool->s));
+    he(hipMemsetAsync(pl->moves, 0, sz.moves, pool->s));
+    he(hipMemsetAsync(pl->sweep_sync, 0, sz.sweep, pool->s));
+  } else if (he.e == hipSuccess) {
     he(hipMemcpy(pl->d_theta, pl->h_theta.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
     he(hipMemcpy(pl->d_a, pl->h_a.data(), pl->P * sizeof(double2), hipMemcpyHostToDevice));
     he(hipMemset(pl->moves, 0, sz.moves));
@@ -1080,6 +1112,16 @@ int run_groups(expm_pfd_batch_t b, hipStream_t st, int S) {
       if (int e = run(g.pl, g.pl->d_descs, none, g.full, g.mp, g.nmax, g.mmax, st)) return e;
     return 0;
   }
+  while ((int)b->br.size() < S) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    b->br.push_back(s);
+  }
+  while ((int)b->ev.size() < 1 + S) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    b->ev.push_back(e);
+  }
   if (hipEventRecord(b->ev[0], st) != hipSuccess) return EXPM_PFD_ERR_HIP;
   for (int i = 0; i < S; ++i)
     if (hipStreamWaitEvent(b->br[i], b->ev[0], 0) != hipSuccess) return EXPM_PFD_ERR_HIP;
@@ -1107,6 +1149,20 @@ int launch_batch(expm_pfd_batch_t b, hipStream_t st, int S) {
   if (!b->use_graph || trace::mask != 0) return run_groups(b, st, S);
   auto it = b->graphs.find(S);
   if (it == b->graphs.end()) {
+    if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    // branch streams and events exist before the capture starts
+    if (S > 1) {
+      while ((int)b->br.size() < std::min<int>(S, (int)b->groups.size())) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return EXPM_PFD_ERR_HIP;
+        b->br.push_back(s);
+      }
+      while ((int)b->ev.size() < 1 + std::min<int>(S, (int)b->groups.size())) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EXPM_PFD_ERR_HIP;
+        b->ev.push_back(e);
+      }
+    }
     hipGraphExec_t ex = nullptr;
     if (int e = capture_graph(b->cap, [&](hipStream_t cs) { return run_groups(b, cs, S); }, &ex)) return e;
     it = b->graphs.emplace(S, ex).first;
@@ -1161,8 +1217,20 @@ int choose_schedule(expm_pfd_batch_t b, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+int batch_plan_impl(expm_pfd_batch_t* out, int count, const int64_t* n, const int64_t* m, int degree,
+                    const expm_pfd_opts* opts, const PoolArg* pool);
+}
+
 extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, const int64_t* m, int degree,
                                    const expm_pfd_opts* opts) {
+  return batch_plan_impl(out, count, n, m, degree, opts, nullptr);
+}
+
+namespace {
+// pool: as in create_plan (nullptr: hipMalloc; otherwise the stream-ordered pool)
+int batch_plan_impl(expm_pfd_batch_t* out, int count, const int64_t* n, const int64_t* m, int degree,
+                    const expm_pfd_opts* opts, const PoolArg* pool) {
   if (!out) return EXPM_PFD_ERR_NULL;
   *out = nullptr;
   if (count < 1) return EXPM_PFD_ERR_DIM;
@@ -1200,7 +1268,7 @@ extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64
     }
     g.work = (double)G * npad * npad * npad;
     rc = create_plan(&g.pl, npad, G, degree, g.full ? 16 : mpk, g.full, precision, opts ? opts->ir_sweeps : 0,
-                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, b->real_data);
+                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, b->real_data, pool);
     if (rc) break;
     b->groups.push_back(std::move(g));
     expm_pfd_plan_t pl = b->groups.back().pl;
@@ -1212,16 +1280,9 @@ extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64
   }
   HipErr he;
   if (!rc) {
+    // (the capture stream and the branch streams are created when first needed)
     he(hipHostMalloc((void**)&b->h_descs, (size_t)count * sizeof(ProblemDesc), hipHostMallocDefault));
     he(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
-    he(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-    const int nb = std::min<int>((int)b->groups.size(), BATCH_MAX_BRANCHES);
-    if (nb > 1) {
-      b->br.resize(nb, nullptr);
-      b->ev.resize(1 + nb, nullptr);
-      for (auto& s : b->br) he(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-      for (auto& e : b->ev) he(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
     if (he.e != hipSuccess) rc = he.e == hipErrorOutOfMemory ? EXPM_PFD_ERR_OOM : EXPM_PFD_ERR_HIP;
   }
   if (rc) {
@@ -1232,6 +1293,7 @@ extern "C" int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64
   *out = b;
   return 0;
 }
+}  // namespace
 
 extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const void* const* A, const int64_t* lda,
                                     const void* const* V, const int64_t* ldv, void* const* X, const int64_t* ldx,
@@ -1320,17 +1382,24 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
   }
   std::vector<int64_t> mk(count);
   for (int i = 0; i < count; ++i) mk[i] = V[i] ? m[i] : 0;
+  // workspace from the stream-ordered pool on the caller's stream: repeated calls
+  // reuse it instead of allocating device memory each time
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  keep_pool_memory(dev);
+  const PoolArg pa{st};
   expm_pfd_batch_t b = nullptr;
-  if (int e = expm_pfd_batch_plan(&b, count, n, mk.data(), degree, opts)) return e;
+  if (int e = batch_plan_impl(&b, count, n, mk.data(), degree, opts, &pa)) return e;
   int* dinfo = nullptr;
   int rc = 0;
-  if (info && hipMalloc((void**)&dinfo, (size_t)count * sizeof(int)) != hipSuccess) rc = EXPM_PFD_ERR_OOM;
+  if (info && hipMallocAsync((void**)&dinfo, (size_t)count * sizeof(int), st) != hipSuccess) rc = EXPM_PFD_ERR_OOM;
   if (!rc) rc = expm_pfd_batch_apply(b, t, A, lda, V, ldv, X, ldx, dinfo, stream);
   if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
   if (!rc) rc = expm_pfd_batch_check(b);
   if (!rc && info && hipMemcpy(info, dinfo, (size_t)count * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     rc = EXPM_PFD_ERR_HIP;
-  if (dinfo) (void)hipFree(dinfo);
+  if (dinfo) (void)hipFreeAsync(dinfo, st);
   expm_pfd_batch_destroy(b);
   return rc;
 }
@@ -1479,7 +1548,8 @@ struct expm_pfd_queue_s {
       cached_bytes -= bytes;
     } else {
       release_cached(bytes);
-      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift, real_data) != 0) {
+      const PoolArg pa{streams[s]};
+      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift, real_data, &pa) != 0) {
         (void)hipGetLastError();
         return false;
       }
@@ -1585,6 +1655,9 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
     q->streams.push_back(st);
     q->busy.push_back(false);
   }
+  // freed plan workspace stays in the device's stream-ordered pool, so plans of
+  // new shapes are carved from it without new device allocations
+  keep_pool_memory(q->device);
   q->worker = std::thread([q] { q->loop(); });
   *out = q;
   return 0;
