@@ -168,8 +168,27 @@ def finish_path(Xh, steps, wall, dom, lat, breakdown, n, m, d, precision, graph)
             "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
         },
         "breakdown_ms_per_step": {c: round(v["ms"], 4) for c, v in breakdown.items() if v["launches"]},
+        "stage_rates": stage_rates(breakdown, precision),
         "graph_replay_autotuned": graph,
     }
+
+
+def stage_rates(breakdown, precision):
+    """Per kernel class of one traced apply: algorithmic TFLOP/s and HBM GB/s (the
+    tracer's per-launch counts over the summed launch times), and the fraction of
+    the bound that applies (matrix cores for the products, HBM for the rest)."""
+    mfma = {"lu_trail", "lu_gemm", "lu_trsm", "ir_gemm"}
+    out = {}
+    for c, v in breakdown.items():
+        if not v["launches"] or v["ms"] <= 0:
+            continue
+        tf = v["flops"] / (v["ms"] * 1e-3) / 1e12
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        peak = 78.6 if (precision == "fp64" or c == "ir_gemm") else 157.3
+        out[c] = {"tflops": round(tf, 2), "gb_per_s": round(gbs, 1),
+                  "bound": "mfma" if c in mfma else "hbm",
+                  "frac": round(tf / peak, 3) if c in mfma else round(gbs / 8000.0, 3)}
+    return out
 
 
 def cpu_baseline(prob):
@@ -400,6 +419,7 @@ def main():
                      "latency_ms": f64["latency_ms"], "gflops": f64["gflops"],
                      "rel_err_vs_oracle": errs.get("fp64"), "roofline": f64["roofline"],
                      "breakdown_ms_per_step": f64["breakdown_ms_per_step"],
+                     "stage_rates": f64["stage_rates"],
                      "graph_replay_autotuned": f64["graph_replay_autotuned"]}
     out = {
         "metric": METRIC,
@@ -423,6 +443,7 @@ def main():
         "speedup_vs_fp64_path": f64["ms_per_step"] / mx["ms_per_step"] if f64 else None,
         "fp64_path": fp64_path,
         "breakdown_ms_per_step": mx["breakdown_ms_per_step"],
+        "stage_rates": mx["stage_rates"],
         "graph_replay_autotuned": mx["graph_replay_autotuned"],
         "roofline": mx["roofline"],
         "cpu_baseline": cpu,

@@ -87,3 +87,20 @@ def test_bench_bookkeeping():
         bench.TRAFFIC["mixed"].update(saved)
     assert bench.measured_traffic("fp64") is None
     json.dumps({"x": bench.PEAK})
+
+
+def test_stage_rates():
+    """Per-stage rates of the bench line: flops and bytes over the summed launch times,
+    matrix-core fraction for the products, HBM fraction (8 TB/s) for the rest."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    b = {"lu_trail": {"launches": 15, "ms": 2.0, "flops": 2.0e11, "bytes": 4.0e9},
+         "solve_gemm": {"launches": 6, "ms": 1.0, "flops": 1.0e9, "bytes": 4.0e9},
+         "panel": {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0}}
+    r = bench.stage_rates(b, "mixed")
+    assert set(r) == {"lu_trail", "solve_gemm"}
+    assert r["lu_trail"]["tflops"] == 100.0 and r["lu_trail"]["bound"] == "mfma"
+    assert r["lu_trail"]["frac"] == round(100.0 / 157.3, 3)
+    assert r["solve_gemm"]["gb_per_s"] == 4000.0 and r["solve_gemm"]["frac"] == 0.5
+    assert bench.stage_rates(b, "fp64")["lu_trail"]["frac"] == round(100.0 / 78.6, 3)
