@@ -355,8 +355,9 @@ def main():
                     help="run a 256 MiB copy kernel first (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the poles or the requests "
-              "would be sharded across GPUs with one final reduction; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the pole pairs or the "
+              "requests would be sharded across GPUs, with one fixed-order reduction of the n x m result).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
