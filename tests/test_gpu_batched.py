@@ -123,6 +123,12 @@ def test_upper_triangle_equals_lower(ep, precision):
     assert np.array_equal(XL, XU)
     tol = 1e-12 if precision == "fp64" else 1e-10
     assert matrix.rel_fro(XU, matrix.expm_R(A, V, t, 16)) < tol
+    # the batched entry point reads the same triangle
+    Xb = ep.expm_pfd_apply_batched([_dev(AU), _dev(AU[:70, :70])], [_dev(V), None], [t, t], 16, precision,
+                                   uplo="U")
+    torch.cuda.synchronize()
+    assert np.array_equal(Xb[0].cpu().numpy(), XU)
+    assert matrix.rel_fro(Xb[1].cpu().numpy(), matrix.expm_R(A[:70, :70], None, t, 16)) < tol
 
 
 def test_batched_status(ep):
