@@ -1792,7 +1792,13 @@ extern "C" int expm_pfd_queue_destroy(expm_pfd_queue_t q) {
     for (expm_pfd_plan_t p : kv.second) free_plan(p);
   for (auto& m : q->mats)
     if (m.A) (void)hipFree(m.A);
+  for (hipStream_t s : q->streams) (void)hipStreamSynchronize(s);
   for (hipStream_t s : q->streams) (void)hipStreamDestroy(s);
+  // the plans' workspace went back to the stream-ordered pool: hand it back to
+  // the device
+  hipMemPool_t mpool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&mpool, q->device) == hipSuccess) (void)hipMemPoolTrimTo(mpool, 0);
+  (void)hipGetLastError();
   delete q;
   return 0;
 }
