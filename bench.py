@@ -178,6 +178,7 @@ def stage_rates(breakdown, precision):
     tracer's per-launch counts over the summed launch times), and the fraction of
     the bound that applies (matrix cores for the products, HBM for the rest)."""
     mfma = {"lu_trail", "lu_gemm", "lu_trsm", "ir_gemm"}
+    latency = {"panel", "moves"}  # one workgroup per matrix / row copies: neither peak applies
     out = {}
     for c, v in breakdown.items():
         if not v["launches"] or v["ms"] <= 0:
@@ -185,9 +186,9 @@ def stage_rates(breakdown, precision):
         tf = v["flops"] / (v["ms"] * 1e-3) / 1e12
         gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
         peak = 78.6 if (precision == "fp64" or c == "ir_gemm") else 157.3
-        out[c] = {"tflops": round(tf, 2), "gb_per_s": round(gbs, 1),
-                  "bound": "mfma" if c in mfma else "hbm",
-                  "frac": round(tf / peak, 3) if c in mfma else round(gbs / 8000.0, 3)}
+        bound = "mfma" if c in mfma else "latency" if c in latency else "hbm"
+        frac = round(tf / peak, 3) if bound == "mfma" else round(gbs / 8000.0, 3) if bound == "hbm" else None
+        out[c] = {"tflops": round(tf, 2), "gb_per_s": round(gbs, 1), "bound": bound, "frac": frac}
     return out
 
 

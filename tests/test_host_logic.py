@@ -104,3 +104,6 @@ def test_stage_rates():
     assert r["lu_trail"]["frac"] == round(100.0 / 157.3, 3)
     assert r["solve_gemm"]["gb_per_s"] == 4000.0 and r["solve_gemm"]["frac"] == 0.5
     assert bench.stage_rates(b, "fp64")["lu_trail"]["frac"] == round(100.0 / 78.6, 3)
+    b["panel"] = {"launches": 4, "ms": 1.0, "flops": 1.0e9, "bytes": 1.0e8}
+    assert bench.stage_rates(b, "mixed")["panel"] == {"tflops": 1.0, "gb_per_s": 100.0, "bound": "latency",
+                                                      "frac": None}
