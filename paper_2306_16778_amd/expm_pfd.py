@@ -24,6 +24,9 @@ LIB_PATH = os.path.join(_HERE, "libexpm_pfd.so")
 
 EXPM_PFD_FP64 = 0
 EXPM_PFD_MIXED = 1
+# largest order and degree the library accepts (EXPM_PFD_MAX_N, EXPM_PFD_MAX_DEGREE)
+MAX_N = 8192
+MAX_DEGREE = 64
 
 # every symbol declared in include/expm_pfd.h
 EXPORTED = (

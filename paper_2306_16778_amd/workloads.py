@@ -55,6 +55,31 @@ def householder_unitary_apply(rng: np.random.Generator, n: int, M: np.ndarray, r
     return X
 
 
+def hermitian_with_known_eigenbasis(rng: np.random.Generator, lam: np.ndarray, reflections: int = 3):
+    """(A, U) with A = U diag(lam) U^H and U = D H_1 ... H_r returned densely.
+
+    Same construction as ``householder_unitary_apply`` (random Householder
+    reflections and a random phase diagonal), O(r n^2), so that the largest
+    orders the library accepts come with their eigenvectors without an O(n^3)
+    eigensolver or QR.  A is symmetrised like ``hermitian_with_spectrum``."""
+    n = lam.shape[0]
+    vs = [complex_gaussian(rng, n) for _ in range(reflections)]
+    vs = [v / np.linalg.norm(v) for v in vs]
+    phase = np.exp(2j * np.pi * rng.random(n))
+    A = np.diag(lam.astype(np.complex128))
+    U = np.eye(n, dtype=np.complex128)
+    for v in reversed(vs):
+        # H = I - 2 v v^H ; A <- H A H^H ; U <- H U
+        A -= 2.0 * np.outer(v, v.conj() @ A)
+        A -= 2.0 * np.outer(A @ v, v.conj())
+        U -= 2.0 * np.outer(v, v.conj() @ U)
+    A *= phase[:, None]
+    A *= phase.conj()[None, :]
+    U *= phase[:, None]
+    A = 0.5 * (A + A.conj().T)
+    return A, U
+
+
 def hermitian_with_spectrum(rng: np.random.Generator, lam: np.ndarray, cheap: bool = False) -> np.ndarray:
     n = lam.shape[0]
     if cheap:

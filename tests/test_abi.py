@@ -32,6 +32,13 @@ def test_header_declares_expected_entry_points():
         assert n in names
 
 
+def test_binding_limits_match_header():
+    from paper_2306_16778_amd import expm_pfd
+    text = open(HEADER).read()
+    assert int(re.search(r"#define EXPM_PFD_MAX_N\s+(\d+)", text).group(1)) == expm_pfd.MAX_N
+    assert int(re.search(r"#define EXPM_PFD_MAX_DEGREE\s+(\d+)", text).group(1)) == expm_pfd.MAX_DEGREE
+
+
 def test_library_exports_every_declared_symbol():
     mod, lib = _lib()
     out = subprocess.run(["nm", "-D", "--defined-only", mod.LIB_PATH], capture_output=True, text=True).stdout
