@@ -162,3 +162,33 @@ def test_batched_status(ep):
         torch.cuda.synchronize()
         assert dinfo.cpu().tolist() == [0, 0, 2, 0, 0, 0]
     ep.expm_pfd_batch_check(bp)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_config4_full_batch(ep, precision, tol):
+    """All 512 problems of the batched workload (n log-uniform in [32, 512], V n x 4,
+    degree 16) in the launch configuration the benchmark times: a reusable batch plan
+    with graph capture and autotuned tiles and schedule.  The first apply tunes and
+    captures, the second replays the graph; both give the same bits for every
+    problem, and a stratified sample (every 16th problem by index, plus the smallest
+    and the largest order) matches the oracle."""
+    import torch
+    probs = wl.config4_batch(512)
+    As = [_dev(p.A) for p in probs]
+    Vs = [_dev(p.V) for p in probs]
+    ts = [p.t for p in probs]
+    ns = [p.A.shape[0] for p in probs]
+    ms = [p.V.shape[1] for p in probs]
+    _announce(f"config4 full batch {precision}: 512 problems, n {min(ns)}..{max(ns)}")
+    bp = ep.expm_pfd_batch_plan(ns, ms, 16, precision, graph=True, autotune=True)
+    X1 = [x.clone() for x in ep.expm_pfd_batch_apply(bp, As, Vs, ts)]
+    X2 = ep.expm_pfd_batch_apply(bp, As, Vs, ts)
+    torch.cuda.synchronize()
+    ep.expm_pfd_batch_check(bp)
+    assert all(torch.equal(a, b) for a, b in zip(X1, X2))
+    assert all(bool(torch.isfinite(torch.view_as_real(x)).all()) for x in X2)
+    sample = sorted(set(range(0, 512, 16)) | {int(np.argmin(ns)), int(np.argmax(ns))})
+    for i in sample:
+        p = probs[i]
+        err = matrix.rel_fro(X2[i].cpu().numpy(), matrix.expm_R(p.A, p.V, p.t, 16))
+        assert err < tol, (i, ns[i], err)

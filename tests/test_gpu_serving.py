@@ -49,6 +49,42 @@ def test_serving_trace_matches_oracle_and_alone(ep, precision, tol):
         assert np.array_equal(X1.cpu().numpy(), X)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_serving_full_order_range(ep, precision, tol):
+    """Requests over the serving workload's whole order range, n log-uniform in
+    [64, 4096], overlapping on the device (arrivals at 400/s).  The oracle uses the
+    eigenpairs the matrices are built from (spectrum and Householder eigenvectors
+    regenerated from the same seeds), so orders up to 4096 need no eigensolver;
+    the matrices the queue factors are the device-assembled copies, which differ
+    from U diag(lam) U^H only by rounding (about 1e-13 relative in the result)."""
+    import torch
+    from paper_2306_16778_amd import serving
+    from paper_2306_16778_amd import workloads as wl
+
+    _announce(f"serving {precision} 40 requests n in [64, 4096]")
+    stats, kept, _ = serving.replay(40, qps=400.0, precision=precision, degree=16, n_lo=64, n_hi=4096,
+                                    budget_bytes=32 << 30, keep=lambda r: True)
+    assert stats["completed"] == 40
+    assert max(r.n for r, *_ in kept) > 2048
+    eig = {}
+    for r, A, v, t, X in kept:
+        if r.matrix_id not in eig:
+            rng = wl.rng_for(5, r.matrix_id + 1)
+            lam = rng.uniform(-200.0, 0.0, r.n)
+            _, U = wl.hermitian_with_known_eigenbasis(rng, lam)
+            eig[r.matrix_id] = (lam, U)
+        Y = matrix.expm_R(A, v, t, 16, eig=eig[r.matrix_id])
+        err = matrix.rel_fro(X, Y)
+        assert err < tol, (r.n, err)
+    # alone: the two largest requests through single-problem plans give the same bits
+    for r, A, v, t, X in sorted(kept, key=lambda k: -k[0].n)[:2]:
+        plan = ep.expm_pfd_plan(r.n, 16, t, 1, precision)
+        X1 = ep.expm_pfd_apply(plan, torch.from_numpy(np.asfortranarray(A)).cuda(),
+                               torch.from_numpy(np.asfortranarray(v)).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(X1.cpu().numpy(), X)
+
+
 def test_budget_admission(ep):
     """A budget too small for one workspace rejects the request; a budget for one
     group at a time still completes every request (they queue, never run out of memory)."""
