@@ -66,6 +66,21 @@ def test_serving_matrix_has_its_drawn_spectrum():
     assert np.allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(lam), atol=1e-10)
 
 
+def test_known_eigenbasis_generator():
+    """The generator used where the oracle is given the eigenpairs: U is unitary,
+    A = U diag(lam) U^H, and it draws what the serving workload's matrix draws from
+    the same seed (the same reflections and phases)."""
+    spec = (90, 7)
+    r = wl.rng_for(5, spec[1] + 1)
+    lam = r.uniform(-200.0, 0.0, spec[0])
+    A, U = wl.hermitian_with_known_eigenbasis(r, lam)
+    n = spec[0]
+    assert np.array_equal(A, A.conj().T)
+    assert np.max(np.abs(U.conj().T @ U - np.eye(n))) < 1e-14
+    assert np.max(np.abs((U * lam) @ U.conj().T - A)) < 200 * 1e-14
+    assert np.max(np.abs(A - wl.config5_matrix(spec))) < 200 * 1e-14
+
+
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
