@@ -252,7 +252,8 @@ def expm_pfd_apply(plan: Plan, A, V=None, X=None, stream=None):
 
 
 def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degree: int, precision="fp64",
-                           ir_sweeps: int = 0, stream=None, info=None, uplo="L"):
+                           ir_sweeps: int = 0, stream=None, info=None, uplo="L", shift: float = 0.0,
+                           real_data: bool = False, ir_extended: int = 0):
     """X_i = R_d(t_i A_i) V_i for every i (V_i None: V_i = I).  Returns the list of X_i.
 
     info: optional host int32 numpy array of len(As), filled with each problem's status."""
@@ -284,7 +285,7 @@ def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degr
         x = torch.empty((int(m[i]), int(n[i])), dtype=torch.complex128, device=a.device).t()
         Xs.append(x)
         ldx[i], px[i] = n[i], x.data_ptr()
-    o = _opts(precision, ir_sweeps, uplo=uplo)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, uplo=uplo)
     if info is not None and (info.dtype != np.int32 or info.size != count or not info.flags.c_contiguous):
         raise ValueError("info must be a contiguous int32 array with one entry per problem")
     _check(lib.expm_pfd_apply_batched(count, n.ctypes.data, t.ctypes.data, int(degree), pa, lda.ctypes.data, pv,
@@ -312,7 +313,7 @@ class BatchPlan:
 
 def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precision="fp64", ir_sweeps: int = 0,
                         graph: bool = False, autotune: bool = False, lu_tile=None,
-                        real_data: bool = False, uplo="L") -> BatchPlan:
+                        real_data: bool = False, uplo="L", shift: float = 0.0, ir_extended: int = 0) -> BatchPlan:
     """Batch plan for problems of orders n[i] with m[i] right-hand-side columns (0: V_i = I)."""
     lib = load_library()
     nn = np.ascontiguousarray(n, dtype=np.int64)
@@ -320,7 +321,7 @@ def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precisi
     if nn.shape != mm.shape:
         raise ValueError("n and m must have the same length")
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, 0, 0.0, real_data, graph, autotune, lu_tile, uplo)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo)
     _check(lib.expm_pfd_batch_plan(ctypes.byref(h), len(nn), nn.ctypes.data, mm.ctypes.data, int(degree),
                                    ctypes.byref(o)), "expm_pfd_batch_plan")
     return BatchPlan(h.value, nn, mm)
@@ -431,10 +432,11 @@ class Queue:
 
 
 def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_sweeps: int = 0, max_group: int = 64,
-                          streams: int = 3) -> Queue:
+                          streams: int = 3, shift: float = 0.0, real_data: bool = False,
+                          ir_extended: int = 0) -> Queue:
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data)
     _check(lib.expm_pfd_queue_create(ctypes.byref(h), int(hbm_budget), int(degree), ctypes.byref(o), int(max_group),
                                      int(streams)), "expm_pfd_queue_create")
     return Queue(h.value)

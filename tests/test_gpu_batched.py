@@ -192,3 +192,61 @@ def test_config4_full_batch(ep, precision, tol):
         p = probs[i]
         err = matrix.rel_fro(X2[i].cpu().numpy(), matrix.expm_R(p.A, p.V, p.t, 16))
         assert err < tol, (i, ns[i], err)
+
+
+def _real_symmetric(rng, n, lo, hi):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(lo, hi, n)
+    A = (Q * lam) @ Q.T
+    return (0.5 * (A + A.T)).astype(np.complex128)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_batched_shift_and_real_data(ep, precision, tol):
+    """The shifting method (Remark rem:shift) and the real-data mode (Remark
+    rem:two_time_real_part) through the batched entry points.  Spectra in [0, 20],
+    t in [0.9, 1] and c = 20 against the oracle's e^c R_d(tA - cI)V, by the one-shot call and a
+    batch plan (same bits); real symmetric problems with real V in real-data mode
+    against R_d(tA)V, with the imaginary parts of the inputs ignored."""
+    import torch
+    rng = np.random.default_rng(31)
+    probs = []
+    # one shift for the whole batch: t near 1 keeps c close to the top of every
+    # spectrum of tA (a shift far above it loses accuracy as e^{c - alpha})
+    for n, m in [(40, 3), (100, 4), (130, None), (64, 2)]:
+        lam = rng.uniform(0.0, 20.0, n)
+        A = wl.hermitian_with_spectrum(rng, lam)
+        V = None if m is None else wl.complex_gaussian(rng, n, m)
+        probs.append((A, V, float(rng.uniform(0.9, 1.0))))
+    c = 20.0
+    As = [_dev(A) for A, _, _ in probs]
+    Vs = [None if V is None else _dev(V) for _, V, _ in probs]
+    ts = [t for _, _, t in probs]
+    _announce(f"batched shift {precision} c={c}")
+    Xs = ep.expm_pfd_apply_batched(As, Vs, ts, 16, precision, shift=c)
+    torch.cuda.synchronize()
+    for (A, V, t), X in zip(probs, Xs):
+        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R_shifted(A, V, t, 16, c)) < tol
+    bp = ep.expm_pfd_batch_plan([A.shape[0] for A, _, _ in probs],
+                                [0 if V is None else V.shape[1] for _, V, _ in probs], 16, precision, shift=c)
+    Xp = ep.expm_pfd_batch_apply(bp, As, Vs, ts)
+    torch.cuda.synchronize()
+    ep.expm_pfd_batch_check(bp)
+    assert all(torch.equal(a, b) for a, b in zip(Xs, Xp))
+
+    real = []
+    for n, m in [(50, 2), (120, 5), (90, None)]:
+        A = _real_symmetric(rng, n, -60.0, 0.0)
+        V = None if m is None else rng.standard_normal((n, m)).astype(np.complex128)
+        real.append((A, V, float(rng.uniform(0.3, 1.0))))
+    _announce(f"batched real data {precision}")
+    Xr = ep.expm_pfd_apply_batched([_dev(A) for A, _, _ in real], [None if V is None else _dev(V) for _, V, _ in real],
+                                   [t for _, _, t in real], 16, precision, real_data=True)
+    Xj = ep.expm_pfd_apply_batched([_dev(A + 1j * rng.standard_normal(A.shape)) for A, _, _ in real],
+                                   [None if V is None else _dev(V + 1j * rng.standard_normal(V.shape))
+                                    for _, V, _ in real],
+                                   [t for _, _, t in real], 16, precision, real_data=True)
+    torch.cuda.synchronize()
+    for (A, V, t), X, XJ in zip(real, Xr, Xj):
+        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16)) < tol
+        assert torch.equal(X, XJ)

@@ -85,6 +85,44 @@ def test_serving_full_order_range(ep, precision, tol):
         assert np.array_equal(X1.cpu().numpy(), X)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
+def test_queue_shift_and_real_data(ep, precision, tol):
+    """Queue options: the shifting method (spectrum in [0, 15], c = 15) against the
+    oracle's e^c R_d(tA - cI)v, and the real-data mode on a real symmetric matrix and
+    real vectors against R_d(tA)v."""
+    import torch
+    from paper_2306_16778_amd import workloads as wl
+
+    rng = np.random.default_rng(57)
+    n, c = 150, 15.0
+    A = wl.hermitian_with_spectrum(rng, rng.uniform(0.0, 15.0, n))
+    q = ep.expm_pfd_queue_create(4 << 30, 16, precision, shift=c)
+    mid = ep.expm_pfd_register_matrix(q, torch.from_numpy(np.asfortranarray(A)).cuda())
+    vs = [wl.complex_gaussian(rng, n, 1) for _ in range(3)]
+    _announce(f"queue shift {precision} n={n} c={c}")
+    ts = [1.0, 0.95, 0.9]  # c near the top of the spectrum of tA (Remark rem:shift)
+    outs = [ep.expm_pfd_submit(q, mid, t, torch.from_numpy(np.asfortranarray(v)).cuda()) for t, v in zip(ts, vs)]
+    ep.expm_pfd_queue_drain(q)
+    for t, (_, X), v in zip(ts, outs, vs):
+        Y = matrix.expm_R_shifted(A, v, t, 16, c)
+        assert matrix.rel_fro(X.cpu().numpy(), Y) < tol
+    ep.expm_pfd_queue_destroy(q)
+
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    B = (Q * rng.uniform(-80.0, 0.0, n)) @ Q.T
+    B = (0.5 * (B + B.T)).astype(np.complex128)
+    q = ep.expm_pfd_queue_create(4 << 30, 16, precision, real_data=True)
+    mid = ep.expm_pfd_register_matrix(q, torch.from_numpy(np.asfortranarray(B)).cuda())
+    ws = [rng.standard_normal((n, 1)).astype(np.complex128) for _ in range(3)]
+    _announce(f"queue real data {precision} n={n}")
+    outs = [ep.expm_pfd_submit(q, mid, 0.4 * (k + 1), torch.from_numpy(np.asfortranarray(w)).cuda())
+            for k, w in enumerate(ws)]
+    ep.expm_pfd_queue_drain(q)
+    for k, ((_, X), w) in enumerate(zip(outs, ws)):
+        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(B, w, 0.4 * (k + 1), 16)) < tol
+    ep.expm_pfd_queue_destroy(q)
+
+
 def test_budget_admission(ep):
     """A budget too small for one workspace rejects the request; a budget for one
     group at a time still completes every request (they queue, never run out of memory)."""
