@@ -433,10 +433,10 @@ class Queue:
 
 def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_sweeps: int = 0, max_group: int = 64,
                           streams: int = 3, shift: float = 0.0, real_data: bool = False,
-                          ir_extended: int = 0) -> Queue:
+                          ir_extended: int = 0, uplo="L") -> Queue:
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data)
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, uplo=uplo)
     _check(lib.expm_pfd_queue_create(ctypes.byref(h), int(hbm_budget), int(degree), ctypes.byref(o), int(max_group),
                                      int(streams)), "expm_pfd_queue_create")
     return Queue(h.value)

@@ -122,6 +122,23 @@ def test_queue_shift_and_real_data(ep, precision, tol):
         assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(B, w, 0.4 * (k + 1), 16)) < tol
     ep.expm_pfd_queue_destroy(q)
 
+    # uplo: a queue reading the upper triangle gives the same bits as one reading the
+    # lower triangle, with the unread triangle set to NaN
+    Blo, Bup = B.copy(), B.copy()
+    Blo[np.triu_indices(n, 1)] = np.nan
+    Bup[np.tril_indices(n, -1)] = np.nan
+    res = []
+    _announce(f"queue uplo {precision} n={n}")
+    for uplo, M in (("L", Blo), ("U", Bup)):
+        q = ep.expm_pfd_queue_create(4 << 30, 16, precision, uplo=uplo)
+        mid = ep.expm_pfd_register_matrix(q, torch.from_numpy(np.asfortranarray(M)).cuda())
+        _, X = ep.expm_pfd_submit(q, mid, 0.5, torch.from_numpy(np.asfortranarray(ws[0])).cuda())
+        ep.expm_pfd_queue_drain(q)
+        res.append(X.cpu().numpy())
+        ep.expm_pfd_queue_destroy(q)
+    assert np.array_equal(res[0], res[1])
+    assert matrix.rel_fro(res[0], matrix.expm_R(B, ws[0], 0.5, 16)) < tol
+
 
 def test_budget_admission(ep):
     """A budget too small for one workspace rejects the request; a budget for one
