@@ -140,3 +140,37 @@ def test_batch_plan_reuse(ep, precision, graph, autotune):
     tol = 1e-12 if precision == "fp64" else 1e-10
     for (A, V, t), X in zip(sets[1], want[1]):
         assert matrix.rel_fro(X, matrix.expm_R(A, V, t, 16)) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_plans_on_two_streams(ep, precision):
+    """Two plans applied at the same time on two streams (each plan owns its
+    workspace and sweep control line, so only concurrent applies of one plan race)
+    give the same bits as the same applies one after another."""
+    import torch
+    rng = np.random.default_rng(404)
+    probs = []
+    for n, m in [(300, 16), (260, 4)]:
+        lam = rng.uniform(-80.0, 0.0, n)
+        A = wl.hermitian_with_spectrum(rng, lam)
+        V = wl.complex_gaussian(rng, n, m)
+        probs.append((_dev(A), _dev(V), n, m))
+    plans = [ep.expm_pfd_plan(n, 24, 0.7, m, precision) for _, _, n, m in probs]
+    _announce(f"two plans, sequential {precision}")
+    ref = []
+    for pl, (Ad, Vd, _, _) in zip(plans, probs):
+        ref.append(ep.expm_pfd_apply(pl, Ad, Vd).clone())
+    torch.cuda.synchronize()
+    _announce(f"two plans, two streams {precision}")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = [None, None]
+    for rep in range(3):
+        for i, (pl, (Ad, Vd, _, _)) in enumerate(zip(plans, probs)):
+            with torch.cuda.stream(streams[i]):
+                outs[i] = ep.expm_pfd_apply(pl, Ad, Vd, stream=streams[i])
+        torch.cuda.synchronize()
+        for pl in plans:
+            ep.expm_pfd_plan_check(pl)
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b)
