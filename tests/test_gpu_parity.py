@@ -258,3 +258,33 @@ def test_real_symmetric_fast_path(ep, precision, tol):
     # the general path on the same data agrees to the tolerance
     X2 = _run(ep, A, V, 1.0, 24, precision)
     assert matrix.rel_fro(X2, Y) < tol
+
+
+def test_apply_argument_errors(ep):
+    """Apply-time argument checks of the C ABI (synchronous, before any launch):
+    leading dimensions below n, m above the plan's m_max, V = I on a plan sized for
+    thin V, a missing A or X; the plan stays usable afterwards."""
+    import ctypes
+    import torch
+    lib = ep.load_library()
+    n, m = 70, 4
+    A, V, t = _problem(n, -20, 0, m, 606)
+    Ad, Vd = _dev(A), _dev(V)
+    X = torch.empty((m, n), dtype=torch.complex128, device="cuda").t()
+    plan = ep.expm_pfd_plan(n, 16, t, m, "fp64")
+    h, s = plan.handle, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pa, pv, px = Ad.data_ptr(), Vd.data_ptr(), X.data_ptr()
+    _announce("apply argument errors n=70 m=4")
+    assert lib.expm_pfd_apply(h, pa, n - 1, pv, n, m, px, n, s) == -4      # lda < n
+    assert lib.expm_pfd_apply(h, pa, n, pv, n - 1, m, px, n, s) == -4      # ldv < n
+    assert lib.expm_pfd_apply(h, pa, n, pv, n, m, px, n - 1, s) == -4      # ldx < n
+    assert lib.expm_pfd_apply(h, pa, n, pv, n, m + 1, px, n, s) == -2      # m > m_max
+    assert lib.expm_pfd_apply(h, pa, n, pv, n, 0, px, n, s) == -2          # m < 1
+    assert lib.expm_pfd_apply(h, pa, n, None, n, n, px, n, s) == -2        # V = I on a thin plan
+    assert lib.expm_pfd_apply(h, None, n, pv, n, m, px, n, s) == -3        # A missing
+    assert lib.expm_pfd_apply(h, pa, n, pv, n, m, None, n, s) == -3        # X missing
+    assert lib.expm_pfd_apply(None, pa, n, pv, n, m, px, n, s) == -3       # no plan
+    assert lib.expm_pfd_apply(h, pa, n, pv, n, m, px, n, s) == 0
+    torch.cuda.synchronize()
+    ep.expm_pfd_plan_check(plan)
+    assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16)) < TOL64
