@@ -168,3 +168,39 @@ def test_budget_admission(ep):
         Y = matrix.expm_R(Ah, V.cpu().numpy(), 0.1 * (k + 1), 16)
         assert matrix.rel_fro(X.cpu().numpy(), Y) < 1e-12
     ep.expm_pfd_queue_destroy(q)
+
+
+def test_queue_errors_and_poll(ep):
+    """Queue error paths and completion polling: an unknown matrix id or ticket is
+    rejected (EXPM_PFD_ERR_TICKET) without disturbing the queue, a request with more
+    than 16 columns is rejected, and polling reports each accepted request done
+    exactly when its result is final."""
+    import torch
+    from paper_2306_16778_amd import workloads as wl
+
+    n = 96
+    A = wl.config5_matrix_device((n, 11))
+    q = ep.expm_pfd_queue_create(2 << 30, 16, "fp64")
+    mid = ep.expm_pfd_register_matrix(q, A)
+    V = torch.randn(n, 1, dtype=torch.complex128, device="cuda")
+    _announce("queue error paths n=96")
+    with pytest.raises(ep.ExpmPfdError) as e:
+        ep.expm_pfd_submit(q, mid + 7, 0.5, V)
+    assert e.value.code == -10
+    with pytest.raises(ep.ExpmPfdError) as e:
+        ep.expm_pfd_poll(q, 123456789)
+    assert e.value.code == -10
+    with pytest.raises(ep.ExpmPfdError) as e:
+        ep.expm_pfd_wait(q, 987654321)
+    assert e.value.code == -10
+    with pytest.raises(ep.ExpmPfdError):
+        ep.expm_pfd_submit(q, mid, 0.5, torch.randn(n, 17, dtype=torch.complex128, device="cuda"))
+    tickets = [ep.expm_pfd_submit(q, mid, 0.2 * (k + 1), V) for k in range(4)]
+    for k, (tk, X) in enumerate(tickets):
+        ep.expm_pfd_wait(q, tk)
+        assert ep.expm_pfd_poll(q, tk)
+        Y = matrix.expm_R(A.cpu().numpy(), V.cpu().numpy(), 0.2 * (k + 1), 16)
+        assert matrix.rel_fro(X.cpu().numpy(), Y) < 1e-12
+    st = ep.expm_pfd_queue_stats_get(q)
+    assert st["completed"] == 4 and st["submitted"] == 4
+    ep.expm_pfd_queue_destroy(q)
