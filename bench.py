@@ -46,8 +46,8 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 # kernel reads and writes per launch hash to the digest below (the kernel, its
 # device helpers, the launcher and the factorization steps that choose the
 # launch shapes), otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 272.28e6 + 130.02e6,
-                     "sources_sha256": "98f65d185a2d84ba84de41a91feceec8750b7422b9006f8a588b268e38c24cd6"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 272.44e6 + 130.02e6,
+                     "sources_sha256": "e750b073c436590125e39c5d1413532bb8e2bdc84b46c3cfb71f0854ac5cd7af"}}
 
 # (file, first marker, end marker) of each source span in the digest
 TRAFFIC_SPANS = (

@@ -219,9 +219,12 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
     launch(k_gemm<R, MODE, 64, 16, 4, 1>, dim3((unsigned)((M + 63) / 64), gy));
     return;
   }
-  // whole-tile LU products (one operand, no conjugation): their own instantiation
-  if ((cls == EXPM_PFD_K_LU_GEMM || cls == EXPM_PFD_K_LU_TRSM) && M % 64 == 0 && N % 64 == 0 && K % 16 == 0 &&
-      a0.conj == 0 && split >= batch) {
+  // whole-tile products with one unconjugated operand (LU updates and U12, the
+  // refinement product, the block products of wide solves): their own
+  // instantiation, same bits as the general one
+  if ((cls == EXPM_PFD_K_LU_GEMM || cls == EXPM_PFD_K_LU_TRSM || cls == EXPM_PFD_K_IR_GEMM ||
+       cls == EXPM_PFD_K_SOLVE_GEMM) &&
+      M % 64 == 0 && N % 64 == 0 && K % 16 == 0 && a0.conj == 0 && split >= batch) {
     launch(k_gemm<R, MODE, 64, 64, 2, 2, 2>, dim3((unsigned)((M / 64) * (N / 64)), gy));
     return;
   }

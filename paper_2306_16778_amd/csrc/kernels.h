@@ -544,8 +544,9 @@ constexpr int gemm_waves() {
   return (sizeof(R) == 4 ? GEMM_WAVES_F32 : GEMM_WAVES_F64) / (BM * BN > 64 * 64 ? 2 : 1);
 }
 
-// TAG 1 (the LU trailing update) and TAG 2 (the other LU products with whole
-// tiles: the narrow K = 64 updates and U12 = L11^-1 A12) are instantiations
+// TAG 1 (the LU trailing update) and TAG 2 (the other products with whole
+// tiles: the narrow K = 64 LU updates, U12 = L11^-1 A12, the refinement product
+// and the block products of wide solves) are instantiations
 // compiled for whole tiles and chunks (M a multiple of BM, N of BN, K of 16: no
 // bounds checks or zero scaling) and an operand that is never conjugated, which
 // keeps the operand fetch free of branches; separate instantiations so kernel
