@@ -291,8 +291,14 @@ void block_inverse(hipStream_t st, int batch, const cx<R>* W, int64_t ws, int64_
   const int nmat = which == 2 ? 2 : 1;
   trace::Scope ts(st, EXPM_PFD_K_PANEL, 8.0 * batch * nsteps * nmat * NB * NB * NB / 6.0,
                   sizeof(cx<R>) * 2.0 * batch * nsteps * nmat * NB * NB);
-  hipLaunchKernelGGL((k_block_inverse<R>), dim3(16 / BI_WAVES * nmat * nsteps, batch), dim3(64 * BI_WAVES), 0, st, W,
-                     ws, ld, step0, which, dinv, ds);
+  // one 16-wave workgroup per block once a launch has enough blocks to fill the
+  // device; otherwise four 4-wave workgroups per block (same bits either way)
+  if ((int64_t)batch * nmat * nsteps >= 256)
+    hipLaunchKernelGGL((k_block_inverse<R, 16>), dim3(nmat * nsteps, batch), dim3(64 * 16), 0, st, W, ws, ld, step0,
+                       which, dinv, ds);
+  else
+    hipLaunchKernelGGL((k_block_inverse<R, 4>), dim3(4 * nmat * nsteps, batch), dim3(64 * 4), 0, st, W, ws, ld, step0,
+                       which, dinv, ds);
 }
 
 inline int grid_for(int64_t count) {

@@ -408,21 +408,22 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
 // the sweeps run as matrix-core products.  One wave per group of four columns
 // of an inverse: lane i holds row i; forward (L) or backward (U) substitution
 // with the current pivot value broadcast by readlane, the four columns carried
-// together to overlap their dependency chains.  A workgroup of BI_WAVES waves
-// loads the diagonal block into LDS once (coalesced rows) and covers
-// 4*BI_WAVES columns; the result is staged back through LDS and written as
-// whole rows.
-// grid (16/BI_WAVES * nsteps_range * (1 or 2), batch), block 64*BI_WAVES;
-// blockIdx.x encodes (step, L or U, group of 4*BI_WAVES columns).
+// together to overlap their dependency chains.  A workgroup of BIW waves
+// loads the diagonal block into LDS once (coalesced rows) and covers 4*BIW
+// columns; the result is staged back through LDS and written as whole rows.
+// BIW = 4 spreads a launch with few blocks over more CUs; BIW = 16 (one
+// workgroup per block) loads each block once and keeps more waves per CU when
+// a launch has many blocks.  Every column is computed the same way in both.
+// grid (16/BIW * nsteps_range * (1 or 2), batch), block 64*BIW;
+// blockIdx.x encodes (step, L or U, group of 4*BIW columns).
 // ---------------------------------------------------------------------------
-constexpr int BI_WAVES = 4;
-
-template <typename R>
-__global__ __launch_bounds__(64 * BI_WAVES) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride,
+template <typename R, int BIW>
+__global__ __launch_bounds__(64 * BIW) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride,
                                                                  int64_t ld, int step0, int which,
                                                                  cx<R>* __restrict__ dinvb, int64_t dstride) {
   using T = cx<R>;
-  constexpr int NB = NB_MAX, NT = 64 * BI_WAVES, GROUPS = 16 / BI_WAVES;
+  constexpr int NB = NB_MAX, NT = 64 * BIW, GROUPS = 16 / BIW;
+  static_assert(16 % BIW == 0, "whole column groups");
   __shared__ T D[NB][NB + 1];
   __shared__ T rdiag[NB];
   const int nmat = which == 2 ? 2 : 1;  // which: 0 = L only, 1 = U only, 2 = both
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(64 * BI_WAVES) void k_block_inverse(const cx<R>* __
   const T* W = Wb + b * wstride;
   const int j0 = step * NB;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int cgrp = wg * BI_WAVES + (tid >> 6);  // this wave's four columns: 4*cgrp ..
+  const int cgrp = wg * BIW + (tid >> 6);  // this wave's four columns: 4*cgrp ..
   // the 64 x 64 diagonal block into LDS: every load issued before the first
   // store (consecutive threads read consecutive columns of a row)
   {
@@ -492,9 +493,9 @@ __global__ __launch_bounds__(64 * BI_WAVES) void k_block_inverse(const cx<R>* __
     D[i][c] = keep ? x[q] : czero<T>();
   }
   __syncthreads();
-  // the workgroup's 4*BI_WAVES columns of every row, written as row segments
+  // the workgroup's 4*BIW columns of every row, written as row segments
   T* out = dinvb + b * dstride + (int64_t)step * 2 * NB * NB + (upper ? NB * NB : 0);
-  constexpr int CW = 4 * BI_WAVES;
+  constexpr int CW = 4 * BIW;
 #pragma unroll
   for (int u = 0; u < NB * CW / NT; ++u) {
     const int e = tid + NT * u;
