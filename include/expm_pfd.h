@@ -59,6 +59,8 @@ extern "C" {
 #define EXPM_PFD_ERR_TICKET  -10  /* unknown ticket or matrix id */
 #define EXPM_PFD_ERR_SYNC    -11  /* a one-launch triangular sweep found its dependency
                                      order broken (a wait hit its cap); results invalid */
+#define EXPM_PFD_ERR_SCRATCH -12  /* expm_pfd_apply_noalloc: the problem's workspace does
+                                     not fit the fixed scratch array */
 
 #define EXPM_PFD_MAX_DEGREE 64
 #define EXPM_PFD_MAX_N      8192
@@ -177,6 +179,44 @@ int expm_pfd_destroy(expm_pfd_plan_t plan);
  * plan should be destroyed), or EXPM_PFD_ERR_HIP.
  */
 int expm_pfd_plan_check(expm_pfd_plan_t plan);
+
+/* ---- single problem without device allocation ---------------------------- */
+/* Size of the library's fixed device scratch array (one per GPU the library runs
+ * on, held until the process ends). */
+#define EXPM_PFD_NOALLOC_BYTES ((size_t)128 << 20)
+
+/*
+ * expm_pfd_apply_noalloc: X = R_d(tA)V, the same computation (same kernels, same
+ * bits) as expm_pfd_plan(n, degree, t, m, opts) + expm_pfd_apply +
+ * expm_pfd_destroy, for callers that cannot allocate device memory: code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * No hipMalloc, hipFree or other allocating call is made (host memory only for
+ * the per-degree constants, computed on the first call of each degree).  The
+ * whole workspace is carved from the library's fixed device array of
+ * EXPM_PFD_NOALLOC_BYTES bytes; its device address is looked up once per device,
+ * on the first call with that device current.  Every launch is a kernel (no
+ * memset or copy nodes), so the call may be captured into a graph.
+ *   n, degree, t   as for expm_pfd_plan.
+ *   A, lda, V, ldv, m, X, ldx   as for expm_pfd_apply (V = NULL: V = I, m = n).
+ *   opts    NULL for defaults; precision, ir_sweeps, ir_extended, real_data,
+ *           lu_tile, uplo and shift apply; graph and autotune are ignored.
+ *   info    device int or NULL: written when the work completes with 0, 2 (X
+ *           holds a non-finite value), or EXPM_PFD_ERR_SYNC (a triangular
+ *           sweep lost its dependency order; X is invalid).
+ *   stream  hipStream_t as void*; the call returns without waiting.
+ * Limits: a problem whose workspace (expm_pfd_workspace_bytes with m_max = m,
+ * plus at most 13 x 255 bytes of alignment) exceeds EXPM_PFD_NOALLOC_BYTES is
+ * rejected with EXPM_PFD_ERR_SCRATCH before any device work.  Largest orders
+ * that fit at degree 16: m <= 16, FP64 n <= 896, mixed n <= 1088; V = I, FP64
+ * n <= 640, mixed n <= 512.
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents (the parts that must start at zero are cleared by each call): calls
+ * that overlap on one GPU (two streams, two host threads) race and give wrong
+ * results; calls ordered on one stream are safe.
+ */
+int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const void* A, int64_t lda, const void* V,
+                           int64_t ldv, int64_t m, void* X, int64_t ldx, const expm_pfd_opts* opts, int* info,
+                           void* stream);
 
 /* ---- batched ------------------------------------------------------------ */
 /*

@@ -32,6 +32,7 @@
 #include <mutex>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -426,11 +427,26 @@ void keep_pool_memory(int device) {
   (void)hipGetLastError();
 }
 
-int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps, int ir_extended, double shift, int real_data, const PoolArg* pool = nullptr) {
-  auto* pl = new expm_pfd_plan_s();
-  pl->pooled = pool != nullptr;
-  pl->pool = pool ? pool->s : nullptr;
+// Poles and residues of the plan: one member per conjugate pair (Im theta > 0),
+// then the shifting method of Remark rem:shift,
+//   e^c R_d(tA - cI) = sum_k (e^c a_k) (tA + (theta_k - c) I)^{-1}.
+int pole_constants(int degree, double shift, double2* theta, double2* a) {
+  if (int rc = expm_pfd_constants(degree, (double*)theta, (double*)a)) return rc;
+  if (shift != 0.0) {
+    const double ec = std::exp(shift);
+    for (int k = 0; k < degree / 2; ++k) {
+      theta[k].x -= shift;
+      a[k].x *= ec;
+      a[k].y *= ec;
+    }
+  }
+  return 0;
+}
+
+// The plan's scalar fields for G problems of padded order npad (everything but
+// the constants and the device pointers).
+void init_plan_fields(expm_pfd_plan_s* pl, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok,
+                      int precision, int ir_sweeps, int ir_extended, int real_data) {
   pl->G = G;
   pl->Gcap = G;
   pl->degree = degree;
@@ -443,26 +459,25 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
   pl->ir_ext = std::min(pl->ir_sweeps, ir_extended < 0 ? 0 : ir_extended > 0 ? ir_extended : degree >= 32 ? 1 : 0);
   pl->full_ok = full_ok;
   pl->mp_max = mp_max;
-  const Sizes sz = plan_sizes(npad, G, degree, mp_max, full_ok, precision);
   pl->npad = npad;
   pl->nsteps = (int)(npad / NB);
-  pl->cols_alloc = sz.cols;
+  pl->cols_alloc = plan_sizes(npad, G, degree, mp_max, full_ok, precision).cols;
   pl->IB = inner_width(npad, precision == EXPM_PFD_FP64);
+}
+
+int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
+                int ir_sweeps, int ir_extended, double shift, int real_data, const PoolArg* pool = nullptr) {
+  auto* pl = new expm_pfd_plan_s();
+  pl->pooled = pool != nullptr;
+  pl->pool = pool ? pool->s : nullptr;
+  init_plan_fields(pl, npad, G, degree, mp_max, full_ok, precision, ir_sweeps, ir_extended, real_data);
+  const Sizes sz = plan_sizes(npad, G, degree, mp_max, full_ok, precision);
   pl->h_theta.resize(pl->P);
   pl->h_a.resize(pl->P);
-  int rc = expm_pfd_constants(degree, (double*)pl->h_theta.data(), (double*)pl->h_a.data());
+  int rc = pole_constants(degree, shift, pl->h_theta.data(), pl->h_a.data());
   if (rc) {
     delete pl;
     return rc;
-  }
-  // shifting method: e^c R_d(tA - cI) = sum_k (e^c a_k) (tA + (theta_k - c) I)^{-1}
-  if (shift != 0.0) {
-    const double ec = std::exp(shift);
-    for (int k = 0; k < pl->P; ++k) {
-      pl->h_theta[k].x -= shift;
-      pl->h_a[k].x *= ec;
-      pl->h_a[k].y *= ec;
-    }
   }
   (void)hipGetDevice(&pl->device);
   HipErr he;
@@ -1068,6 +1083,136 @@ extern "C" int expm_pfd_plan_check(expm_pfd_plan_t pl) {
   if (hipDeviceSynchronize() != hipSuccess) return EXPM_PFD_ERR_HIP;
   const int f = sweep_fault(pl);
   return f < 0 ? EXPM_PFD_ERR_HIP : (f ? EXPM_PFD_ERR_SYNC : 0);
+}
+
+// ============================================================================
+// The single-problem path for callers that cannot allocate: the whole plan
+// workspace is carved from one fixed device array per GPU.
+// ============================================================================
+// Host code never hands this name to a kernel or a copy (on the host it only
+// stands in for the symbol): the per-device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[EXPM_PFD_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_at[SCRATCH_DEVICES] = {};  // device address of `scratch` per device (null: not looked up yet)
+
+// The current device's copy of the scratch array (looked up with that device
+// current, on its first use).
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return EXPM_PFD_ERR_HIP;
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return EXPM_PFD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_at[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return EXPM_PFD_ERR_HIP;
+    }
+    scratch_at[dev] = p;
+  }
+  *out = scratch_at[dev];
+  return 0;
+}
+
+// Lays the plan's arrays out from `base` (256-byte aligned pieces, in the
+// order of plan_sizes) and returns the bytes used; base == nullptr only counts.
+size_t carve_plan(expm_pfd_plan_s* pl, const Sizes& sz, char* base, bool mixed) {
+  size_t off = 0;
+  auto take = [&](auto** p, size_t bytes) {
+    if (base) *p = (std::remove_pointer_t<decltype(p)>)(base + off);
+    off += round_up((int64_t)bytes, 256);
+  };
+  take(&pl->d_theta, 64 * sizeof(double2));
+  take(&pl->d_a, 64 * sizeof(double2));
+  take(&pl->W, sz.w);
+  take(&pl->ipiv, sz.ipiv);
+  take(&pl->moves, sz.moves);
+  take(&pl->dinv, sz.dinv);
+  take(&pl->sweep_sync, sz.sweep);
+  take(&pl->Xs, sz.xs);
+  take(&pl->d_descs, sz.descs);
+  if (mixed) {
+    take(&pl->Ah, sz.ah);
+    take(&pl->X64, sz.x64);
+    take(&pl->R64, sz.r64);
+    take(&pl->Rpart, sz.rpart);
+  }
+  return off;
+}
+
+}  // namespace
+
+extern "C" int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const void* A, int64_t lda, const void* V,
+                                      int64_t ldv, int64_t m, void* X, int64_t ldx, const expm_pfd_opts* opts,
+                                      int* info, void* stream) {
+  if (!A || !X) return EXPM_PFD_ERR_NULL;
+  if (int e = check_degree(degree)) return e;
+  if (n < 1 || n > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
+  if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
+  if (int e = check_opts(opts)) return e;
+  if (lda < n || ldx < n) return EXPM_PFD_ERR_LD;
+  const bool full = V == nullptr;
+  if (full) {
+    if (m != n) return EXPM_PFD_ERR_DIM;
+  } else {
+    if (m < 1 || m > n) return EXPM_PFD_ERR_DIM;
+    if (ldv < n) return EXPM_PFD_ERR_LD;
+  }
+  const int precision = opts ? opts->precision : EXPM_PFD_FP64;
+  const bool mixed = precision == EXPM_PFD_MIXED;
+  const int64_t npad = round_up(n, NB);
+  // the workspace of a plan made for exactly this call (expm_pfd_plan with m_max = m)
+  const int64_t mp_max = full ? 16 : round_up(m, 16);
+  const Sizes sz = plan_sizes(npad, 1, degree, mp_max, full, precision);
+  expm_pfd_plan_s pl;
+  if (carve_plan(&pl, sz, nullptr, mixed) > EXPM_PFD_NOALLOC_BYTES) return EXPM_PFD_ERR_SCRATCH;
+  init_plan_fields(&pl, npad, 1, degree, mp_max, full, precision, opts ? opts->ir_sweeps : 0,
+                   opts ? opts->ir_extended : 0, opts ? opts->real_data : 0);
+  PoleConsts pc{};
+  if (int e = pole_constants(degree, opts ? opts->shift : 0.0, pc.theta, pc.a)) return e;
+  void* base = nullptr;
+  if (int e = scratch_address(&base)) return e;
+  carve_plan(&pl, sz, (char*)base, mixed);
+  pl.n = n;
+  pl.t = t;
+  pl.m_max = full ? 0 : m;
+  pl.upper = opts ? opts->uplo : 0;
+  pl.lu_tile = opts && opts->lu_tile > 0 ? opts->lu_tile - 1 : 0;
+  (void)hipGetDevice(&pl.device);
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_put_consts, dim3(1), dim3(64), 0, st, pl.d_theta, pl.d_a, pc, pl.P);
+  // the previous call may have left another layout here: the sweeps' control
+  // line and ready flags, and the row moves, start from zero
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)(sz.sweep / sizeof(int)))), dim3(256), 0, st,
+                     pl.sweep_sync, (int64_t)(sz.sweep / sizeof(int)));
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)(sz.moves / sizeof(int)))), dim3(256), 0, st,
+                     pl.moves, (int64_t)(sz.moves / sizeof(int)));
+  ProblemDesc one;
+  one.A = (const double2*)A;
+  one.lda = lda;
+  one.V = (const double2*)V;
+  one.ldv = full ? n : ldv;
+  one.X = (double2*)X;
+  one.ldx = ldx;
+  one.t = t;
+  one.n = (int)n;
+  one.m = (int)m;
+  one.real = pl.real_data;
+  one.upper = pl.upper;
+  one.info = info;
+  // the kernels read the descriptor from device memory, as a graph replay does
+  hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(1), 0, st, pl.d_descs, one);
+  const int mp = full ? (int)npad : (int)round_up(m, 16);
+  ProblemDesc none{};
+  if (int e = run(&pl, pl.d_descs, none, full, mp, (int)n, (int)m, st)) return e;
+  if (info) hipLaunchKernelGGL(k_sweep_status, dim3(1), dim3(1), 0, st, pl.sweep_sync, info, EXPM_PFD_ERR_SYNC);
+  return hipGetLastError() == hipSuccess ? 0 : EXPM_PFD_ERR_HIP;
 }
 
 // ============================================================================
@@ -1853,6 +1998,7 @@ extern "C" const char* expm_pfd_strerror(int code) {
     case EXPM_PFD_ERR_BUDGET: return "request exceeds the queue's HBM budget";
     case EXPM_PFD_ERR_TICKET: return "unknown ticket or matrix id";
     case EXPM_PFD_ERR_SYNC: return "a triangular sweep lost its dependency order; results are invalid";
+    case EXPM_PFD_ERR_SCRATCH: return "the problem's workspace exceeds the fixed scratch array (EXPM_PFD_NOALLOC_BYTES)";
     default: return "unknown error";
   }
 }

@@ -21,6 +21,31 @@ namespace expm {
 __global__ void k_put_desc(ProblemDesc* dst, ProblemDesc d) { *dst = d; }
 
 // ---------------------------------------------------------------------------
+// Pole and residue constants of one plan, passed by value (at most 32 pairs for
+// the largest degree, 64), and their store into device memory.  Used where the
+// workspace lives in the library's fixed device array and no host-to-device
+// copy from caller memory is wanted.
+// grid 1, block 64
+// ---------------------------------------------------------------------------
+struct PoleConsts {
+  double2 theta[32], a[32];
+};
+__global__ void k_put_consts(double2* __restrict__ theta, double2* __restrict__ a, PoleConsts c, int P) {
+  const int i = threadIdx.x;
+  if (i < P) {
+    theta[i] = c.theta[i];
+    a[i] = c.a[i];
+  }
+}
+
+// Zero fill of count ints (a kernel, not a memset node, so that a caller's
+// stream capture records only kernels).  grid-stride.
+__global__ __launch_bounds__(256) void k_fill_zero(int* __restrict__ p, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Per-problem status: *d.info = 2 if the result X (n x m, column-major) holds a
 // non-finite value (non-finite input; a zero pivot cannot occur for finite
 // Hermitian A, since |lambda + theta_k| >= |Im theta_k| > 0), else 0.  Problems
@@ -1100,6 +1125,13 @@ __global__ __launch_bounds__(256) void k_sweep_whole(int fwd, int nsteps, int cp
   const int c = blockIdx.x;
   for (int q = 0; q < nsteps; ++q)
     sweep_tile<R, false>(q, c, fwd, nsteps, cpb, d0, d1, a0, a1, split, X, sX, ldx, nullptr, 0, nullptr);
+}
+
+// After a whole pass: if any one-launch sweep of the plan lost its dependency
+// order (the sticky status word of its control line), the problem's status word
+// becomes `code` instead of the finiteness status.  grid 1, block 1
+__global__ void k_sweep_status(const int* __restrict__ ctl, int* __restrict__ info, int code) {
+  if (ctl[SW_STATUS] != 0) *info = code;
 }
 
 // ---------------------------------------------------------------------------

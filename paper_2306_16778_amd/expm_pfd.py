@@ -36,6 +36,7 @@ EXPORTED = (
     "expm_pfd_apply",
     "expm_pfd_destroy",
     "expm_pfd_plan_check",
+    "expm_pfd_apply_noalloc",
     "expm_pfd_apply_batched",
     "expm_pfd_batch_plan",
     "expm_pfd_batch_apply",
@@ -100,6 +101,8 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_apply.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
     lib.expm_pfd_destroy.argtypes = [vp]
     lib.expm_pfd_plan_check.argtypes = [vp]
+    lib.expm_pfd_apply_noalloc.argtypes = [i64, c_int, c_double, vp, i64, vp, i64, i64, vp, i64,
+                                           ctypes.POINTER(_Opts), vp, vp]
     lib.expm_pfd_apply_batched.argtypes = [c_int, vp, vp, c_int, vp, vp, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(_Opts), vp, vp]
     lib.expm_pfd_batch_plan.argtypes = [ctypes.POINTER(vp), c_int, vp, vp, c_int, ctypes.POINTER(_Opts)]
@@ -248,6 +251,41 @@ def expm_pfd_apply(plan: Plan, A, V=None, X=None, stream=None):
                               _stream_ptr(stream, torch)), "expm_pfd_apply")
     # keep staged copies alive until the stream has consumed them
     X._expm_keepalive = (Ac, V if V is None else Vc)
+    return X
+
+
+# size of the library's fixed device scratch array (EXPM_PFD_NOALLOC_BYTES)
+NOALLOC_BYTES = 128 << 20
+
+
+def expm_pfd_apply_noalloc(n: int, degree: int, t: float, A, V=None, X=None, precision="fp64",
+                           ir_sweeps: int = 0, ir_extended: int = 0, shift: float = 0.0, real_data: bool = False,
+                           lu_tile=None, uplo="L", info=None, stream=None):
+    """X = R_d(tA)V without any device allocation by the library (its fixed scratch
+    array holds the workspace).  X, when given, must be a column-major (n, m)
+    complex128 tensor; info an optional int32 device tensor of one element."""
+    import torch
+
+    lib = load_library()
+    Ac, lda = _colmajor(A, torch)
+    if Ac.shape[0] != n:
+        raise ValueError("A must be n x n")
+    if V is None:
+        Vp, ldv, m, Vc = None, n, n, None
+    else:
+        Vc, ldv = _colmajor(V, torch)
+        Vp, m = Vc.data_ptr(), Vc.shape[1]
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.complex128, device=Ac.device).t()
+    if not (X.stride(0) == 1 and X.stride(1) >= n and tuple(X.shape) == (n, m)):
+        raise ValueError("X must be a column-major (n, m) complex128 tensor")
+    if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() != 1):
+        raise ValueError("info must be a one-element int32 device tensor")
+    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, lu_tile=lu_tile, uplo=uplo)
+    _check(lib.expm_pfd_apply_noalloc(int(n), int(degree), float(t), Ac.data_ptr(), lda, Vp, ldv, m, X.data_ptr(),
+                                      X.stride(1), ctypes.byref(o), None if info is None else info.data_ptr(),
+                                      _stream_ptr(stream, torch)), "expm_pfd_apply_noalloc")
+    X._expm_keepalive = (Ac, Vc)
     return X
 
 

@@ -85,7 +85,7 @@ def test_argument_validation_without_device():
     th = np.zeros(4)
     assert lib.expm_pfd_constants(5, th.ctypes.data, th.ctypes.data) == -1
     assert lib.expm_pfd_constants(4, None, th.ctypes.data) == -3
-    for code in range(-11, 1):
+    for code in range(-12, 1):
         assert isinstance(mod.expm_pfd_strerror(code), str)
 
 
@@ -129,3 +129,27 @@ def test_batch_and_option_validation_without_device():
     # option names of the binding map onto the C struct
     assert mod._opts("mixed", 0, graph=True, autotune=True, lu_tile="64x128").lu_tile == 3
     assert ctypes.sizeof(mod._Opts) == 4 * 8 + 8
+
+
+def test_noalloc_rejects_before_device_work():
+    """The no-allocation entry point checks its arguments and its fixed scratch
+    limit on the host, before it looks the scratch array up on a device."""
+    mod, lib = _lib()
+    o = mod._Opts()
+    p = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below is rejected first
+    assert lib.expm_pfd_apply_noalloc(64, 16, 1.0, None, 64, None, 64, 64, p, 64, None, None, None) == -3
+    assert lib.expm_pfd_apply_noalloc(64, 15, 1.0, p, 64, None, 64, 64, p, 64, None, None, None) == -1
+    assert lib.expm_pfd_apply_noalloc(64, 16, 1.0, p, 63, None, 64, 64, p, 64, None, None, None) == -4
+    assert lib.expm_pfd_apply_noalloc(64, 16, 1.0, p, 64, None, 64, 63, p, 64, None, None, None) == -2
+    assert lib.expm_pfd_apply_noalloc(64, 16, 1.0, p, 64, p, 64, 65, p, 64, None, None, None) == -2
+    assert lib.expm_pfd_apply_noalloc(64, 16, float("inf"), p, 64, p, 64, 4, p, 64, None, None, None) == -7
+    # workspace beyond EXPM_PFD_NOALLOC_BYTES: FP64 thin blocks fit up to n = 896 at degree 16
+    # (12 shifted matrices of 960^2 x 16 bytes alone exceed 128 MiB at degree 24)
+    assert lib.expm_pfd_apply_noalloc(960, 16, 1.0, p, 960, p, 960, 4, p, 960, ctypes.byref(o), None, None) == -12
+    assert lib.expm_pfd_apply_noalloc(4096, 16, 1.0, p, 4096, None, 4096, 4096, p, 4096, None, None, None) == -12
+    o.precision = 1
+    assert lib.expm_pfd_apply_noalloc(1152, 16, 1.0, p, 1152, p, 1152, 16, p, 1152, ctypes.byref(o), None,
+                                      None) == -12
+    text = open(HEADER).read()
+    size = re.search(r"#define EXPM_PFD_NOALLOC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert int(size.group(1)) << int(size.group(2)) == mod.NOALLOC_BYTES
