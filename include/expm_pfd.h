@@ -75,8 +75,10 @@ extern "C" {
 
 typedef struct expm_pfd_opts {
   int precision;   /* EXPM_PFD_FP64 (default) or EXPM_PFD_MIXED */
-  int ir_sweeps;   /* MIXED: refinement sweeps per solve; <= 0 selects the default
-                      (2, or 3 for degree >= 32) */
+  int ir_max_iter; /* MIXED: most refinement sweeps per solve; 0 selects the default
+                      (2, or 3 for degree >= 32), a negative value none.  With the
+                      convergence test (ir_tol >= 0) fewer run when every solve of
+                      a launch has converged. */
   int ir_extended; /* MIXED: how many of the last sweeps accumulate the residual
                       V - (tA + theta I) X in double-double (error-free products and
                       sums; needed when the shifted matrices are ill conditioned,
@@ -110,7 +112,27 @@ typedef struct expm_pfd_opts {
                       covered by the negative-spectrum error bound of the
                       Theorem of Sec. 3 (relative error controlled when c bounds
                       the spectrum).  Default 0; e^c must be finite (c < 709),
-                      otherwise EXPM_PFD_ERR_ARG. */
+                      otherwise EXPM_PFD_ERR_ARG.  With shift_scale_t, c is in
+                      units of A instead. */
+  double ir_tol;   /* MIXED: convergence test of the refinement.  After every sweep
+                      a solve (one pole of one problem, all its columns) has
+                      converged when its largest correction is at most ir_tol
+                      times its largest solution entry (max norms); once all
+                      solves of a launch have converged the remaining sweeps are
+                      skipped on the device (no host round trip; graphs replay
+                      it).  A problem with a solve that has not converged after
+                      the last sweep gets status 1: the batched entry point
+                      expm_pfd_apply_batched and the queue then solve it again on
+                      the FP64 path; expm_pfd_batch_apply reports it in `info`,
+                      expm_pfd_apply through expm_pfd_plan_check.  0 selects the
+                      default 1e-10; a negative value turns the test off (fixed
+                      sweep count, status 1 never set).  NaN: EXPM_PFD_ERR_ARG. */
+  int shift_scale_t; /* nonzero: `shift` is c in units of A, and problem i is
+                      shifted by t_i * c in units of t_i A (one c bounding the
+                      spectra of all A_i serves problems of different t_i in a
+                      batch or queue): e^(t_i c) R_d(t_i (A_i - cI)) V_i.
+                      e^(t_i c) must be finite for every apply (otherwise
+                      EXPM_PFD_ERR_ARG from the apply or submit). */
 } expm_pfd_opts;
 
 /* ---- constants (host only) ---------------------------------------------- */
@@ -176,7 +198,10 @@ int expm_pfd_destroy(expm_pfd_plan_t plan);
  * sweep whose workgroups wait on each other's results; each wait is capped,
  * and a capped wait marks the plan.  Returns 0, or EXPM_PFD_ERR_SYNC once a
  * wait has hit its cap (the plan's results since then are invalid and the
- * plan should be destroyed), or EXPM_PFD_ERR_HIP.
+ * plan should be destroyed), or EXPM_PFD_ERR_HIP.  For a MIXED plan with the
+ * refinement convergence test on (opts.ir_tol >= 0) it returns 1 when a solve
+ * of the last apply had not converged after its last sweep (X then holds the
+ * refined, unconverged result; apply again with precision FP64).
  */
 int expm_pfd_plan_check(expm_pfd_plan_t plan);
 
@@ -235,7 +260,10 @@ int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const void* A, int64
  *   info    host array of count ints, or NULL: per-problem status on return,
  *           0 = result finite, 2 = X_i holds a non-finite value (non-finite
  *           input; a zero pivot cannot occur for finite Hermitian A, since
- *           |lambda + theta_k| >= |Im theta_k| > 0).
+ *           |lambda + theta_k| >= |Im theta_k| > 0), 1 = (MIXED) a shifted
+ *           solve's refinement missed opts.ir_tol, so X_i was computed again
+ *           on the FP64 path (Sec. 4, Prop. prop:digit: the working precision
+ *           must match the accuracy sought).
  */
 int expm_pfd_apply_batched(int count, const int64_t* n, const double* t, int degree,
                            const void* const* A, const int64_t* lda, const void* const* V,
@@ -274,7 +302,8 @@ int expm_pfd_batch_plan(expm_pfd_batch_t* out, int count, const int64_t* n, cons
  *           V[i] must be NULL exactly where the plan has m[i] = 0.
  *   info    device array of count ints, or NULL: per-problem status written
  *           when the work completes (0 = finite result, 2 = non-finite values
- *           in X_i, as for expm_pfd_apply_batched).
+ *           in X_i, 1 = (MIXED) refinement missed opts.ir_tol; X_i holds the
+ *           refined result and no FP64 solve is made here).
  * Asynchronous on `stream`: uploads the problem descriptors (from pinned
  * staging the plan owns; it waits only for the previous apply's upload) and
  * enqueues or replays the groups.  Concurrent applies of one batch plan race.
@@ -336,60 +365,105 @@ int expm_pfd_trace_summary(int kernel_class, double* ms, int64_t* launches, doub
 
 /* ---- queued serving --------------------------------------------------------- */
 /*
- * A queue serves exp(t_i A_i) v_i requests as they arrive (continuous
- * batching).  A scheduler thread owned by the queue repeatedly takes the
- * pending requests whose workspace fits the HBM budget, groups them by padded
- * order and launches each group as one batched evaluation (every pole of
- * every request in the group in each launch) on one of several worker
- * streams, so groups overlap on the device and requests arriving while others
- * run join the next group.  Matrices are registered once (copied into queue
- * memory, counted against the budget) and can be reused with new t and v.
- * Completion is observed by events; latency is host time from submit to the
- * observed completion.  All requests of a queue share degree and precision.
+ * A queue serves exp(t_i A_i) v_i requests as they arrive (continuous batching;
+ * Sec. 3, eq. equ:expAx per request).  A scheduler thread owned by the queue
+ * repeatedly takes the oldest pending request and the later ones whose orders
+ * are compatible with it (the padded orders of one group stay within a factor 2
+ * of each other in LU work, lo^3 >= hi^3 / 2, or all are at most 512), as many
+ * as fit the HBM budget (at most max_group), and launches the group as one
+ * batched evaluation -- every pole of every request in each launch, the
+ * group's order the largest of its requests' (smaller ones are padded with the
+ * identity) -- on a free worker stream, so groups overlap on the device and
+ * requests arriving meanwhile join the next group.  Completion is observed by
+ * one thread per worker stream sleeping on the stream's event (no polling).
+ * Latency is host time from submit to that observation.  All requests of a
+ * queue share degree and options.
+ *
+ * Matrices are either registered (copied into queue memory, counted against the
+ * budget, reusable by any number of requests with new t and v, released by
+ * expm_pfd_unregister_matrix) or passed with each request and read in place.
+ * A MIXED request whose refinement misses opts.ir_tol is solved again on the
+ * FP64 path before its ticket completes (status 1).
  * Entry points are thread-safe with respect to each other.
  */
 typedef struct expm_pfd_queue_s* expm_pfd_queue_t;
 
 typedef struct expm_pfd_queue_stats {
-  int64_t submitted, completed;
+  int64_t submitted;
+  int64_t completed;         /* requests whose result is in X */
+  int64_t failed;            /* requests failed (budget or sweep fault); not in `completed` */
+  int64_t fallbacks;         /* requests solved again on the FP64 path (status 1) */
   int64_t groups;            /* batched evaluations launched */
   double p50_ms, p99_ms;     /* latency percentiles of completed requests */
   double mean_ms, max_ms;
   double solves_per_s;       /* completed / (last completion - first submit) */
   double mean_group_size;
-  size_t peak_bytes;         /* peak of registered matrices + in-flight workspace */
+  int64_t padded_up;         /* requests evaluated in a group of a larger padded order */
+  size_t peak_bytes;         /* peak of registered matrices + in-flight and cached workspace */
+  int64_t registered;        /* matrices registered and not yet freed */
+  size_t registered_bytes;
 } expm_pfd_queue_stats;
 
 /*
- * hbm_budget  device bytes the queue may hold (registered matrices plus
- *             in-flight workspace); a request whose workspace alone exceeds
- *             it is rejected by expm_pfd_submit with EXPM_PFD_ERR_BUDGET.
+ * hbm_budget  device bytes the queue may hold: registered matrices, in-flight
+ *             workspace and idle cached workspace (released when needed).  A
+ *             request whose workspace alone cannot fit next to the registered
+ *             matrices is rejected by expm_pfd_submit with EXPM_PFD_ERR_BUDGET.
  * degree      even degree used for every request.
+ * opts        precision, refinement, real-data, uplo and shift options of every
+ *             request (graph, autotune: ignored); NULL for defaults.
  * max_group   most requests evaluated together (<= 0: 64).
  * streams     worker streams (<= 0: 3).
  */
 int expm_pfd_queue_create(expm_pfd_queue_t* q, size_t hbm_budget, int degree, const expm_pfd_opts* opts,
                           int max_group, int streams);
 
-/* Copy the n x n column-major device matrix A (lower triangle read) into the
- * queue; *mat_id identifies it in expm_pfd_submit.  Synchronous. */
-int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, int64_t* mat_id);
+/*
+ * Register the n x n column-major device matrix A (lower triangle read, or the
+ * upper one with opts.uplo) with the queue: a copy in queue memory (from the
+ * device's stream-ordered pool), made on `stream` after the caller's work
+ * already enqueued there, so A may be reused once that stream passes the copy.
+ * *mat_id identifies it in expm_pfd_submit.  Returns at once.
+ * EXPM_PFD_ERR_BUDGET: the copy does not fit next to the registered matrices
+ * and the work in flight (unregister matrices no longer needed).
+ */
+int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, void* stream,
+                             int64_t* mat_id);
+
+/* Release a registered matrix: no new request may name it; its memory returns to
+ * the budget once the requests already submitted for it have completed.
+ * EXPM_PFD_ERR_TICKET for an unknown or already released id. */
+int expm_pfd_unregister_matrix(expm_pfd_queue_t q, int64_t mat_id);
 
 /*
- * Enqueue X = R_d(t A_mat) V.  V: device n x m column-major (ldv >= n), m <= 16;
- * X: device n x m (ldx >= n), written when the ticket completes.  V and X must
- * stay valid and V unchanged until then.  Returns at once.
+ * Enqueue X = R_d(t A) V.
+ *   mat_id, A  A == NULL: the registered matrix mat_id (n and lda are not
+ *           read); otherwise (mat_id ignored) the caller's n x n device matrix
+ *           A with leading dimension lda, read in place: it must stay valid and
+ *           unchanged until the ticket completes.
+ *   V       device n x m column-major (ldv >= n), 1 <= m <= 16;
+ *   X       device n x m (ldx >= n), written when the ticket completes.  V and X
+ *           must stay valid and V unchanged until then.
+ *   stream  the caller's stream whose work already enqueued writes A and V
+ *           (an event recorded on it orders the request after that work);
+ *           NULL: the null stream.
+ * Returns at once with *ticket.  EXPM_PFD_ERR_ARG: t not finite or e^(shift)
+ * overflows; EXPM_PFD_ERR_TICKET: unknown or released mat_id.
  */
-int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, const void* V, int64_t m, int64_t ldv, void* X,
-                    int64_t ldx, uint64_t* ticket);
+int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, const void* A, int64_t n, int64_t lda, double t,
+                    const void* V, int64_t m, int64_t ldv, void* X, int64_t ldx, void* stream, uint64_t* ticket);
 
-/* *done = 1 once the ticket's result is in X (0 otherwise).  Returns
- * EXPM_PFD_ERR_BUDGET for a request that was failed because it could no longer
- * fit the budget (matrices registered after it was submitted filled it). */
-int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done);
-/* Block until the ticket completes (same return codes as expm_pfd_poll). */
-int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket);
-/* Block until every submitted request completes. */
+/* *done = 1 once the ticket's result is in X (0 otherwise); *info (may be NULL)
+ * its status then: 0, 1 (MIXED: refinement missed opts.ir_tol, X solved again
+ * on the FP64 path) or 2 (non-finite values in X).  Returns
+ * EXPM_PFD_ERR_BUDGET for a request failed because it could no longer fit the
+ * budget (matrices registered after it was submitted filled it) and
+ * EXPM_PFD_ERR_SYNC for one whose triangular sweeps lost their order. */
+int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done, int* info);
+/* Block until the ticket completes (same return codes and *info as expm_pfd_poll). */
+int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket, int* info);
+/* Block until every submitted request has completed or failed; returns 0, or
+ * the error code of a failed request (EXPM_PFD_ERR_BUDGET, EXPM_PFD_ERR_SYNC). */
 int expm_pfd_queue_drain(expm_pfd_queue_t q);
 int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats* out);
 /* Drain, stop the scheduler and free everything the queue owns. */

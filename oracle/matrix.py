@@ -88,6 +88,26 @@ def expm_exact(A, V, t: float, eig=None):
     return _apply_spectral(U, np.exp(t * w), V)
 
 
+def pfd_amplification(A, V, t: float, d: int, eig=None) -> float:
+    """sum_k |a_k| ||(tA + theta_k I)^{-1} V||_F / ||R_d(tA) V||_F over all d poles.
+
+    The rounding of each shifted solve (relative size u) enters the pole sum
+    weighted by its residue, as in the scalar bound of Prop. prop:digit
+    (sum_k |a_k| times the digit error); relative to the result this factor
+    multiplies u.  So about u times this factor is the accuracy any FP64
+    evaluation of the partial fractions can reach.  It is >= 1 (triangle
+    inequality).  Frobenius norms are unitarily invariant, so with A = U
+    diag(w) U^H only U^H V is needed.
+    """
+    w, U = eig if eig is not None else _eig(A)
+    theta, a = scalar.pfd_all(d)
+    W = U.conj().T if V is None else U.conj().T @ np.asarray(V, dtype=np.complex128)
+    x = t * w
+    num = sum(abs(ak) * np.linalg.norm(W / (x + th)[:, None]) for th, ak in zip(theta, a))
+    den = np.linalg.norm(W * scalar.R_direct(x, d)[:, None])
+    return float(num / den)
+
+
 def rel_fro(X, Y) -> float:
     """||X - Y||_F / ||Y||_F."""
     X = np.asarray(X)

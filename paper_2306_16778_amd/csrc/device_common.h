@@ -226,7 +226,11 @@ struct ProblemDesc {
   int n, m;
   int real;   // 1: A and V are real; their imaginary parts are not read
   int upper;  // 1: the upper triangle of A is read instead of the lower one
-  int* info;  // device word for this problem's status (0, or 2: non-finite result); may be null
+  int* info;  // device word for this problem's status (0, 1: refinement missed its
+              // tolerance, 2: non-finite result); may be null
+  double c;   // shift of the shifting method in units of tA (0: none): the problem's
+              // poles are theta_k - c and its residues e^c a_k
+  double ec;  // e^c, rounded once on the host
 };
 // descriptor g of a group: from the device array, or the single inline one
 __device__ __forceinline__ ProblemDesc desc_of(const ProblemDesc* arr, const ProblemDesc& one, int g) {

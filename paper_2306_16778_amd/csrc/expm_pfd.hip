@@ -29,6 +29,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <tuple>
@@ -197,27 +198,49 @@ void panel(hipStream_t st, int IB, int S, const PanelArgs& g, cx<R>* W) {
 constexpr int LU_TILES = 3;
 const char* const LU_TILE_NAMES[LU_TILES] = {"64x64", "128x64", "64x128"};
 
+// The plain and (GATABLE) the gated kernel of one k_gemm instantiation.
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0, bool GATABLE = true>
+struct GemmKernels {
+  static constexpr bool gatable = GATABLE;
+  static constexpr auto plain = &k_gemm<R, MODE, BM, BN, WGM, WGN, TAG>;
+  static constexpr auto gated = &k_gemm_gated<R, MODE, BM, BN, WGM, WGN, TAG>;
+};
+
 // MODE 0: C -= op(A) B;  MODE 1: C = op(A) B.  Batches < split use a0, others a1.
 // tile: LU trailing-update shape (index into LU_TILE_NAMES), MODE 0 only.
+// gate: non-null for products of refinement sweeps (skipped once *gate == 0).
 template <typename R, int MODE>
 void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
           const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp = {1, 0, 0, 0},
-          int tile = 0) {
+          int tile = 0, const int* gate = nullptr) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return;
   const double e = sizeof(cx<R>);
   const double Kt = (double)K * ksp.ks;
   trace::Scope ts(st, cls, 8.0 * batch * (double)M * N * Kt,
                   e * batch * ((double)M * Kt + Kt * N + (MODE == 0 ? 2.0 : (double)ksp.ks) * M * N), true);
   const unsigned gy = (unsigned)(batch * ksp.ks);
-  auto launch = [&](auto kernel, dim3 grid) {
-    if (ts.active)
-      hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, st, ts.r.a, ts.r.b, 0, M, N, K, a0, a1, split, B, sB, ldb,
-                            C, sC, ldc, ksp);
-    else
-      hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
+  auto launch = [&](auto kernels, dim3 grid) {
+    using K2 = decltype(kernels);
+    if constexpr (K2::gatable) {
+      if (gate != nullptr) {
+        if (ts.active)
+          hipExtLaunchKernelGGL(K2::gated, grid, dim3(256), 0, st, ts.r.a, ts.r.b, 0, gate, M, N, K, a0, a1, split,
+                                B, sB, ldb, C, sC, ldc, ksp);
+        else
+          hipLaunchKernelGGL(K2::gated, grid, dim3(256), 0, st, gate, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc,
+                             ksp);
+        return;
+      }
+    }
+    if (ts.active) {
+      hipExtLaunchKernelGGL(K2::plain, grid, dim3(256), 0, st, ts.r.a, ts.r.b, 0, M, N, K, a0, a1, split, B, sB,
+                            ldb, C, sC, ldc, ksp);
+    } else {
+      hipLaunchKernelGGL(K2::plain, grid, dim3(256), 0, st, M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
+    }
   };
   if (N <= 16 && cls != EXPM_PFD_K_LU_GEMM && cls != EXPM_PFD_K_LU_TRAIL && cls != EXPM_PFD_K_LU_TRSM) {
-    launch(k_gemm<R, MODE, 64, 16, 4, 1>, dim3((unsigned)((M + 63) / 64), gy));
+    launch(GemmKernels<R, MODE, 64, 16, 4, 1>{}, dim3((unsigned)((M + 63) / 64), gy));
     return;
   }
   // whole-tile products with one unconjugated operand (LU updates and U12, the
@@ -226,33 +249,36 @@ void gemm(hipStream_t st, int cls, int batch, int M, int N, int K, GemmOperand<R
   if ((cls == EXPM_PFD_K_LU_GEMM || cls == EXPM_PFD_K_LU_TRSM || cls == EXPM_PFD_K_IR_GEMM ||
        cls == EXPM_PFD_K_SOLVE_GEMM) &&
       M % 64 == 0 && N % 64 == 0 && K % 16 == 0 && a0.conj == 0 && split >= batch) {
-    launch(k_gemm<R, MODE, 64, 64, 2, 2, 2>, dim3((unsigned)((M / 64) * (N / 64)), gy));
+    launch(GemmKernels<R, MODE, 64, 64, 2, 2, 2>{}, dim3((unsigned)((M / 64) * (N / 64)), gy));
     return;
   }
   if constexpr (MODE == 0) {
     const bool trail = cls == EXPM_PFD_K_LU_TRAIL && K % 16 == 0 && a0.conj == 0;
     if (tile == 1) {
       if (trail && M % 128 == 0 && N % 64 == 0)
-        launch(k_gemm<R, MODE, 128, 64, 2, 2, 1>, dim3((unsigned)((M / 128) * (N / 64)), gy));
+        launch(GemmKernels<R, MODE, 128, 64, 2, 2, 1, false>{}, dim3((unsigned)((M / 128) * (N / 64)), gy));
       else
-        launch(k_gemm<R, MODE, 128, 64, 2, 2>, dim3((unsigned)(((M + 127) / 128) * ((N + 63) / 64)), gy));
+        launch(GemmKernels<R, MODE, 128, 64, 2, 2, 0, false>{},
+               dim3((unsigned)(((M + 127) / 128) * ((N + 63) / 64)), gy));
       return;
     }
     if (tile == 2) {
       if (trail && M % 64 == 0 && N % 128 == 0)
-        launch(k_gemm<R, MODE, 64, 128, 2, 2, 1>, dim3((unsigned)((M / 64) * (N / 128)), gy));
+        launch(GemmKernels<R, MODE, 64, 128, 2, 2, 1, false>{}, dim3((unsigned)((M / 64) * (N / 128)), gy));
       else
-        launch(k_gemm<R, MODE, 64, 128, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
+        launch(GemmKernels<R, MODE, 64, 128, 2, 2, 0, false>{},
+               dim3((unsigned)(((M + 63) / 64) * ((N + 127) / 128)), gy));
       return;
     }
     // the trailing update's own instantiation needs whole tiles and chunks (always
     // so: padded orders and panel widths are multiples of 64); otherwise the general one
     if (cls == EXPM_PFD_K_LU_TRAIL && M % 64 == 0 && N % 64 == 0 && K % 16 == 0 && a0.conj == 0) {
-      launch(k_gemm<R, MODE, 64, 64, 2, 2, 1>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
+      launch(GemmKernels<R, MODE, 64, 64, 2, 2, 1, false>{},
+             dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
       return;
     }
   }
-  launch(k_gemm<R, MODE, 64, 64, 2, 2>, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
+  launch(GemmKernels<R, MODE, 64, 64, 2, 2>{}, dim3((unsigned)(((M + 63) / 64) * ((N + 63) / 64)), gy));
 }
 
 // K slices of the FP64 refinement product (t A) X for thin right-hand sides: a
@@ -274,14 +300,15 @@ GemmOperand<R> opnd(const cx<R>* p, int64_t stride, int64_t ld, bool conj) {
   return o;
 }
 
+// gate: see KSplit (nullptr: always runs)
 template <typename R>
 void moves_apply(hipStream_t st, int batch, cx<R>* Bm, int64_t sB, int64_t ldb, int ncols, int gap_at, int gap_len,
-                 const int* moves, int64_t smv, int s_begin, int s_end, int inverse) {
+                 const int* moves, int64_t smv, int s_begin, int s_end, int inverse, const int* gate = nullptr) {
   if (ncols <= 0 || s_end <= s_begin) return;
   trace::Scope ts(st, EXPM_PFD_K_MOVES, 0.0, 0.0);
   const int g = (ncols + 15) / 16;
   hipLaunchKernelGGL((k_moves<R, 16>), dim3(g, batch), dim3(256), 0, st, Bm, sB, ldb, ncols, gap_at, gap_len, moves,
-                     smv, s_begin, s_end, inverse);
+                     smv, s_begin, s_end, inverse, gate);
 }
 
 // which: 0 = L11^{-1}, 1 = U11^{-1}, 2 = both, for steps [step0, step0 + nsteps)
@@ -318,6 +345,9 @@ struct expm_pfd_plan_s {
   int64_t n = 0, npad = 0, m_max = 0;  // n, m_max: the single-problem arguments
   int G = 1, degree = 0, P = 0, PB = 0, precision = EXPM_PFD_FP64, ir_sweeps = 2, IB = 16, nsteps = 0;
   int ir_ext = 0;  // last sweeps with double-double residuals
+  double ir_tol = 1e-10;  // convergence test of the refinement (< 0: none, fixed sweep count)
+  double shift = 0.0;     // c of the shifting method (tA units, or A units with shift_t)
+  int shift_t = 0;        // the shift is in units of A: problem i uses t_i * shift
   int real_data = 0;  // A and V real: conjugate poles need no solves of their own
   int upper = 0;      // the upper triangle of A is read
   int Gcap = 1;  // problems the workspace was sized for; G <= Gcap is the active count
@@ -340,6 +370,9 @@ struct expm_pfd_plan_s {
   double2* X64 = nullptr;    // mixed: npad x cols_alloc
   double2* R64 = nullptr;    // mixed: npad x cols_alloc
   double2* Rpart = nullptr;  // mixed: ir_kslices(npad) x npad x (2 PB min(mp_max, 64)) split-K partials
+  int* ir_words = nullptr;   // mixed: [0] refinement gate, [1] the check's finish counter, [2 + g] problem
+                             // g's solves missed ir_tol (g < G), then one convergence word per block
+  unsigned long long* ir_max = nullptr;  // mixed: 2 x 2PB per-block maxima of the convergence test
   ProblemDesc* d_descs = nullptr;  // G problem descriptors on the device (batched entry point)
   int device = 0;
   bool pooled = false;             // workspace from the stream-ordered pool (freed on `pool`)
@@ -354,8 +387,10 @@ namespace {
 
 struct Sizes {
   int64_t npad, cols, w_elem;
-  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, rpart, consts, descs;
-  size_t total() const { return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + rpart + consts + descs; }
+  size_t w, ipiv, moves, dinv, sweep, xs, ah, x64, r64, rpart, consts, descs, irw, irm;
+  size_t total() const {
+    return w + ipiv + moves + dinv + sweep + xs + ah + x64 + r64 + rpart + consts + descs + irw + irm;
+  }
 };
 
 Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision) {
@@ -377,6 +412,9 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
   s.rpart = fp64 ? 0 : (size_t)ir_kslices(npad) * npad * (2 * PB * std::min<int64_t>(mp_max, CHAIN_MP_MAX)) * 16;
   s.consts = 2 * 64 * 16;
   s.descs = (size_t)G * sizeof(ProblemDesc);
+  s.irw = fp64 ? 0 : (size_t)(2 + G + 2 * PB) * sizeof(int);
+  // two per workgroup of the per-block refinement kernels (at most max(2048, 2 PB) workgroups)
+  s.irm = fp64 ? 0 : (size_t)2 * std::max<int64_t>(2048, 2 * PB) * sizeof(unsigned long long);
   return s;
 }
 
@@ -385,16 +423,26 @@ int check_opts(const expm_pfd_opts* o) {
   if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
   if (o->lu_tile < 0 || o->lu_tile > LU_TILES) return EXPM_PFD_ERR_ARG;
   if (o->uplo != EXPM_PFD_LOWER && o->uplo != EXPM_PFD_UPPER) return EXPM_PFD_ERR_ARG;
-  if (!std::isfinite(o->shift) || !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
+  if (!std::isfinite(o->shift)) return EXPM_PFD_ERR_ARG;
+  if (!o->shift_scale_t && !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
+  if (std::isnan(o->ir_tol)) return EXPM_PFD_ERR_ARG;
   return 0;
+}
+
+// Shift of one problem in units of its tA (c = shift, or t * shift when the
+// shift is given in units of A) and e^c; EXPM_PFD_ERR_ARG if e^c overflows.
+int problem_shift(double shift, int scale_t, double t, ProblemDesc& d) {
+  d.c = scale_t ? t * shift : shift;
+  d.ec = std::exp(d.c);
+  return std::isfinite(d.c) && std::isfinite(d.ec) ? 0 : EXPM_PFD_ERR_ARG;
 }
 
 void free_plan(expm_pfd_plan_t p) {
   if (!p) return;
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->cap) (void)hipStreamDestroy(p->cap);
-  void* ptrs[] = {p->d_theta, p->d_a, p->W,  p->ipiv, p->moves, p->dinv,
-                  p->sweep_sync, p->Xs, p->Ah, p->X64,  p->R64,   p->Rpart, p->d_descs};
+  void* ptrs[] = {p->d_theta, p->d_a, p->W,     p->ipiv,    p->moves,    p->dinv,  p->sweep_sync, p->Xs,
+                  p->Ah,      p->X64, p->R64,   p->Rpart,   p->d_descs, p->ir_words, p->ir_max};
   for (void* q : ptrs)
     if (q) (void)(p->pooled ? hipFreeAsync(q, p->pool) : hipFree(q));
   delete p;
@@ -427,26 +475,18 @@ void keep_pool_memory(int device) {
   (void)hipGetLastError();
 }
 
-// Poles and residues of the plan: one member per conjugate pair (Im theta > 0),
-// then the shifting method of Remark rem:shift,
-//   e^c R_d(tA - cI) = sum_k (e^c a_k) (tA + (theta_k - c) I)^{-1}.
-int pole_constants(int degree, double shift, double2* theta, double2* a) {
-  if (int rc = expm_pfd_constants(degree, (double*)theta, (double*)a)) return rc;
-  if (shift != 0.0) {
-    const double ec = std::exp(shift);
-    for (int k = 0; k < degree / 2; ++k) {
-      theta[k].x -= shift;
-      a[k].x *= ec;
-      a[k].y *= ec;
-    }
-  }
-  return 0;
+// Poles and residues of the plan: one member per conjugate pair (Im theta > 0).
+// The shifting method of Remark rem:shift,
+//   e^c R_d(tA - cI) = sum_k (e^c a_k) (tA + (theta_k - c) I)^{-1},
+// is applied per problem by the kernels (ProblemDesc::c, ::ec).
+int pole_constants(int degree, double2* theta, double2* a) {
+  return expm_pfd_constants(degree, (double*)theta, (double*)a);
 }
 
 // The plan's scalar fields for G problems of padded order npad (everything but
 // the constants and the device pointers).
 void init_plan_fields(expm_pfd_plan_s* pl, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok,
-                      int precision, int ir_sweeps, int ir_extended, int real_data) {
+                      int precision, int ir_max_iter, int ir_extended, int real_data, double ir_tol) {
   pl->G = G;
   pl->Gcap = G;
   pl->degree = degree;
@@ -454,7 +494,8 @@ void init_plan_fields(expm_pfd_plan_s* pl, int64_t npad, int G, int degree, int6
   pl->PB = G * pl->P;
   pl->precision = precision;
   // degree >= 32: one more sweep, the last with a double-double residual
-  pl->ir_sweeps = ir_sweeps > 0 ? ir_sweeps : degree >= 32 ? 3 : 2;
+  pl->ir_sweeps = ir_max_iter > 0 ? ir_max_iter : ir_max_iter < 0 ? 0 : degree >= 32 ? 3 : 2;
+  pl->ir_tol = ir_tol == 0.0 ? 1e-10 : ir_tol;
   pl->real_data = real_data ? 1 : 0;
   pl->ir_ext = std::min(pl->ir_sweeps, ir_extended < 0 ? 0 : ir_extended > 0 ? ir_extended : degree >= 32 ? 1 : 0);
   pl->full_ok = full_ok;
@@ -465,16 +506,21 @@ void init_plan_fields(expm_pfd_plan_s* pl, int64_t npad, int G, int degree, int6
   pl->IB = inner_width(npad, precision == EXPM_PFD_FP64);
 }
 
+// opts: the options that shape the plan's work (precision excepted): refinement
+// sweeps, tolerance and extended sweeps, real data, shift (NULL: defaults)
 int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, int precision,
-                int ir_sweeps, int ir_extended, double shift, int real_data, const PoolArg* pool = nullptr) {
+                const expm_pfd_opts* opts, const PoolArg* pool = nullptr) {
   auto* pl = new expm_pfd_plan_s();
   pl->pooled = pool != nullptr;
   pl->pool = pool ? pool->s : nullptr;
-  init_plan_fields(pl, npad, G, degree, mp_max, full_ok, precision, ir_sweeps, ir_extended, real_data);
+  init_plan_fields(pl, npad, G, degree, mp_max, full_ok, precision, opts ? opts->ir_max_iter : 0,
+                   opts ? opts->ir_extended : 0, opts ? opts->real_data : 0, opts ? opts->ir_tol : 0.0);
+  pl->shift = opts ? opts->shift : 0.0;
+  pl->shift_t = opts && opts->shift_scale_t ? 1 : 0;
   const Sizes sz = plan_sizes(npad, G, degree, mp_max, full_ok, precision);
   pl->h_theta.resize(pl->P);
   pl->h_a.resize(pl->P);
-  int rc = pole_constants(degree, shift, pl->h_theta.data(), pl->h_a.data());
+  int rc = pole_constants(degree, pl->h_theta.data(), pl->h_a.data());
   if (rc) {
     delete pl;
     return rc;
@@ -498,6 +544,8 @@ int create_plan(expm_pfd_plan_t* out, int64_t npad, int G, int degree, int64_t m
     dmalloc(&pl->X64, sz.x64);
     dmalloc(&pl->R64, sz.r64);
     dmalloc(&pl->Rpart, sz.rpart);
+    dmalloc(&pl->ir_words, sz.irw);
+    dmalloc(&pl->ir_max, sz.irm);
   }
   if (he.e == hipSuccess && pool) {
     // the constants' host copies live in the plan, so the copies may complete later
@@ -773,7 +821,8 @@ SweepOperand<R> sweep_op(const cx<R>* p, int64_t stride, int64_t ld, bool conj) 
 // Thin right-hand sides (mp <= CHAIN_MP_MAX): each sweep is one launch in which
 // every 16-column chain runs its block steps back to back (k_sweep_chain).
 template <typename R>
-void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st,
+                  const int* gate) {
   const int PB = pl->PB;
   const int npad = (int)pl->npad;
   const int64_t ld = npad, ws = (int64_t)npad * npad;
@@ -785,7 +834,7 @@ void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoin
   const int nblk = adjoint ? 2 * PB : PB;
   const int cpb = mp / 16, nchain = nblk * cpb;
   const double e = sizeof(cx<R>);
-  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0, gate);
   for (int dirn = 0; dirn < 2; ++dirn) {
     const bool fwd = dirn == 0;
     // forward: L (primal), U^H (adjoint); backward: U (primal), L^H (adjoint)
@@ -799,18 +848,21 @@ void solves_chain(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoin
     const unsigned nwg = (unsigned)nchain * (unsigned)nsteps;
     if (nchain >= WHOLE_CHAIN_MIN)
       hipLaunchKernelGGL((k_sweep_whole<R>), dim3((unsigned)nchain), dim3(256), 0, st, fwd ? 1 : 0, nsteps, cpb, d0,
-                         d1, a0, a1, PB, X, (int64_t)mp, ldS);
+                         d1, a0, a1, PB, X, (int64_t)mp, ldS, gate);
     else
       hipLaunchKernelGGL((k_sweep_chain<R>), dim3(nwg), dim3(256), 0, st, fwd ? 1 : 0, nsteps, nchain, cpb, d0, d1,
-                         a0, a1, PB, X, (int64_t)mp, ldS, pl->sweep_sync);
+                         a0, a1, PB, X, (int64_t)mp, ldS, pl->sweep_sync, gate);
   }
-  if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
+  if (adjoint)
+    moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1, gate);
 }
 
+// gate: see KSplit (nullptr: always runs)
 template <typename R>
-void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st) {
+void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hipStream_t st,
+            const int* gate = nullptr) {
   if (mp <= CHAIN_MP_MAX) {
-    solves_chain<R>(pl, X, ldS, mp, adjoint, st);
+    solves_chain<R>(pl, X, ldS, mp, adjoint, st, gate);
     return;
   }
   const int PB = pl->PB;
@@ -823,7 +875,7 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
   const int nsteps = pl->nsteps;
   const int nb_batch = adjoint ? 2 * PB : PB;  // primal blocks 0..PB-1, adjoint blocks PB..2PB-1
   // P^T on the primal blocks
-  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0);
+  moves_apply<R>(st, PB, X, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 0, gate);
   // forward sweeps: L (primal) and U^H (adjoint); diagonal blocks by their inverses
   for (int s = 0; s < nsteps; ++s) {
     const int j0 = s * NB, nb = std::min(NB, npad - j0);
@@ -832,11 +884,12 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
     const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
     const cx<R>* Uinv = Linv + NB * NB;
     gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Linv, ds, NB, false),
-               opnd<R>(Uinv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+               opnd<R>(Uinv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS,
+               {1, 0, 0, 0}, 0, gate);
     if (below > 0)
       gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, below, mp, nb, opnd<R>(W + r1 * ld + j0, ws, ld, false),
                  opnd<R>(W + (int64_t)j0 * ld + r1, ws, ld, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + r1 * ldS,
-                 mp, ldS);
+                 mp, ldS, {1, 0, 0, 0}, 0, gate);
   }
   // backward sweeps: U (primal) and L^H (adjoint)
   for (int s = nsteps - 1; s >= 0; --s) {
@@ -844,13 +897,16 @@ void solves(expm_pfd_plan_t pl, cx<R>* X, int64_t ldS, int mp, bool adjoint, hip
     const cx<R>* Linv = dinv + (int64_t)s * 2 * NB * NB;
     const cx<R>* Uinv = Linv + NB * NB;
     gemm<R, 1>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, nb, mp, nb, opnd<R>(Uinv, ds, NB, false),
-               opnd<R>(Linv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS);
+               opnd<R>(Linv, ds, NB, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X + (int64_t)j0 * ldS, mp, ldS,
+               {1, 0, 0, 0}, 0, gate);
     if (j0 > 0)
       gemm<R, 0>(st, EXPM_PFD_K_SOLVE_GEMM, nb_batch, j0, mp, nb, opnd<R>(W + j0, ws, ld, false),
-                 opnd<R>(W + (int64_t)j0 * ld, ws, ld, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS);
+                 opnd<R>(W + (int64_t)j0 * ld, ws, ld, true), PB, X + (int64_t)j0 * ldS, mp, ldS, X, mp, ldS,
+                 {1, 0, 0, 0}, 0, gate);
   }
   // P on the adjoint blocks
-  if (adjoint) moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1);
+  if (adjoint)
+    moves_apply<R>(st, PB, X + (int64_t)PB * mp, mp, ldS, mp, mp, 0, pl->moves, mstride, 0, nsteps, 1, gate);
 }
 
 // ---- one pass of the whole path over the plan's G problems ------------------------
@@ -886,47 +942,58 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
     {
       trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
       hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
-                         one);
+                         one, nullptr);
     }
     solves<double>(pl, Xs, ldS, mp, adj, st);
     accumulate(Xs);
-  } else {
-    factor<float>(pl, descs, one, st);
-    float2* Xs = (float2*)pl->Xs;
+    // per-problem status words (only written where the descriptor names one)
+    if (descs) hipLaunchKernelGGL(k_status, dim3((unsigned)G), dim3(256), 0, st, descs, one, nullptr);
+    return 0;
+  }
+  factor<float>(pl, descs, one, st);
+  float2* Xs = (float2*)pl->Xs;
+  {
+    trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 8.0 * count);
+    hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs, one,
+                       nullptr);
+  }
+  solves<float>(pl, Xs, ldS, mp, adj, st);
+  {
+    trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
+  }
+  // Convergence test (ir_tol >= 0): after every sweep, each solve's largest
+  // correction against its largest entry.  Once every solve of the launch has
+  // converged, the gate word is 0 and the later sweeps' kernels return at once,
+  // with no host round trip (captured graphs keep the same launches).
+  const bool test = pl->ir_tol >= 0.0;
+  int* gate = test ? pl->ir_words : nullptr;
+  unsigned* done = test ? (unsigned*)pl->ir_words + 1 : nullptr;
+  int* nc = test ? pl->ir_words + 2 : nullptr;
+  int* conv = test ? pl->ir_words + 2 + G : nullptr;
+  // (with no sweep at all no solve has been shown to meet the tolerance)
+  if (test)
+    hipLaunchKernelGGL(k_ir_begin, dim3(1), dim3(256), 0, st, gate, nc, G, pl->ir_sweeps == 0 ? 1 : 0, done);
+  const int64_t nn = (int64_t)npad * npad;
+  // per-block kernels: about 2048 workgroups in all, each block's elements grid-strided
+  const int64_t per_blk = (int64_t)npad * mp;
+  const dim3 gblk((unsigned)std::max<int64_t>(1, std::min<int64_t>((per_blk + 255) / 256, 2048 / nblk)),
+                  (unsigned)nblk);
+  for (int it = 0; it < pl->ir_sweeps; ++it) {
+    // R = V - (tA + theta I) X in FP64 for every pole solve: one product per
+    // problem and half (primal / adjoint blocks) with the problem's FP64 t*A
     {
-      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 8.0 * count);
-      hipLaunchKernelGGL((k_stage<float>), dim3(grid_for(count)), dim3(256), 0, st, Xs, ldS, npad, mp, PB, P, descs,
-                         one);
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
+      hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, PB, P,
+                         descs, one, gate);
     }
-    solves<float>(pl, Xs, ldS, mp, adj, st);
-    {
-      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 24.0 * count);
-      hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(count)), dim3(256), 0, st, Xs, pl->X64, count);
-    }
-    const int64_t nn = (int64_t)npad * npad;
-    for (int it = 0; it < pl->ir_sweeps; ++it) {
-      // R = V - (tA + theta I) X in FP64 for every pole solve: one product per
-      // problem and half (primal / adjoint blocks) with the problem's FP64 t*A
-      {
-        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, e64 * count);
-        hipLaunchKernelGGL((k_stage<double>), dim3(grid_for(count)), dim3(256), 0, st, pl->R64, ldS, npad, mp, PB, P,
-                           descs, one);
-      }
-      if (it >= pl->ir_sweeps - pl->ir_ext) {
-        // the last sweeps: residual accumulated in double-double
-        {
-          trace::Scope ts(st, EXPM_PFD_K_IR_GEMM, 8.0 * (double)npad * npad * ldS,
-                          e64 * ((double)G * npad * npad + 3.0 * count) + 8.0 * count);
-          hipLaunchKernelGGL(k_residual_dd, dim3((unsigned)(npad / 64), (unsigned)(ldS / 16)), dim3(256), 0, st,
-                             pl->Ah, nn, pl->X64, pl->R64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
-        }
-        solves<float>(pl, Xs, ldS, mp, adj, st);
-        {
-          trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
-          hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
-        }
-        continue;
-      }
+    if (it >= pl->ir_sweeps - pl->ir_ext) {
+      // the last sweeps: residual accumulated in double-double
+      trace::Scope ts(st, EXPM_PFD_K_IR_GEMM, 8.0 * (double)npad * npad * ldS,
+                      e64 * ((double)G * npad * npad + 3.0 * count) + 8.0 * count);
+      hipLaunchKernelGGL(k_residual_dd, dim3((unsigned)(npad / 64), (unsigned)(ldS / 16)), dim3(256), 0, st, pl->Ah,
+                         nn, pl->X64, pl->R64, ldS, npad, mp, PB, P, pl->d_theta, descs, one, Xs, gate);
+    } else {
       // up to 64 right-hand-side columns per pole: the product in K slices
       // (partials in Rpart, too few output tiles otherwise); wider blocks and
       // V = I: subtracted from R64 directly
@@ -938,7 +1005,7 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
           const int64_t off = (int64_t)half * PB * mp;
           gemm<double, 0>(st, EXPM_PFD_K_IR_GEMM, G, npad, P * mp, npad, opnd<double>(pl->Ah, nn, npad, false),
                           opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS, pl->R64 + off,
-                          (int64_t)P * mp, ldS);
+                          (int64_t)P * mp, ldS, KSplit{1, 0, 0, 0}, 0, gate);
         }
       } else {
         const int Ks = npad / S;
@@ -949,24 +1016,26 @@ int run(expm_pfd_plan_t pl, const ProblemDesc* descs, const ProblemDesc& one, bo
           const int64_t off = (int64_t)half * PB * mp;
           gemm<double, 1>(st, EXPM_PFD_K_IR_GEMM, G, npad, ncols, Ks, opnd<double>(pl->Ah, nn, npad, false),
                           opnd<double>(nullptr, 0, 0, false), G, pl->X64 + off, (int64_t)P * mp, ldS,
-                          pl->Rpart + off, (int64_t)P * mp, ldS, ksp);
+                          pl->Rpart + off, (int64_t)P * mp, ldS, ksp, 0, gate);
         }
       }
-      {
-        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, (2.0 + S) * e64 * count + 8.0 * count);
-        hipLaunchKernelGGL(k_residual32, dim3(grid_for(count)), dim3(256), 0, st, pl->R64, pl->Rpart, S, pstride,
-                           pl->X64, ldS, npad, mp, PB, P, pl->d_theta, Xs);
-      }
-      solves<float>(pl, Xs, ldS, mp, adj, st);
-      {
-        trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
-        hipLaunchKernelGGL(k_add_correction, dim3(grid_for(count)), dim3(256), 0, st, pl->X64, Xs, count);
-      }
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 8.0 * count, (2.0 + S) * e64 * count + 8.0 * count);
+      hipLaunchKernelGGL(k_residual32, gblk, dim3(256), 0, st, pl->R64, pl->Rpart, S, pstride, pl->X64, ldS, npad, mp,
+                         PB, P, pl->d_theta, descs, one, Xs, gate);
     }
-    accumulate(pl->X64);
+    solves<float>(pl, Xs, ldS, mp, adj, st, gate);
+    {
+      trace::Scope ts(st, EXPM_PFD_K_ELEMENTWISE, 0.0, 40.0 * count);
+      hipLaunchKernelGGL(k_add_correction, gblk, dim3(256), 0, st, pl->X64, Xs, ldS, npad, mp,
+                         test ? pl->ir_max : nullptr, gate);
+    }
+    if (test)
+      hipLaunchKernelGGL(k_ir_check, dim3((unsigned)nblk), dim3(64), 0, st, pl->ir_max, nblk, (int)gblk.x, PB, P,
+                         pl->ir_tol, gate, nc, conv, done);
   }
+  accumulate(pl->X64);
   // per-problem status words (only written where the descriptor names one)
-  if (descs) hipLaunchKernelGGL(k_status, dim3((unsigned)G), dim3(256), 0, st, descs, one);
+  if (descs) hipLaunchKernelGGL(k_status, dim3((unsigned)G), dim3(256), 0, st, descs, one, nc);
   return 0;
 }
 
@@ -1014,8 +1083,7 @@ extern "C" int expm_pfd_plan(expm_pfd_plan_t* out, int64_t n, int degree, double
   const bool full_ok = (m_max == 0 || m_max >= n);
   const int64_t mp = round_up(std::min<int64_t>(m_max == 0 ? n : m_max, n), 16);
   expm_pfd_plan_t pl = nullptr;
-  int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64,
-                       opts ? opts->ir_sweeps : 0, opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, opts ? opts->real_data : 0);
+  int rc = create_plan(&pl, round_up(n, NB), 1, degree, mp, full_ok, opts ? opts->precision : EXPM_PFD_FP64, opts);
   if (rc) return rc;
   pl->n = n;
   pl->t = t;
@@ -1054,6 +1122,7 @@ extern "C" int expm_pfd_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, co
   one.real = pl->real_data;
   one.upper = pl->upper;
   one.info = nullptr;
+  if (problem_shift(pl->shift, pl->shift_t, pl->t, one)) return EXPM_PFD_ERR_ARG;
   (void)hipGetLastError();
   const int mp = full ? (int)pl->npad : (int)round_up(m, 16);
   if (pl->use_graph && trace::mask == 0) {
@@ -1082,7 +1151,13 @@ extern "C" int expm_pfd_plan_check(expm_pfd_plan_t pl) {
   if (!pl) return EXPM_PFD_ERR_NULL;
   if (hipDeviceSynchronize() != hipSuccess) return EXPM_PFD_ERR_HIP;
   const int f = sweep_fault(pl);
-  return f < 0 ? EXPM_PFD_ERR_HIP : (f ? EXPM_PFD_ERR_SYNC : 0);
+  if (f) return f < 0 ? EXPM_PFD_ERR_HIP : EXPM_PFD_ERR_SYNC;
+  if (pl->precision == EXPM_PFD_MIXED && pl->ir_tol >= 0.0) {
+    int nc = 0;
+    if (hipMemcpy(&nc, pl->ir_words + 2, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return EXPM_PFD_ERR_HIP;
+    if (nc) return 1;
+  }
+  return 0;
 }
 
 // ============================================================================
@@ -1141,6 +1216,8 @@ size_t carve_plan(expm_pfd_plan_s* pl, const Sizes& sz, char* base, bool mixed) 
     take(&pl->X64, sz.x64);
     take(&pl->R64, sz.r64);
     take(&pl->Rpart, sz.rpart);
+    take(&pl->ir_words, sz.irw);
+    take(&pl->ir_max, sz.irm);
   }
   return off;
 }
@@ -1171,10 +1248,12 @@ extern "C" int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const voi
   const Sizes sz = plan_sizes(npad, 1, degree, mp_max, full, precision);
   expm_pfd_plan_s pl;
   if (carve_plan(&pl, sz, nullptr, mixed) > EXPM_PFD_NOALLOC_BYTES) return EXPM_PFD_ERR_SCRATCH;
-  init_plan_fields(&pl, npad, 1, degree, mp_max, full, precision, opts ? opts->ir_sweeps : 0,
-                   opts ? opts->ir_extended : 0, opts ? opts->real_data : 0);
+  init_plan_fields(&pl, npad, 1, degree, mp_max, full, precision, opts ? opts->ir_max_iter : 0,
+                   opts ? opts->ir_extended : 0, opts ? opts->real_data : 0, opts ? opts->ir_tol : 0.0);
+  ProblemDesc one;
+  if (problem_shift(opts ? opts->shift : 0.0, opts ? opts->shift_scale_t : 0, t, one)) return EXPM_PFD_ERR_ARG;
   PoleConsts pc{};
-  if (int e = pole_constants(degree, opts ? opts->shift : 0.0, pc.theta, pc.a)) return e;
+  if (int e = pole_constants(degree, pc.theta, pc.a)) return e;
   void* base = nullptr;
   if (int e = scratch_address(&base)) return e;
   carve_plan(&pl, sz, (char*)base, mixed);
@@ -1189,11 +1268,10 @@ extern "C" int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const voi
   hipLaunchKernelGGL(k_put_consts, dim3(1), dim3(64), 0, st, pl.d_theta, pl.d_a, pc, pl.P);
   // the previous call may have left another layout here: the sweeps' control
   // line and ready flags, and the row moves, start from zero
-  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)(sz.sweep / sizeof(int)))), dim3(256), 0, st,
-                     pl.sweep_sync, (int64_t)(sz.sweep / sizeof(int)));
-  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)(sz.moves / sizeof(int)))), dim3(256), 0, st,
-                     pl.moves, (int64_t)(sz.moves / sizeof(int)));
-  ProblemDesc one;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(sz.sweep / sizeof(int)))), dim3(256), 0, st, pl.sweep_sync,
+                     (int64_t)(sz.sweep / sizeof(int)), 0);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)(sz.moves / sizeof(int)))), dim3(256), 0, st, pl.moves,
+                     (int64_t)(sz.moves / sizeof(int)), 0);
   one.A = (const double2*)A;
   one.lda = lda;
   one.V = (const double2*)V;
@@ -1211,7 +1289,7 @@ extern "C" int expm_pfd_apply_noalloc(int64_t n, int degree, double t, const voi
   const int mp = full ? (int)npad : (int)round_up(m, 16);
   ProblemDesc none{};
   if (int e = run(&pl, pl.d_descs, none, full, mp, (int)n, (int)m, st)) return e;
-  if (info) hipLaunchKernelGGL(k_sweep_status, dim3(1), dim3(1), 0, st, pl.sweep_sync, info, EXPM_PFD_ERR_SYNC);
+  if (info) hipLaunchKernelGGL(k_sweep_status, dim3(1), dim3(64), 0, st, pl.sweep_sync, info, 1, EXPM_PFD_ERR_SYNC);
   return hipGetLastError() == hipSuccess ? 0 : EXPM_PFD_ERR_HIP;
 }
 
@@ -1228,7 +1306,9 @@ struct expm_pfd_batch_s {
     int mp = 0, nmax = 0, mmax = 0;
     double work = 0;  // G * npad^3: the schedule's load estimate
   };
-  int count = 0, degree = 0, real_data = 0, upper = 0, use_graph = 0, autotune = 0;
+  int count = 0, degree = 0, real_data = 0, upper = 0, use_graph = 0, autotune = 0, precision = 0;
+  double shift = 0.0;  // c of the shifting method (tA units, or A units with shift_t)
+  int shift_t = 0;
   int schedule = 0;  // concurrent branches the groups run on (0: not chosen yet)
   std::vector<int64_t> n, m;  // m[i] = 0: V_i = I
   std::vector<Group> groups;
@@ -1403,6 +1483,9 @@ int batch_plan_impl(expm_pfd_batch_t* out, int count, const int64_t* n, const in
   b->upper = opts ? opts->uplo : 0;
   b->use_graph = opts ? (opts->graph ? 1 : 0) : 0;
   b->autotune = opts ? (opts->autotune ? 1 : 0) : 0;
+  b->precision = precision;
+  b->shift = opts ? opts->shift : 0.0;
+  b->shift_t = opts && opts->shift_scale_t ? 1 : 0;
   b->n.assign(n, n + count);
   b->m.assign(m, m + count);
   // groups: same padded order and same kind (V = I, or 16-column-rounded width)
@@ -1421,8 +1504,7 @@ int batch_plan_impl(expm_pfd_batch_t* out, int count, const int64_t* n, const in
       g.mmax = std::max<int>(g.mmax, (int)(m[i] ? m[i] : n[i]));
     }
     g.work = (double)G * npad * npad * npad;
-    rc = create_plan(&g.pl, npad, G, degree, g.full ? 16 : mpk, g.full, precision, opts ? opts->ir_sweeps : 0,
-                     opts ? opts->ir_extended : 0, opts ? opts->shift : 0.0, b->real_data, pool);
+    rc = create_plan(&g.pl, npad, G, degree, g.full ? 16 : mpk, g.full, precision, opts, pool);
     if (rc) break;
     b->groups.push_back(std::move(g));
     expm_pfd_plan_t pl = b->groups.back().pl;
@@ -1459,6 +1541,8 @@ extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const v
     if ((V[i] == nullptr) != (b->m[i] == 0)) return EXPM_PFD_ERR_ARG;
     if (lda[i] < b->n[i] || ldx[i] < b->n[i] || (V[i] && ldv[i] < b->n[i])) return EXPM_PFD_ERR_LD;
     if (!std::isfinite(t[i])) return EXPM_PFD_ERR_ARG;
+    ProblemDesc d;
+    if (problem_shift(b->shift, b->shift_t, t[i], d)) return EXPM_PFD_ERR_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
   (void)hipGetLastError();
@@ -1482,6 +1566,7 @@ extern "C" int expm_pfd_batch_apply(expm_pfd_batch_t b, const double* t, const v
       d.real = b->real_data;
       d.upper = b->upper;
       d.info = info ? info + i : nullptr;
+      (void)problem_shift(b->shift, b->shift_t, t[i], d);  // checked above
     }
     if (hipMemcpyAsync(g.pl->d_descs, hd, g.idx.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice, st) !=
         hipSuccess)
@@ -1543,18 +1628,55 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
   (void)hipGetDevice(&dev);
   keep_pool_memory(dev);
   const PoolArg pa{st};
-  expm_pfd_batch_t b = nullptr;
-  if (int e = batch_plan_impl(&b, count, n, mk.data(), degree, opts, &pa)) return e;
-  int* dinfo = nullptr;
-  int rc = 0;
-  if (info && hipMallocAsync((void**)&dinfo, (size_t)count * sizeof(int), st) != hipSuccess) rc = EXPM_PFD_ERR_OOM;
-  if (!rc) rc = expm_pfd_batch_apply(b, t, A, lda, V, ldv, X, ldx, dinfo, stream);
-  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
-  if (!rc) rc = expm_pfd_batch_check(b);
-  if (!rc && info && hipMemcpy(info, dinfo, (size_t)count * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-    rc = EXPM_PFD_ERR_HIP;
-  if (dinfo) (void)hipFreeAsync(dinfo, st);
-  expm_pfd_batch_destroy(b);
+  std::vector<int> hinfo(count, 0);
+  // one batched pass over the problems listed in `idx`; their status into hinfo
+  auto pass = [&](const std::vector<int>& idx, const expm_pfd_opts* o) -> int {
+    const int c = (int)idx.size();
+    std::vector<int64_t> n2(c), m2(c), lda2(c), ldv2(c), ldx2(c);
+    std::vector<double> t2(c);
+    std::vector<const void*> A2(c), V2(c);
+    std::vector<void*> X2(c);
+    for (int k = 0; k < c; ++k) {
+      const int i = idx[k];
+      n2[k] = n[i], m2[k] = mk[i], lda2[k] = lda[i], ldv2[k] = ldv[i], ldx2[k] = ldx[i], t2[k] = t[i];
+      A2[k] = A[i], V2[k] = V[i], X2[k] = X[i];
+    }
+    expm_pfd_batch_t b = nullptr;
+    if (int e = batch_plan_impl(&b, c, n2.data(), m2.data(), degree, o, &pa)) return e;
+    int* dinfo = nullptr;
+    int rc = 0;
+    if (hipMallocAsync((void**)&dinfo, (size_t)c * sizeof(int), st) != hipSuccess) rc = EXPM_PFD_ERR_OOM;
+    if (!rc)
+      rc = expm_pfd_batch_apply(b, t2.data(), A2.data(), lda2.data(), V2.data(), ldv2.data(), X2.data(), ldx2.data(),
+                                dinfo, stream);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = EXPM_PFD_ERR_HIP;
+    if (!rc) rc = expm_pfd_batch_check(b);
+    std::vector<int> h(c, 0);
+    if (!rc && hipMemcpy(h.data(), dinfo, (size_t)c * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = EXPM_PFD_ERR_HIP;
+    for (int k = 0; k < c && !rc; ++k) hinfo[idx[k]] = h[k];
+    if (dinfo) (void)hipFreeAsync(dinfo, st);
+    expm_pfd_batch_destroy(b);
+    return rc;
+  };
+  std::vector<int> all(count);
+  for (int i = 0; i < count; ++i) all[i] = i;
+  int rc = pass(all, opts);
+  // FP64 fallback: problems whose refinement missed its tolerance are solved
+  // again on the FP64 path; their status stays 1 (or 2 for a non-finite result)
+  if (!rc && opts && opts->precision == EXPM_PFD_MIXED) {
+    std::vector<int> redo;
+    for (int i = 0; i < count; ++i)
+      if (hinfo[i] == 1) redo.push_back(i);
+    if (!redo.empty()) {
+      expm_pfd_opts o = *opts;
+      o.precision = EXPM_PFD_FP64;
+      rc = pass(redo, &o);
+      for (int i : redo)
+        if (hinfo[i] == 0) hinfo[i] = 1;
+    }
+  }
+  if (!rc && info) std::memcpy(info, hinfo.data(), (size_t)count * sizeof(int));
   return rc;
 }
 
@@ -1563,219 +1685,349 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
 // ============================================================================
 struct expm_pfd_queue_s {
   using clock = std::chrono::steady_clock;
+  enum { PENDING = 1, DONE = 2, FAIL_BUDGET = 3, FAIL_SYNC = 4 };
   struct Req {
-    uint64_t ticket;
-    int64_t mat;
-    double t;
-    const void* V;
-    int64_t m, ldv;
-    void* X;
-    int64_t ldx;
+    uint64_t ticket = 0;
+    int64_t mat = -1;                // registered matrix, or -1: the caller's A read in place
+    const double2* A = nullptr;      // the matrix the request reads
+    int64_t n = 0, lda = 0;
+    double t = 1.0;
+    const void* V = nullptr;
+    int64_t m = 0, ldv = 0;
+    void* X = nullptr;
+    int64_t ldx = 0;
+    hipEvent_t ready = nullptr;      // recorded on the caller's stream at submit (inputs written)
+    hipEvent_t mat_ready = nullptr;  // the registered copy is complete
     clock::time_point submitted;
+    int fp64 = 0;                    // FP64 re-solve after the mixed refinement missed its tolerance
   };
   struct Mat {
     double2* A = nullptr;
     int64_t n = 0;
+    size_t bytes = 0;
+    int refs = 0;           // requests submitted and not yet completed
+    bool released = false;  // unregistered: freed once refs is 0
+    hipEvent_t ready = nullptr;
   };
   struct Flight {
-    hipEvent_t ev = nullptr;
-    int stream = 0;
-    expm_pfd_plan_t plan = nullptr;
     std::vector<Req> reqs;
     std::vector<ProblemDesc> descs;  // source of the descriptor upload, kept until completion
+    expm_pfd_plan_t plan = nullptr;
     size_t bytes = 0;
+    bool launched = false;  // its work is enqueued and its stream event recorded
+  };
+  struct Ticket {
+    int state = PENDING;
+    int info = 0;
   };
 
   std::mutex mu;
-  std::condition_variable cv, cv_done;
+  std::condition_variable cv;         // scheduler: new requests, completed flights, freed memory, stop
+  std::condition_variable cv_flight;  // waiters: a flight was launched on their stream
+  std::condition_variable cv_done;    // callers: a ticket completed
   std::deque<Req> pending;
-  std::unordered_map<uint64_t, int> state;  // 1 pending/in flight, 2 done, 3 failed (budget), 4 failed (sweep)
-  std::vector<Mat> mats;
-  std::vector<Flight> flights;
-  std::map<std::pair<int64_t, int>, std::vector<expm_pfd_plan_t>> free_plans;  // (npad, Gcap)
+  std::unordered_map<uint64_t, Ticket> tickets;
+  std::map<int64_t, Mat> mats;
+  int64_t next_mat = 0;
+  std::vector<std::unique_ptr<Flight>> flight;  // per worker stream: the flight in progress (or null)
+  std::map<std::tuple<int64_t, int, int>, std::vector<expm_pfd_plan_t>> free_plans;  // (npad, Gcap, precision)
   std::vector<hipStream_t> streams;
-  std::vector<bool> busy;
+  std::vector<hipEvent_t> stream_ev;  // per worker stream: completion of its flight (blocking sync)
+  hipStream_t aux = nullptr;          // frees of released matrices
+  int* dev_status = nullptr;          // per worker stream: max_group status words on the device ...
+  int* host_status = nullptr;         // ... and their pinned host copies
+  std::vector<hipEvent_t> event_pool;
   std::thread worker;
-  bool stop = false;
+  std::vector<std::thread> waiters;
+  bool stop = false;          // no more submissions: the scheduler ends once all is done
+  bool stop_waiters = false;  // set after the scheduler has ended
   size_t budget = 0, mat_bytes = 0, flight_bytes = 0, cached_bytes = 0, peak = 0;
-  int degree = 16, precision = EXPM_PFD_FP64, ir = 0, ir_ext = 0, max_group = 64, device = 0;
-  double shift = 0.0;
-  int real_data = 0;
-  int upper = 0;    // registered matrices: upper triangle read
-  int lu_tile = 0;  // LU trailing-update tile shape of every plan the queue creates
+  expm_pfd_opts opts{};  // precision and refinement options of every request
+  int degree = 16, max_group = 64, device = 0;
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, completed = 0, failed = 0, groups = 0, grouped = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, fallbacks = 0, groups = 0, grouped = 0, padded_up = 0;
   std::vector<double> lat_ms;
   clock::time_point first_submit, last_done;
   bool any_submit = false;
 
-  size_t plan_bytes(int64_t npad, int Gcap) const {
-    return plan_sizes(npad, Gcap, degree, 16, false, precision).total();
+  // Orders within one group: the padded order of the group is the largest of
+  // its requests; a request joins when the group's orders stay within a factor
+  // 2 of each other in LU work (hi^3 <= 2 lo^3), or when every order is at
+  // most SMALL_PAD, where a pass is bound by its launch sequence rather than
+  // by its arithmetic.
+  static constexpr int64_t SMALL_PAD = 512;
+  static bool orders_compatible(int64_t lo, int64_t hi) { return hi <= SMALL_PAD || hi * hi * hi <= 2 * lo * lo * lo; }
+
+  size_t plan_bytes(int64_t npad, int Gcap, int prec) const {
+    return plan_sizes(npad, Gcap, degree, 16, false, prec).total();
   }
-  // plans are cached by (padded order, capacity); capacities are powers of two
-  static int capacity_for(int G) {
+  static int capacity_for(int G) {  // plans are cached by capacity: powers of two
     int c = 1;
     while (c < G) c <<= 1;
     return c;
   }
+  size_t held() const { return mat_bytes + flight_bytes + cached_bytes; }
+  void note_peak() { peak = std::max(peak, held()); }
+  hipEvent_t take_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    return e;
+  }
+  void give_event(hipEvent_t e) {
+    if (e) event_pool.push_back(e);
+  }
+  // free cached plans until `need` more bytes fit the budget
   void release_cached(size_t need) {
-    // free cached plans until `need` more bytes fit the budget
-    for (auto it = free_plans.begin(); it != free_plans.end() && mat_bytes + flight_bytes + cached_bytes + need > budget;) {
+    for (auto it = free_plans.begin(); it != free_plans.end() && held() + need > budget;) {
       auto& v = it->second;
-      while (!v.empty() && mat_bytes + flight_bytes + cached_bytes + need > budget) {
-        cached_bytes -= plan_bytes(it->first.first, it->first.second);
+      while (!v.empty() && held() + need > budget) {
+        cached_bytes -= plan_bytes(std::get<0>(it->first), std::get<1>(it->first), std::get<2>(it->first));
         free_plan(v.back());
         v.pop_back();
       }
       it = v.empty() ? free_plans.erase(it) : std::next(it);
     }
   }
-  void retire() {
-    for (size_t i = 0; i < flights.size();) {
-      Flight& f = flights[i];
-      if (hipEventQuery(f.ev) != hipSuccess) {
-        ++i;
-        continue;
-      }
-      const auto now = clock::now();
-      const bool bad = sweep_fault(f.plan) != 0;
-      for (const Req& r : f.reqs) {
-        state[r.ticket] = bad ? 4 : 2;
-        if (bad)
-          ++failed;
-        else
-          lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
-        ++completed;
-      }
-      last_done = now;
-      busy[f.stream] = false;
-      flight_bytes -= f.bytes;
-      if (bad) {
-        free_plan(f.plan);  // its sweep counters can no longer be trusted
-      } else {
-        cached_bytes += f.bytes;
-        free_plans[{f.plan->npad, f.plan->Gcap}].push_back(f.plan);
-      }
-      (void)hipEventDestroy(f.ev);
-      flights.erase(flights.begin() + i);
-      cv_done.notify_all();
-    }
+  void free_matrix(std::map<int64_t, Mat>::iterator it) {
+    Mat& mt = it->second;
+    // the copy may still be in flight on the registering stream
+    (void)hipStreamWaitEvent(aux, mt.ready, 0);
+    (void)hipFreeAsync(mt.A, aux);
+    give_event(mt.ready);
+    mat_bytes -= mt.bytes;
+    mats.erase(it);
   }
-  // launch one group on a free stream; returns false if nothing could be launched
-  bool launch_one() {
+  void drop_ref(int64_t mat) {
+    if (mat < 0) return;
+    auto it = mats.find(mat);
+    if (it == mats.end()) return;
+    if (--it->second.refs == 0 && it->second.released) free_matrix(it);
+  }
+  void finish(Req& r, int state, int info, clock::time_point now) {
+    Ticket& tk = tickets[r.ticket];
+    tk.state = state;
+    tk.info = info;
+    if (state == DONE) {
+      lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.submitted).count());
+      ++completed;
+      last_done = now;
+    } else {
+      ++failed;
+    }
+    give_event(r.ready);
+    r.ready = nullptr;
+    drop_ref(r.mat);
+  }
+  // Completion of stream s's flight (its event has completed): statuses from the
+  // pinned copies, FP64 re-solves queued for requests whose refinement missed
+  // its tolerance, the plan back to the cache.
+  void retire(int s) {
+    Flight& f = *flight[s];
+    const auto now = clock::now();
+    const int* st = host_status + (size_t)s * max_group;
+    bool sync_fault = false;
+    std::vector<Req> redo;
+    for (size_t k = 0; k < f.reqs.size(); ++k) {
+      Req& r = f.reqs[k];
+      const int code = st[k];
+      if (code == EXPM_PFD_ERR_SYNC) {
+        sync_fault = true;
+        finish(r, FAIL_SYNC, 0, now);
+      } else if (code == 1 && !r.fp64) {
+        Req again = r;
+        again.fp64 = 1;
+        redo.push_back(again);
+      } else {
+        // a re-solve on the FP64 path keeps status 1 (2 if its result is not finite)
+        finish(r, DONE, r.fp64 && code == 0 ? 1 : code, now);
+      }
+    }
+    // re-solves go first, oldest first (their inputs are still the caller's)
+    for (auto it = redo.rbegin(); it != redo.rend(); ++it) pending.push_front(*it);
+    fallbacks += (int64_t)redo.size();
+    flight_bytes -= f.bytes;
+    if (sync_fault) {
+      free_plan(f.plan);  // its sweep control line can no longer be trusted
+    } else {
+      cached_bytes += f.bytes;
+      free_plans[std::make_tuple(f.plan->npad, f.plan->Gcap, f.plan->precision)].push_back(f.plan);
+    }
+    flight[s].reset();
+    cv_done.notify_all();
+    cv.notify_all();
+  }
+  // Launch one group on a free stream; false if nothing could be launched.
+  // Called with `lk` held; the group is chosen under the lock, its launches are
+  // enqueued with the lock released (a group is hundreds of launches, which
+  // submitters and the waiters should not wait for).
+  bool launch_one(std::unique_lock<std::mutex>& lk) {
     int s = -1;
     for (int i = 0; i < (int)streams.size(); ++i)
-      if (!busy[i]) {
+      if (!flight[i]) {
         s = i;
         break;
       }
     if (s < 0 || pending.empty()) return false;
-    const int64_t npad = round_up(mats[pending.front().mat].n, NB);
+    const int prec = pending.front().fp64 ? EXPM_PFD_FP64 : opts.precision;
+    // the group: the oldest request, then later ones (same precision) in arrival
+    // order while the orders stay compatible
     std::vector<size_t> pick;
-    for (size_t i = 0; i < pending.size() && (int)pick.size() < max_group; ++i)
-      if (round_up(mats[pending[i].mat].n, NB) == npad) pick.push_back(i);
-    // largest group whose workspace fits next to the registered matrices and the
-    // flights (cached idle plans can be released to make room)
-    int G = (int)pick.size();
-    int Gcap = capacity_for(G);
+    int64_t lo = round_up(pending.front().n, NB), hi = lo;
+    for (size_t i = 0; i < pending.size() && (int)pick.size() < max_group; ++i) {
+      const Req& r = pending[i];
+      if ((r.fp64 ? EXPM_PFD_FP64 : opts.precision) != prec) continue;
+      const int64_t np = round_up(r.n, NB);
+      const int64_t nlo = std::min(lo, np), nhi = std::max(hi, np);
+      if (!orders_compatible(nlo, nhi)) continue;
+      lo = nlo;
+      hi = nhi;
+      pick.push_back(i);
+    }
+    // largest leading part of the group whose workspace fits next to the
+    // registered matrices and the flights (idle cached plans can be released)
+    int G = (int)pick.size(), Gcap = capacity_for(G);
     auto reusable = [&](int cap) {
-      auto it = free_plans.find({npad, cap});
+      auto it = free_plans.find(std::make_tuple(hi, cap, prec));
       return it != free_plans.end() && !it->second.empty();
     };
     for (;;) {
-      if (reusable(Gcap) || mat_bytes + flight_bytes + plan_bytes(npad, Gcap) <= budget) break;
-      if (Gcap == 1) {
-        G = 0;
-        break;
-      }
+      if (reusable(Gcap) || mat_bytes + flight_bytes + plan_bytes(hi, Gcap, prec) <= budget) break;
+      if (Gcap == 1) return false;
       Gcap /= 2;
       G = std::min(G, Gcap);
     }
-    if (G == 0) return false;
     pick.resize(G);
+    int64_t npad = 0;  // the group's order after trimming
+    for (size_t i : pick) npad = std::max(npad, round_up(pending[i].n, NB));
     expm_pfd_plan_t pl = nullptr;
-    const size_t bytes = plan_bytes(npad, Gcap);
-    auto it = free_plans.find({npad, Gcap});
+    const size_t bytes = plan_bytes(npad, Gcap, prec);
+    auto it = free_plans.find(std::make_tuple(npad, Gcap, prec));
     if (it != free_plans.end() && !it->second.empty()) {
       pl = it->second.back();
       it->second.pop_back();
       cached_bytes -= bytes;
     } else {
       release_cached(bytes);
-      const PoolArg pa{streams[s]};
-      if (create_plan(&pl, npad, Gcap, degree, 16, false, precision, ir, ir_ext, shift, real_data, &pa) != 0) {
-        (void)hipGetLastError();
-        return false;
-      }
-      pl->lu_tile = lu_tile;
+      if (mat_bytes + flight_bytes + bytes > budget) return false;
     }
-    Flight f;
-    f.stream = s;
-    f.plan = pl;
-    f.bytes = bytes;
-    int nmax = 0, mmax = 0;
+    auto f = std::make_unique<Flight>();
+    f->plan = pl;
+    f->bytes = bytes;
     for (int g = G - 1; g >= 0; --g) {  // erase from the back so earlier indices stay valid
-      f.reqs.push_back(pending[pick[g]]);
+      f->reqs.push_back(pending[pick[g]]);
       pending.erase(pending.begin() + (int64_t)pick[g]);
     }
-    std::reverse(f.reqs.begin(), f.reqs.end());
-    for (const Req& r : f.reqs) {
+    std::reverse(f->reqs.begin(), f->reqs.end());
+    int nmax = 0, mmax = 0;
+    int* dst = dev_status + (size_t)s * max_group;
+    for (size_t k = 0; k < f->reqs.size(); ++k) {
+      const Req& r = f->reqs[k];
       ProblemDesc d;
-      d.A = mats[r.mat].A;
-      d.lda = mats[r.mat].n;
+      d.A = r.A;
+      d.lda = r.lda;
       d.V = (const double2*)r.V;
       d.ldv = r.ldv;
       d.X = (double2*)r.X;
       d.ldx = r.ldx;
       d.t = r.t;
-      d.n = (int)mats[r.mat].n;
+      d.n = (int)r.n;
       d.m = (int)r.m;
-      d.real = real_data;
-      d.upper = upper;
-      d.info = nullptr;
+      d.real = opts.real_data ? 1 : 0;
+      d.upper = opts.uplo;
+      d.info = dst + k;
+      (void)problem_shift(opts.shift, opts.shift_scale_t, r.t, d);  // checked at submit
       nmax = std::max(nmax, d.n);
       mmax = std::max(mmax, d.m);
-      f.descs.push_back(d);
+      if (round_up(r.n, NB) < npad) ++padded_up;
+      f->descs.push_back(d);
     }
-    pl->G = G;
-    pl->PB = G * pl->P;
-    hipStream_t st = streams[s];
-    (void)hipMemcpyAsync(pl->d_descs, f.descs.data(), G * sizeof(ProblemDesc), hipMemcpyHostToDevice, st);
-    ProblemDesc none{};
-    (void)run(pl, pl->d_descs, none, false, 16, nmax, mmax, st);
-    (void)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
-    (void)hipEventRecord(f.ev, st);
-    busy[s] = true;
     flight_bytes += bytes;
-    peak = std::max(peak, mat_bytes + flight_bytes + cached_bytes);
+    note_peak();
     ++groups;
     grouped += G;
-    flights.push_back(std::move(f));
+    Flight* fl = f.get();
+    flight[s] = std::move(f);  // the stream is taken; its waiter sleeps until `launched`
+    lk.unlock();
+    // ---- enqueue without the lock ----
+    hipStream_t st = streams[s];
+    bool ok = true;
+    if (!pl) {
+      const PoolArg pa{st};
+      expm_pfd_opts o = opts;
+      o.precision = prec;
+      ok = create_plan(&pl, npad, Gcap, degree, 16, false, prec, &o, &pa) == 0;
+      if (ok) pl->lu_tile = opts.lu_tile > 0 ? opts.lu_tile - 1 : 0;
+    }
+    if (ok) {
+      for (const Req& r : fl->reqs) {
+        if (r.ready) (void)hipStreamWaitEvent(st, r.ready, 0);
+        if (r.mat_ready) (void)hipStreamWaitEvent(st, r.mat_ready, 0);
+      }
+      pl->G = G;
+      pl->PB = G * pl->P;
+      (void)hipMemcpyAsync(pl->d_descs, fl->descs.data(), G * sizeof(ProblemDesc), hipMemcpyHostToDevice, st);
+      ProblemDesc none{};
+      (void)run(pl, pl->d_descs, none, false, 16, nmax, mmax, st);
+      hipLaunchKernelGGL(k_sweep_status, dim3(1), dim3(64), 0, st, pl->sweep_sync, dst, G, EXPM_PFD_ERR_SYNC);
+      (void)hipMemcpyAsync(host_status + (size_t)s * max_group, dst, G * sizeof(int), hipMemcpyDeviceToHost, st);
+      (void)hipEventRecord(stream_ev[s], st);
+    } else {
+      (void)hipGetLastError();
+    }
+    lk.lock();
+    if (!ok) {
+      // no workspace after all: the requests go back to the front, oldest first
+      for (auto r = fl->reqs.rbegin(); r != fl->reqs.rend(); ++r) pending.push_front(*r);
+      flight_bytes -= bytes;
+      --groups;
+      grouped -= G;
+      flight[s].reset();
+      return false;
+    }
+    fl->plan = pl;
+    fl->launched = true;
+    cv_flight.notify_all();
     return true;
   }
   void loop() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      retire();
-      while (launch_one()) {
+      while (launch_one(lk)) {
       }
-      if (flights.empty() && !pending.empty()) {
+      bool any_flight = false;
+      for (auto& f : flight) any_flight |= (bool)f;
+      if (!any_flight && !pending.empty()) {
         // nothing runs and the oldest request still does not fit (matrices were
         // registered after it was submitted): fail it rather than wait forever
-        const Req r = pending.front();
+        Req r = pending.front();
         pending.pop_front();
-        state[r.ticket] = 3;
-        ++completed;
-        ++failed;
+        finish(r, FAIL_BUDGET, 0, clock::now());
         cv_done.notify_all();
         continue;
       }
-      if (stop && pending.empty() && flights.empty()) break;
-      if (flights.empty())
-        cv.wait(lk, [&] { return stop || !pending.empty(); });
-      else
-        cv.wait_for(lk, std::chrono::microseconds(30));
+      if (stop && pending.empty() && !any_flight) break;
+      cv.wait(lk);
+    }
+  }
+  // One thread per worker stream: sleeps on the stream's flight event and
+  // retires the flight when it completes.
+  void wait_loop(int s) {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv_flight.wait(lk, [&] { return stop_waiters || (flight[s] && flight[s]->launched); });
+      if (!flight[s]) break;  // the scheduler has ended and nothing is in flight here
+      hipEvent_t ev = stream_ev[s];
+      lk.unlock();
+      (void)hipEventSynchronize(ev);
+      lk.lock();
+      retire(s);
     }
   }
 };
@@ -1789,78 +2041,132 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   auto* q = new expm_pfd_queue_s();
   q->budget = hbm_budget;
   q->degree = degree;
-  q->precision = opts ? opts->precision : EXPM_PFD_FP64;
-  q->ir = opts ? opts->ir_sweeps : 0;
-  q->ir_ext = opts ? opts->ir_extended : 0;
-  q->shift = opts ? opts->shift : 0.0;
-  q->real_data = opts ? opts->real_data : 0;
-  q->lu_tile = opts && opts->lu_tile > 0 ? opts->lu_tile - 1 : 0;
-  q->upper = opts ? opts->uplo : 0;
+  if (opts) q->opts = *opts;
+  q->opts.graph = 0;
+  q->opts.autotune = 0;
   q->max_group = max_group > 0 ? max_group : 64;
   (void)hipGetDevice(&q->device);
   const int ns = nstreams > 0 ? nstreams : 3;
-  for (int i = 0; i < ns; ++i) {
+  HipErr he;
+  for (int i = 0; i < ns && he.e == hipSuccess; ++i) {
     hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : q->streams) (void)hipStreamDestroy(x);
-      delete q;
-      return EXPM_PFD_ERR_HIP;
-    }
+    hipEvent_t ev = nullptr;
+    he(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    he(hipEventCreateWithFlags(&ev, hipEventDisableTiming | hipEventBlockingSync));
     q->streams.push_back(st);
-    q->busy.push_back(false);
+    q->stream_ev.push_back(ev);
+    q->flight.emplace_back();
+  }
+  he(hipStreamCreateWithFlags(&q->aux, hipStreamNonBlocking));
+  he(hipMalloc((void**)&q->dev_status, (size_t)ns * q->max_group * sizeof(int)));
+  he(hipHostMalloc((void**)&q->host_status, (size_t)ns * q->max_group * sizeof(int), hipHostMallocDefault));
+  if (he.e != hipSuccess) {
+    (void)hipGetLastError();
+    for (hipStream_t x : q->streams)
+      if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : q->stream_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (q->aux) (void)hipStreamDestroy(q->aux);
+    if (q->dev_status) (void)hipFree(q->dev_status);
+    if (q->host_status) (void)hipHostFree(q->host_status);
+    delete q;
+    return he.e == hipErrorOutOfMemory ? EXPM_PFD_ERR_OOM : EXPM_PFD_ERR_HIP;
   }
   // freed plan workspace stays in the device's stream-ordered pool, so plans of
   // new shapes are carved from it without new device allocations
   keep_pool_memory(q->device);
   q->worker = std::thread([q] { q->loop(); });
+  for (int i = 0; i < ns; ++i) q->waiters.emplace_back([q, i] { q->wait_loop(i); });
   *out = q;
   return 0;
 }
 
-extern "C" int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, int64_t* mat_id) {
+extern "C" int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64_t n, int64_t lda, void* stream,
+                                        int64_t* mat_id) {
   if (!q || !A || !mat_id) return EXPM_PFD_ERR_NULL;
   if (n < 1 || n > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
   if (lda < n) return EXPM_PFD_ERR_LD;
   const size_t bytes = (size_t)n * n * sizeof(double2);
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(q->mu);
+  q->release_cached(bytes);
+  if (q->mat_bytes + q->flight_bytes + bytes > q->budget) return EXPM_PFD_ERR_BUDGET;
   double2* d = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(q->mu);
-    if (q->mat_bytes + bytes > q->budget) return EXPM_PFD_ERR_BUDGET;
-    q->release_cached(bytes);
-    q->mat_bytes += bytes;
-  }
-  if (hipMalloc(&d, bytes) != hipSuccess ||
-      hipMemcpy2D(d, n * sizeof(double2), A, lda * sizeof(double2), n * sizeof(double2), n, hipMemcpyDeviceToDevice) !=
-          hipSuccess) {
+  hipEvent_t ev = q->take_event();
+  // stream-ordered: the copy follows the caller's work that wrote A; requests
+  // wait for `ev` before they read the copy
+  if (!ev || hipMallocAsync((void**)&d, bytes, st) != hipSuccess) {
     (void)hipGetLastError();
-    if (d) (void)hipFree(d);
-    std::lock_guard<std::mutex> lk(q->mu);
-    q->mat_bytes -= bytes;
+    q->give_event(ev);
+    return EXPM_PFD_ERR_OOM;
+  }
+  if (hipMemcpy2DAsync(d, n * sizeof(double2), A, lda * sizeof(double2), n * sizeof(double2), n,
+                       hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipEventRecord(ev, st) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFreeAsync(d, st);
+    q->give_event(ev);
     return EXPM_PFD_ERR_HIP;
   }
-  std::lock_guard<std::mutex> lk(q->mu);
   expm_pfd_queue_s::Mat m;
   m.A = d;
   m.n = n;
-  q->mats.push_back(m);
-  q->peak = std::max(q->peak, q->mat_bytes + q->flight_bytes + q->cached_bytes);
-  *mat_id = (int64_t)q->mats.size() - 1;
+  m.bytes = bytes;
+  m.ready = ev;
+  const int64_t id = q->next_mat++;
+  q->mats.emplace(id, m);
+  q->mat_bytes += bytes;
+  q->note_peak();
+  *mat_id = id;
   return 0;
 }
 
-extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, const void* V, int64_t m, int64_t ldv,
-                               void* X, int64_t ldx, uint64_t* ticket) {
+extern "C" int expm_pfd_unregister_matrix(expm_pfd_queue_t q, int64_t mat_id) {
+  if (!q) return EXPM_PFD_ERR_NULL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->mats.find(mat_id);
+  if (it == q->mats.end() || it->second.released) return EXPM_PFD_ERR_TICKET;
+  it->second.released = true;
+  if (it->second.refs == 0) q->free_matrix(it);
+  q->cv.notify_all();
+  return 0;
+}
+
+extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, const void* A, int64_t n, int64_t lda, double t,
+                               const void* V, int64_t m, int64_t ldv, void* X, int64_t ldx, void* stream,
+                               uint64_t* ticket) {
   if (!q || !V || !X || !ticket) return EXPM_PFD_ERR_NULL;
   if (!std::isfinite(t)) return EXPM_PFD_ERR_ARG;
+  ProblemDesc probe;
+  if (problem_shift(q->opts.shift, q->opts.shift_scale_t, t, probe)) return EXPM_PFD_ERR_ARG;
   std::lock_guard<std::mutex> lk(q->mu);
-  if (mat_id < 0 || mat_id >= (int64_t)q->mats.size()) return EXPM_PFD_ERR_TICKET;
-  const int64_t n = q->mats[mat_id].n;
-  if (m < 1 || m > 16) return EXPM_PFD_ERR_DIM;
-  if (ldv < n || ldx < n) return EXPM_PFD_ERR_LD;
-  if (q->mat_bytes + q->plan_bytes(round_up(n, NB), 1) > q->budget) return EXPM_PFD_ERR_BUDGET;
   expm_pfd_queue_s::Req r;
+  if (A == nullptr) {
+    auto it = q->mats.find(mat_id);
+    if (it == q->mats.end() || it->second.released) return EXPM_PFD_ERR_TICKET;
+    r.mat = mat_id;
+    r.A = it->second.A;
+    r.n = it->second.n;
+    r.lda = it->second.n;
+    r.mat_ready = it->second.ready;
+  } else {
+    if (n < 1 || n > EXPM_PFD_MAX_N) return EXPM_PFD_ERR_DIM;
+    if (lda < n) return EXPM_PFD_ERR_LD;
+    r.A = (const double2*)A;
+    r.n = n;
+    r.lda = lda;
+  }
+  if (m < 1 || m > 16) return EXPM_PFD_ERR_DIM;
+  if (ldv < r.n || ldx < r.n) return EXPM_PFD_ERR_LD;
+  if (q->mat_bytes + q->plan_bytes(round_up(r.n, NB), 1, q->opts.precision) > q->budget) return EXPM_PFD_ERR_BUDGET;
+  r.ready = q->take_event();
+  if (!r.ready || hipEventRecord(r.ready, (hipStream_t)stream) != hipSuccess) {
+    (void)hipGetLastError();
+    q->give_event(r.ready);
+    return EXPM_PFD_ERR_HIP;
+  }
+  if (r.mat >= 0) ++q->mats[r.mat].refs;
   r.ticket = q->next_ticket++;
-  r.mat = mat_id;
   r.t = t;
   r.V = V;
   r.m = m;
@@ -1873,38 +2179,49 @@ extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, double t, con
     q->any_submit = true;
   }
   q->pending.push_back(r);
-  q->state[r.ticket] = 1;
+  q->tickets[r.ticket] = expm_pfd_queue_s::Ticket{};
   ++q->submitted;
   *ticket = r.ticket;
   q->cv.notify_all();
   return 0;
 }
 
-static int state_error(int st) { return st == 3 ? EXPM_PFD_ERR_BUDGET : st == 4 ? EXPM_PFD_ERR_SYNC : 0; }
-
-extern "C" int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done) {
-  if (!q || !done) return EXPM_PFD_ERR_NULL;
-  std::lock_guard<std::mutex> lk(q->mu);
-  auto it = q->state.find(ticket);
-  if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
-  *done = it->second == 2 ? 1 : 0;
-  return state_error(it->second);
+static int state_error(int st) {
+  return st == expm_pfd_queue_s::FAIL_BUDGET ? EXPM_PFD_ERR_BUDGET
+         : st == expm_pfd_queue_s::FAIL_SYNC ? EXPM_PFD_ERR_SYNC
+                                              : 0;
 }
 
-extern "C" int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket) {
+extern "C" int expm_pfd_poll(expm_pfd_queue_t q, uint64_t ticket, int* done, int* info) {
+  if (!q || !done) return EXPM_PFD_ERR_NULL;
+  std::lock_guard<std::mutex> lk(q->mu);
+  auto it = q->tickets.find(ticket);
+  if (it == q->tickets.end()) return EXPM_PFD_ERR_TICKET;
+  *done = it->second.state == expm_pfd_queue_s::DONE ? 1 : 0;
+  if (info) *info = it->second.info;
+  return state_error(it->second.state);
+}
+
+extern "C" int expm_pfd_wait(expm_pfd_queue_t q, uint64_t ticket, int* info) {
   if (!q) return EXPM_PFD_ERR_NULL;
   std::unique_lock<std::mutex> lk(q->mu);
-  auto it = q->state.find(ticket);
-  if (it == q->state.end()) return EXPM_PFD_ERR_TICKET;
-  q->cv_done.wait(lk, [&] { return q->state[ticket] >= 2; });
-  return state_error(q->state[ticket]);
+  if (q->tickets.find(ticket) == q->tickets.end()) return EXPM_PFD_ERR_TICKET;
+  // (a lookup each time: submissions may rehash the table while this waits)
+  q->cv_done.wait(lk, [&] { return q->tickets[ticket].state != expm_pfd_queue_s::PENDING; });
+  const expm_pfd_queue_s::Ticket tk = q->tickets[ticket];
+  if (info) *info = tk.info;
+  return state_error(tk.state);
 }
 
 extern "C" int expm_pfd_queue_drain(expm_pfd_queue_t q) {
   if (!q) return EXPM_PFD_ERR_NULL;
   std::unique_lock<std::mutex> lk(q->mu);
-  q->cv_done.wait(lk, [&] { return q->completed == q->submitted; });
-  return 0;
+  q->cv_done.wait(lk, [&] { return q->completed + q->failed == q->submitted; });
+  if (q->failed == 0) return 0;
+  // the first failure kind found among the tickets
+  for (auto& kv : q->tickets)
+    if (int e = state_error(kv.second.state)) return e;
+  return EXPM_PFD_ERR_HIP;
 }
 
 extern "C" int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats* out) {
@@ -1913,9 +2230,14 @@ extern "C" int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats
   expm_pfd_queue_stats s{};
   s.submitted = q->submitted;
   s.completed = q->completed;
+  s.failed = q->failed;
+  s.fallbacks = q->fallbacks;
   s.groups = q->groups;
   s.mean_group_size = q->groups ? (double)q->grouped / q->groups : 0.0;
+  s.padded_up = q->padded_up;
   s.peak_bytes = q->peak;
+  s.registered = (int64_t)q->mats.size();
+  s.registered_bytes = q->mat_bytes;
   std::vector<double> v = q->lat_ms;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
@@ -1940,14 +2262,26 @@ extern "C" int expm_pfd_queue_destroy(expm_pfd_queue_t q) {
     q->stop = true;
     q->cv.notify_all();
   }
-  q->worker.join();
+  q->worker.join();  // returns once every request has completed or failed
+  {
+    std::lock_guard<std::mutex> lk(q->mu);
+    q->stop_waiters = true;
+    q->cv_flight.notify_all();
+  }
+  for (auto& w : q->waiters) w.join();
   (void)hipDeviceSynchronize();
   for (auto& kv : q->free_plans)
     for (expm_pfd_plan_t p : kv.second) free_plan(p);
-  for (auto& m : q->mats)
-    if (m.A) (void)hipFree(m.A);
+  for (auto& kv : q->mats) (void)hipFreeAsync(kv.second.A, q->aux);
+  (void)hipStreamSynchronize(q->aux);
+  for (auto& kv : q->mats) q->give_event(kv.second.ready);
   for (hipStream_t s : q->streams) (void)hipStreamSynchronize(s);
   for (hipStream_t s : q->streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : q->stream_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : q->event_pool) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(q->aux);
+  (void)hipFree(q->dev_status);
+  (void)hipHostFree(q->host_status);
   // the plans' workspace went back to the stream-ordered pool: hand it back to
   // the device
   hipMemPool_t mpool = nullptr;

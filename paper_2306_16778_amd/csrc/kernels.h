@@ -38,21 +38,23 @@ __global__ void k_put_consts(double2* __restrict__ theta, double2* __restrict__ 
   }
 }
 
-// Zero fill of count ints (a kernel, not a memset node, so that a caller's
-// stream capture records only kernels).  grid-stride.
-__global__ __launch_bounds__(256) void k_fill_zero(int* __restrict__ p, int64_t count) {
+// Fill of count ints with `value` (a kernel, not a memset node, so that a
+// caller's stream capture records only kernels).  grid-stride.
+__global__ __launch_bounds__(256) void k_fill(int* __restrict__ p, int64_t count, int value) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = 0;
+    p[e] = value;
 }
 
 // ---------------------------------------------------------------------------
 // Per-problem status: *d.info = 2 if the result X (n x m, column-major) holds a
 // non-finite value (non-finite input; a zero pivot cannot occur for finite
-// Hermitian A, since |lambda + theta_k| >= |Im theta_k| > 0), else 0.  Problems
-// without a status word are skipped.
+// Hermitian A, since |lambda + theta_k| >= |Im theta_k| > 0), else 1 if the
+// refinement of one of its solves missed its tolerance (ir_nc[g] set), else 0.
+// Problems without a status word are skipped.
 // grid (G), block 256
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_status(const ProblemDesc* __restrict__ descs, ProblemDesc one) {
+__global__ __launch_bounds__(256) void k_status(const ProblemDesc* __restrict__ descs, ProblemDesc one,
+                                                const int* __restrict__ ir_nc) {
   const ProblemDesc d = desc_of(descs, one, blockIdx.x);
   if (d.info == nullptr) return;
   int bad = 0;
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(256) void k_status(const ProblemDesc* __restrict__ 
     bad |= !(isfinite(v.x) && isfinite(v.y));
   }
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) *d.info = bad ? 2 : 0;
+  if (threadIdx.x == 0) *d.info = bad ? 2 : (ir_nc && ir_nc[blockIdx.x]) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ de
       double2 w = v;
       if (r == c) {
         if (r < n) {
-          w.x += theta[p].x;
+          w.x += theta[p].x - d.c;
           w.y += theta[p].y;
         } else {
           w.x = 1;
@@ -578,10 +580,10 @@ constexpr int gemm_waves() {
 // keeps the operand fetch free of branches; separate instantiations so kernel
 // traces and counters tell them apart.  The launcher uses them only for shapes
 // that satisfy this.
-template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
-                                              const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
-                                              int64_t ldc, KSplit ksp) {
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG>
+__device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
+                                           const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC,
+                                           int64_t ldc, KSplit ksp) {
   using T = cx<R>;
   using MF = Mfma<R>;
   using V = typename MF::V;
@@ -736,6 +738,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<
         }
         if (FULL || (row < M && col < N)) C[(int64_t)row * ldc + col] = c;
       }
+}
+
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm(
+    int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split, const cx<R>* B, int64_t sB, int64_t ldb,
+    cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp) {
+  gemm_block<R, MODE, BM, BN, WGM, WGN, TAG>(M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
+}
+
+// The same product, doing nothing when *gate == 0: the refinement sweeps after
+// every solve of the launch has converged.
+template <typename R, int MODE, int BM, int BN, int WGM, int WGN, int TAG = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves<R, BM, BN>()))) void k_gemm_gated(
+    const int* __restrict__ gate, int M, int N, int K, GemmOperand<R> a0, GemmOperand<R> a1, int split,
+    const cx<R>* B, int64_t sB, int64_t ldb, cx<R>* C, int64_t sC, int64_t ldc, KSplit ksp) {
+  if (*gate == 0) return;
+  gemm_block<R, MODE, BM, BN, WGM, WGN, TAG>(M, N, K, a0, a1, split, B, sB, ldb, C, sC, ldc, ksp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,22 +1100,29 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nchain, int cpb, SweepOperand<R> d0,
                                                      SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
                                                      int split, cx<R>* X, int64_t sX, int64_t ldx,
-                                                     int* ctl) {
+                                                     int* ctl, const int* __restrict__ gate) {
   __shared__ unsigned s_ticket;
-  __shared__ int s_epoch;
+  __shared__ int s_epoch, s_run;
   const int tid = threadIdx.x;
   int* status = ctl + SW_STATUS;
   int* flags = ctl + FLAG_STRIDE;
   const unsigned total = (unsigned)(nchain * nsteps);  // == gridDim.x
   if (tid == 0) {
-    s_ticket = atomicAdd((unsigned*)ctl + SW_TICKET, 1u);
+    // the gate is read beside the ticket and the epoch (all three in flight
+    // together); a skipped sweep still takes its tickets and re-arms the line
+    const unsigned tk = atomicAdd((unsigned*)ctl + SW_TICKET, 1u);
     const int e = __hip_atomic_load(ctl + SW_EPOCH, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int gv = gate != nullptr ? __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
+    s_ticket = tk;
     s_epoch = e == INT32_MAX ? 1 : e + 1;
+    s_run = gv != 0;
   }
   __syncthreads();
   const unsigned ticket = (unsigned)__builtin_amdgcn_readfirstlane((int)s_ticket);
   const int epoch = __builtin_amdgcn_readfirstlane(s_epoch);
-  if (ticket < total)
+  if (!__builtin_amdgcn_readfirstlane(s_run)) {
+    // nothing to solve
+  } else if (ticket < total)
     sweep_tile<R, true>((int)(ticket / (unsigned)nchain), (int)(ticket % (unsigned)nchain), fwd, nsteps, cpb, d0, d1,
                         a0, a1, split, X, sX, ldx, flags, epoch, status);
   else if (tid == 0)
@@ -1121,17 +1147,20 @@ __global__ __launch_bounds__(256) void k_sweep_chain(int fwd, int nsteps, int nc
 template <typename R>
 __global__ __launch_bounds__(256) void k_sweep_whole(int fwd, int nsteps, int cpb, SweepOperand<R> d0,
                                                      SweepOperand<R> d1, SweepOperand<R> a0, SweepOperand<R> a1,
-                                                     int split, cx<R>* X, int64_t sX, int64_t ldx) {
+                                                     int split, cx<R>* X, int64_t sX, int64_t ldx,
+                                                     const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int c = blockIdx.x;
   for (int q = 0; q < nsteps; ++q)
     sweep_tile<R, false>(q, c, fwd, nsteps, cpb, d0, d1, a0, a1, split, X, sX, ldx, nullptr, 0, nullptr);
 }
 
 // After a whole pass: if any one-launch sweep of the plan lost its dependency
-// order (the sticky status word of its control line), the problem's status word
-// becomes `code` instead of the finiteness status.  grid 1, block 1
-__global__ void k_sweep_status(const int* __restrict__ ctl, int* __restrict__ info, int code) {
-  if (ctl[SW_STATUS] != 0) *info = code;
+// order (the sticky status word of its control line), the status words
+// info[0..count) of the plan's problems become `code`.  grid 1, block 64
+__global__ void k_sweep_status(const int* __restrict__ ctl, int* __restrict__ info, int count, int code) {
+  if (ctl[SW_STATUS] == 0) return;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) info[i] = code;
 }
 
 // ---------------------------------------------------------------------------
@@ -1144,9 +1173,10 @@ __global__ void k_sweep_status(const int* __restrict__ ctl, int* __restrict__ in
 template <typename R, int CW>
 __global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols, int gap_at,
                                                int gap_len, const int* __restrict__ moves, int64_t smv, int s_begin,
-                                               int s_end, int inverse) {
+                                               int s_end, int inverse, const int* __restrict__ gate) {
   using T = cx<R>;
   __shared__ T Mv[MOVE_CAP][CW];
+  if (gate != nullptr && *gate == 0) return;
   __shared__ int from_s[MOVE_CAP], to_s[MOVE_CAP];
   __shared__ int cnt_s;
   const int bb = blockIdx.y;
@@ -1189,7 +1219,9 @@ __global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t s
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(256) void k_stage(cx<R>* __restrict__ X, int64_t ldS, int npad, int mp, int GP, int P,
-                                               const ProblemDesc* __restrict__ descs, ProblemDesc one) {
+                                               const ProblemDesc* __restrict__ descs, ProblemDesc one,
+                                               const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int64_t total = (int64_t)npad * ldS;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / ldS);
@@ -1229,7 +1261,9 @@ __global__ __launch_bounds__(256) void k_accum_thin(const double2* __restrict__ 
   const double2* row = Xs + (int64_t)i * ldS;
   double sr = 0, si = 0;
   for (int p = 0; p < P; ++p) {
-    const double2 ap = a[p];
+    double2 ap = a[p];
+    ap.x *= d.ec;
+    ap.y *= d.ec;
     const double2 y = row[(g * P + p) * mp + j];
     // real data: the conjugate pole's solution is the conjugate of the primal one
     const double2 z = adjoint_blocks ? row[(GP + g * P + p) * mp + j] : cconj(y);
@@ -1270,7 +1304,9 @@ __global__ __launch_bounds__(256) void k_accum_full(const double2* __restrict__ 
       t2[rr][tx] = Y[(int64_t)(bj + rr) * ldS + bi + tx];  // (j, i) block
     }
     __syncthreads();
-    const double2 ap = a[p];
+    double2 ap = a[p];
+    ap.x *= d.ec;
+    ap.y *= d.ec;
     for (int q = 0; q < 4; ++q) {
       const int jj = ty + 8 * q;
       // w1 = a Y[i][j], w2 = a Y[j][i] with identical rounding, so entry (j, i)
@@ -1309,29 +1345,93 @@ __global__ __launch_bounds__(256) void k_convert(const cx<RI>* __restrict__ in, 
   }
 }
 
-// X64 += D32
-__global__ __launch_bounds__(256) void k_add_correction(double2* __restrict__ X, const float2* __restrict__ D,
-                                                        int64_t count) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
-    X[e].x += (double)D[e].x;
-    X[e].y += (double)D[e].y;
+// Largest of the non-negative doubles x and y held by the workgroup's threads, as
+// ordered bit patterns (NaN compares above every number), stored to dst[0] and
+// dst[1].  Every thread of the (256-thread) workgroup calls it.
+__device__ __forceinline__ void block_max2_bits(double x, double y, unsigned long long* dst) {
+  __shared__ unsigned long long part[2][4];
+  unsigned long long a = (unsigned long long)__double_as_longlong(x);
+  unsigned long long b = (unsigned long long)__double_as_longlong(y);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long u = __shfl_xor(a, o), v = __shfl_xor(b, o);
+    a = u > a ? u : a;
+    b = v > b ? v : b;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = a;
+    part[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long m = part[threadIdx.x][0];
+    for (int w = 1; w < 4; ++w) m = part[threadIdx.x][w] > m ? part[threadIdx.x][w] : m;
+    dst[threadIdx.x] = m;
   }
 }
 
-// Refinement right-hand side in FP32:
+// X64 += D32 on solution block b = blockIdx.y (mp columns of the row-major
+// npad x ldS arrays).  With `maxima`, also the workgroup's largest correction and
+// largest updated entry (max of |Re| and |Im|) into maxima[2w], maxima[2w + 1],
+// w = b * gridDim.x + blockIdx.x, for the convergence test.
+// grid (any, nblk), block 256: each block's npad*mp elements grid-strided
+__global__ __launch_bounds__(256) void k_add_correction(double2* __restrict__ X, const float2* __restrict__ D,
+                                                        int64_t ldS, int npad, int mp,
+                                                        unsigned long long* __restrict__ maxima,
+                                                        const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int blk = blockIdx.y;
+  double dm = 0.0, xm = 0.0;
+  const int64_t count = (int64_t)npad * mp;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = (q / mp) * ldS + (int64_t)blk * mp + q % mp;
+    const float2 d = D[e];
+    double2 x = X[e];
+    x.x += (double)d.x;
+    x.y += (double)d.y;
+    X[e] = x;
+    // (fmax would drop a NaN: the comparison form keeps it)
+    const double a = fabs((double)d.x), b = fabs((double)d.y);
+    const double m1 = !(a <= b) ? a : b;
+    dm = !(m1 <= dm) ? m1 : dm;
+    xm = fmax(xm, fmax(fabs(x.x), fabs(x.y)));
+  }
+  if (maxima != nullptr)
+    block_max2_bits(dm, xm, maxima + 2 * ((int64_t)blk * gridDim.x + blockIdx.x));
+}
+
+// Start of the refinement sweeps: gate open, the check's finish counter cleared,
+// every problem's flag set to `nc0`.  grid 1, block 256
+__global__ __launch_bounds__(256) void k_ir_begin(int* __restrict__ gate, int* __restrict__ ir_nc, int G, int nc0,
+                                                  unsigned* __restrict__ done) {
+  for (int g = threadIdx.x; g < G; g += blockDim.x) ir_nc[g] = nc0;
+  if (threadIdx.x == 0) {
+    *gate = 1;
+    *done = 0u;
+  }
+}
+
+// Refinement right-hand side in FP32 on solution block b = blockIdx.y:
 //   out = Rres - sum_{s < nparts} part[s*pstride + e] - shift_b * X
 // Rres holds the staged V (minus the product, when nparts = 0); part the split-K
 // partial products of (t A) X, summed in slice order.  Block b's shift: primal
-// blocks (b < GP) theta of pair b mod P, adjoint blocks its conjugate.
+// blocks (b < GP) theta - c of pair b mod P (c the problem's shift), adjoint
+// blocks its conjugate.
+// grid (any, nblk), block 256: each block's npad*mp elements grid-strided
 __global__ __launch_bounds__(256) void k_residual32(const double2* __restrict__ Rres, const double2* __restrict__ part,
                                                     int nparts, int64_t pstride, const double2* __restrict__ X,
                                                     int64_t ldS, int npad, int mp, int GP, int P,
-                                                    const double2* __restrict__ theta, float2* __restrict__ out) {
-  const int64_t total = (int64_t)npad * ldS;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int blk = (int)((e % ldS) / mp);
-    double2 th = theta[(blk % GP) % P];
-    if (blk >= GP) th.y = -th.y;
+                                                    const double2* __restrict__ theta,
+                                                    const ProblemDesc* __restrict__ descs, ProblemDesc one,
+                                                    float2* __restrict__ out, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int blk = blockIdx.y;
+  double2 th = theta[(blk % GP) % P];
+  th.x -= desc_of(descs, one, (blk % GP) / P).c;
+  if (blk >= GP) th.y = -th.y;
+  const int64_t count = (int64_t)npad * mp;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = (q / mp) * ldS + (int64_t)blk * mp + q % mp;
     double2 sum = {0.0, 0.0};
     for (int s = 0; s < nparts; ++s) {
       const double2 p = part[s * pstride + e];
@@ -1348,6 +1448,59 @@ __global__ __launch_bounds__(256) void k_residual32(const double2* __restrict__ 
     o.x = (float)r.x;
     o.y = (float)r.y;
     out[e] = o;
+  }
+}
+
+// After a refinement sweep (the per-workgroup maxima of k_add_correction, wpb
+// workgroups per block): block b has converged when its largest correction is
+// at most tol times its largest solution entry (a NaN never converges).  One
+// workgroup per block writes conv[b]; the last one to finish (counted in *done)
+// sets ir_nc[g] = 1 for each problem g with a block that has not converged (0
+// otherwise) and *gate = 1 while any block has not (the next sweep runs), 0
+// once all have (its kernels return at once), and clears *done.
+// Blocks: primal b = g*P + p (b < GP), adjoint GP + g*P + p when present.
+// grid (nblk), block 64
+__global__ __launch_bounds__(64) void k_ir_check(const unsigned long long* __restrict__ maxima, int nblk, int wpb,
+                                                 int GP, int P, double tol, int* __restrict__ gate,
+                                                 int* __restrict__ ir_nc, int* __restrict__ conv,
+                                                 unsigned* __restrict__ done) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  unsigned long long dmb = 0ull, xmb = 0ull;
+  for (int w = lane; w < wpb; w += 64) {
+    const unsigned long long u = maxima[2 * ((int64_t)b * wpb + w)];
+    const unsigned long long v = maxima[2 * ((int64_t)b * wpb + w) + 1];
+    dmb = u > dmb ? u : dmb;
+    xmb = v > xmb ? v : xmb;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long u = __shfl_xor(dmb, o), v = __shfl_xor(xmb, o);
+    dmb = u > dmb ? u : dmb;
+    xmb = v > xmb ? v : xmb;
+  }
+  __shared__ bool last;
+  if (lane == 0) {
+    const double dm = __longlong_as_double((long long)dmb), xm = __longlong_as_double((long long)xmb);
+    conv[b] = dm <= tol * xm ? 1 : 0;
+    __threadfence();
+    last = atomicAdd(done, 1u) == (unsigned)nblk - 1u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int G = GP / P;
+  int any = 0;
+  for (int g = lane; g < G; g += 64) {
+    int nc = 0;
+    for (int b0 = g * P; b0 < nblk; b0 += GP)
+      for (int p = 0; p < P; ++p) nc |= __hip_atomic_load(conv + b0 + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    ir_nc[g] = nc;
+    any |= nc;
+  }
+  any = __any(any);
+  if (lane == 0) {
+    *gate = any ? 1 : 0;
+    *done = 0u;
   }
 }
 
@@ -1381,7 +1534,10 @@ __device__ __forceinline__ void dd_fma(DD& s, double a, double b) {
 __global__ __launch_bounds__(256) void k_residual_dd(const double2* __restrict__ Ah, int64_t nn,
                                                      const double2* __restrict__ X, const double2* __restrict__ Rv,
                                                      int64_t ldS, int npad, int mp, int GP, int P,
-                                                     const double2* __restrict__ theta, float2* __restrict__ out) {
+                                                     const double2* __restrict__ theta,
+                                                     const ProblemDesc* __restrict__ descs, ProblemDesc one,
+                                                     float2* __restrict__ out, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   constexpr int KC = 16;
   __shared__ double2 As[64][KC + 1];
   __shared__ double2 Xs[KC][16];
@@ -1417,6 +1573,7 @@ __global__ __launch_bounds__(256) void k_residual_dd(const double2* __restrict__
     __syncthreads();
   }
   double2 th = theta[(blk % GP) % P];
+  th.x -= desc_of(descs, one, g).c;
   if (blk >= GP) th.y = -th.y;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -1431,22 +1588,6 @@ __global__ __launch_bounds__(256) void k_residual_dd(const double2* __restrict__
     o.x = (float)((v.x - re[a].hi) - re[a].lo);
     o.y = (float)((v.y - im[a].hi) - im[a].lo);
     out[e] = o;
-  }
-}
-
-// Rres -= shift_b * X for block b: primal blocks (b < GP) theta of pair b mod P,
-// adjoint blocks its conjugate.
-__global__ __launch_bounds__(256) void k_shift_sub(double2* __restrict__ Rres, const double2* __restrict__ X,
-                                                   int64_t ldS, int npad, int mp, int GP, int P,
-                                                   const double2* __restrict__ theta) {
-  const int64_t total = (int64_t)npad * ldS;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int blk = (int)((e % ldS) / mp);
-    double2 th = theta[(blk % GP) % P];
-    if (blk >= GP) th.y = -th.y;
-    const double2 x = X[e];
-    Rres[e].x -= th.x * x.x - th.y * x.y;
-    Rres[e].y -= th.x * x.y + th.y * x.x;
   }
 }
 

@@ -48,6 +48,7 @@ EXPORTED = (
     "expm_pfd_trace_summary",
     "expm_pfd_queue_create",
     "expm_pfd_register_matrix",
+    "expm_pfd_unregister_matrix",
     "expm_pfd_submit",
     "expm_pfd_poll",
     "expm_pfd_wait",
@@ -68,16 +69,19 @@ class ExpmPfdError(RuntimeError):
 
 
 class _QueueStats(ctypes.Structure):
-    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("groups", ctypes.c_int64),
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64), ("groups", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
-                ("mean_group_size", ctypes.c_double), ("peak_bytes", ctypes.c_size_t)]
+                ("mean_group_size", ctypes.c_double), ("padded_up", ctypes.c_int64), ("peak_bytes", ctypes.c_size_t),
+                ("registered", ctypes.c_int64), ("registered_bytes", ctypes.c_size_t)]
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("ir_sweeps", ctypes.c_int), ("ir_extended", ctypes.c_int),
+    _fields_ = [("precision", ctypes.c_int), ("ir_max_iter", ctypes.c_int), ("ir_extended", ctypes.c_int),
                 ("real_data", ctypes.c_int), ("graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("lu_tile", ctypes.c_int), ("uplo", ctypes.c_int), ("shift", ctypes.c_double)]
+                ("lu_tile", ctypes.c_int), ("uplo", ctypes.c_int), ("shift", ctypes.c_double),
+                ("ir_tol", ctypes.c_double), ("shift_scale_t", ctypes.c_int)]
 
 # tile shapes of the LU trailing update, in the order of expm_pfd_opts.lu_tile - 1
 LU_TILES = ("64x64", "128x64", "64x128")
@@ -115,10 +119,12 @@ def load_library() -> ctypes.CDLL:
                                            ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
     lib.expm_pfd_queue_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, c_int, ctypes.POINTER(_Opts), c_int,
                                           c_int]
-    lib.expm_pfd_register_matrix.argtypes = [vp, vp, i64, i64, ctypes.POINTER(i64)]
-    lib.expm_pfd_submit.argtypes = [vp, i64, c_double, vp, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
-    lib.expm_pfd_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(c_int)]
-    lib.expm_pfd_wait.argtypes = [vp, ctypes.c_uint64]
+    lib.expm_pfd_register_matrix.argtypes = [vp, vp, i64, i64, vp, ctypes.POINTER(i64)]
+    lib.expm_pfd_unregister_matrix.argtypes = [vp, i64]
+    lib.expm_pfd_submit.argtypes = [vp, i64, vp, i64, i64, c_double, vp, i64, i64, vp, i64, vp,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    lib.expm_pfd_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    lib.expm_pfd_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(c_int)]
     lib.expm_pfd_queue_drain.argtypes = [vp]
     lib.expm_pfd_queue_stats_get.argtypes = [vp, ctypes.POINTER(_QueueStats)]
     lib.expm_pfd_queue_destroy.argtypes = [vp]
@@ -136,14 +142,16 @@ def _check(code: int, where: str):
         raise ExpmPfdError(code, where)
 
 
-def _opts(precision, ir_sweeps, ir_extended=0, shift=0.0, real_data=False, graph=False, autotune=False,
-          lu_tile=None, uplo="L") -> _Opts:
+def _opts(precision, ir_max_iter, ir_extended=0, shift=0.0, real_data=False, graph=False, autotune=False,
+          lu_tile=None, uplo="L", ir_tol=0.0, shift_scale_t=False) -> _Opts:
     p = {"fp64": EXPM_PFD_FP64, "mixed": EXPM_PFD_MIXED}.get(precision, precision)
     o = _Opts()
     o.precision = int(p)
-    o.ir_sweeps = int(ir_sweeps)
+    o.ir_max_iter = int(ir_max_iter)
     o.ir_extended = int(ir_extended)
     o.shift = float(shift)
+    o.ir_tol = float(ir_tol)
+    o.shift_scale_t = 1 if shift_scale_t else 0
     o.real_data = 1 if real_data else 0
     o.graph = 1 if graph else 0
     o.autotune = 1 if autotune else 0
@@ -165,10 +173,10 @@ def expm_pfd_constants(degree: int):
     return th.view(np.complex128).copy(), a.view(np.complex128).copy()
 
 
-def expm_pfd_workspace_bytes(n: int, degree: int, m_max: int = 0, precision="fp64", ir_sweeps: int = 0) -> int:
+def expm_pfd_workspace_bytes(n: int, degree: int, m_max: int = 0, precision="fp64", ir_max_iter: int = 0) -> int:
     lib = load_library()
     out = ctypes.c_size_t(0)
-    o = _opts(precision, ir_sweeps)
+    o = _opts(precision, ir_max_iter)
     _check(lib.expm_pfd_workspace_bytes(int(n), int(degree), int(m_max), ctypes.byref(o), ctypes.byref(out)),
            "expm_pfd_workspace_bytes")
     return int(out.value)
@@ -189,14 +197,16 @@ class Plan:
             pass
 
 
-def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_sweeps: int = 0,
+def expm_pfd_plan(n: int, degree: int, t: float, m_max: int = 0, precision="fp64", ir_max_iter: int = 0,
                   ir_extended: int = 0, shift: float = 0.0, real_data: bool = False, graph: bool = False,
-                  autotune: bool = False, lu_tile=None, uplo="L") -> Plan:
+                  autotune: bool = False, lu_tile=None, uplo="L", ir_tol: float = 0.0,
+                  shift_scale_t: bool = False) -> Plan:
     """lu_tile: None (built-in or autotuned), a name from LU_TILES, or the C option value (1..3).
     uplo: "L" (lower triangle of A read) or "U"."""
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo)
+    o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo, ir_tol,
+              shift_scale_t)
     _check(lib.expm_pfd_plan(ctypes.byref(h), int(n), int(degree), float(t), int(m_max), ctypes.byref(o)),
            "expm_pfd_plan")
     return Plan(h.value, n, degree, t, m_max, precision)
@@ -208,9 +218,14 @@ def expm_pfd_destroy(plan: Plan):
         plan.handle = None
 
 
-def expm_pfd_plan_check(plan: Plan):
-    """Raise ExpmPfdError if a triangular sweep of this plan lost its dependency order."""
-    _check(load_library().expm_pfd_plan_check(plan.handle), "expm_pfd_plan_check")
+def expm_pfd_plan_check(plan: Plan) -> int:
+    """Raise ExpmPfdError if a triangular sweep of this plan lost its dependency order;
+    otherwise 0, or 1 if the last apply's refinement missed its tolerance (mixed plans
+    with the convergence test)."""
+    rc = load_library().expm_pfd_plan_check(plan.handle)
+    if rc < 0:
+        _check(rc, "expm_pfd_plan_check")
+    return rc
 
 
 def _colmajor(x, torch):
@@ -259,8 +274,9 @@ NOALLOC_BYTES = 128 << 20
 
 
 def expm_pfd_apply_noalloc(n: int, degree: int, t: float, A, V=None, X=None, precision="fp64",
-                           ir_sweeps: int = 0, ir_extended: int = 0, shift: float = 0.0, real_data: bool = False,
-                           lu_tile=None, uplo="L", info=None, stream=None):
+                           ir_max_iter: int = 0, ir_extended: int = 0, shift: float = 0.0, real_data: bool = False,
+                           lu_tile=None, uplo="L", info=None, stream=None, ir_tol: float = 0.0,
+                           shift_scale_t: bool = False):
     """X = R_d(tA)V without any device allocation by the library (its fixed scratch
     array holds the workspace).  X, when given, must be a column-major (n, m)
     complex128 tensor; info an optional int32 device tensor of one element."""
@@ -281,7 +297,8 @@ def expm_pfd_apply_noalloc(n: int, degree: int, t: float, A, V=None, X=None, pre
         raise ValueError("X must be a column-major (n, m) complex128 tensor")
     if info is not None and (info.dtype != torch.int32 or not info.is_cuda or info.numel() != 1):
         raise ValueError("info must be a one-element int32 device tensor")
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, lu_tile=lu_tile, uplo=uplo)
+    o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, lu_tile=lu_tile, uplo=uplo, ir_tol=ir_tol,
+              shift_scale_t=shift_scale_t)
     _check(lib.expm_pfd_apply_noalloc(int(n), int(degree), float(t), Ac.data_ptr(), lda, Vp, ldv, m, X.data_ptr(),
                                       X.stride(1), ctypes.byref(o), None if info is None else info.data_ptr(),
                                       _stream_ptr(stream, torch)), "expm_pfd_apply_noalloc")
@@ -290,8 +307,9 @@ def expm_pfd_apply_noalloc(n: int, degree: int, t: float, A, V=None, X=None, pre
 
 
 def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degree: int, precision="fp64",
-                           ir_sweeps: int = 0, stream=None, info=None, uplo="L", shift: float = 0.0,
-                           real_data: bool = False, ir_extended: int = 0):
+                           ir_max_iter: int = 0, stream=None, info=None, uplo="L", shift: float = 0.0,
+                           real_data: bool = False, ir_extended: int = 0, ir_tol: float = 0.0,
+                           shift_scale_t: bool = False):
     """X_i = R_d(t_i A_i) V_i for every i (V_i None: V_i = I).  Returns the list of X_i.
 
     info: optional host int32 numpy array of len(As), filled with each problem's status."""
@@ -323,7 +341,8 @@ def expm_pfd_apply_batched(As: Sequence, Vs: Sequence, ts: Sequence[float], degr
         x = torch.empty((int(m[i]), int(n[i])), dtype=torch.complex128, device=a.device).t()
         Xs.append(x)
         ldx[i], px[i] = n[i], x.data_ptr()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, uplo=uplo)
+    o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, uplo=uplo, ir_tol=ir_tol,
+              shift_scale_t=shift_scale_t)
     if info is not None and (info.dtype != np.int32 or info.size != count or not info.flags.c_contiguous):
         raise ValueError("info must be a contiguous int32 array with one entry per problem")
     _check(lib.expm_pfd_apply_batched(count, n.ctypes.data, t.ctypes.data, int(degree), pa, lda.ctypes.data, pv,
@@ -349,9 +368,10 @@ class BatchPlan:
             pass
 
 
-def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precision="fp64", ir_sweeps: int = 0,
+def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precision="fp64", ir_max_iter: int = 0,
                         graph: bool = False, autotune: bool = False, lu_tile=None,
-                        real_data: bool = False, uplo="L", shift: float = 0.0, ir_extended: int = 0) -> BatchPlan:
+                        real_data: bool = False, uplo="L", shift: float = 0.0, ir_extended: int = 0,
+                        ir_tol: float = 0.0, shift_scale_t: bool = False) -> BatchPlan:
     """Batch plan for problems of orders n[i] with m[i] right-hand-side columns (0: V_i = I)."""
     lib = load_library()
     nn = np.ascontiguousarray(n, dtype=np.int64)
@@ -359,7 +379,8 @@ def expm_pfd_batch_plan(n: Sequence[int], m: Sequence[int], degree: int, precisi
     if nn.shape != mm.shape:
         raise ValueError("n and m must have the same length")
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo)
+    o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, graph, autotune, lu_tile, uplo, ir_tol,
+              shift_scale_t)
     _check(lib.expm_pfd_batch_plan(ctypes.byref(h), len(nn), nn.ctypes.data, mm.ctypes.data, int(degree),
                                    ctypes.byref(o)), "expm_pfd_batch_plan")
     return BatchPlan(h.value, nn, mm)
@@ -460,6 +481,7 @@ class Queue:
     def __init__(self, handle):
         self.handle = handle
         self._live = {}
+        self._sources = []  # registered matrices' sources until their copies are done
 
     def __del__(self):
         try:
@@ -469,55 +491,84 @@ class Queue:
             pass
 
 
-def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_sweeps: int = 0, max_group: int = 64,
+def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_max_iter: int = 0, max_group: int = 64,
                           streams: int = 3, shift: float = 0.0, real_data: bool = False,
-                          ir_extended: int = 0, uplo="L") -> Queue:
+                          ir_extended: int = 0, uplo="L", ir_tol: float = 0.0, shift_scale_t: bool = False) -> Queue:
     lib = load_library()
     h = ctypes.c_void_p()
-    o = _opts(precision, ir_sweeps, ir_extended, shift, real_data, uplo=uplo)
+    o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, uplo=uplo, ir_tol=ir_tol,
+              shift_scale_t=shift_scale_t)
     _check(lib.expm_pfd_queue_create(ctypes.byref(h), int(hbm_budget), int(degree), ctypes.byref(o), int(max_group),
                                      int(streams)), "expm_pfd_queue_create")
     return Queue(h.value)
 
 
-def expm_pfd_register_matrix(q: Queue, A) -> int:
+def expm_pfd_register_matrix(q: Queue, A, stream=None) -> int:
+    """Register A with the queue (copied on `stream`, default the current one, after the
+    work already enqueued there); returns the matrix id."""
     import torch
 
     Ac, lda = _colmajor(A, torch)
     mid = ctypes.c_int64()
-    torch.cuda.current_stream().synchronize()
-    _check(load_library().expm_pfd_register_matrix(q.handle, Ac.data_ptr(), Ac.shape[0], lda, ctypes.byref(mid)),
+    _check(load_library().expm_pfd_register_matrix(q.handle, Ac.data_ptr(), Ac.shape[0], lda,
+                                                   _stream_ptr(stream, torch), ctypes.byref(mid)),
            "expm_pfd_register_matrix")
+    # the copy is stream-ordered: keep the source alive until the stream has passed it
+    q._sources.append((Ac, torch.cuda.Event()))
+    q._sources[-1][1].record(stream if stream is not None else torch.cuda.current_stream())
+    q._sources = [(a, e) for a, e in q._sources if not e.query()]
     return int(mid.value)
 
 
-def expm_pfd_submit(q: Queue, mat_id: int, t: float, V, X=None):
-    """Enqueue X = R_d(t A_mat) V; returns (ticket, X).  V: (n, m) complex128 device tensor, m <= 16."""
+def expm_pfd_unregister_matrix(q: Queue, mat_id: int):
+    _check(load_library().expm_pfd_unregister_matrix(q.handle, int(mat_id)), "expm_pfd_unregister_matrix")
+
+
+def expm_pfd_submit(q: Queue, mat, t: float, V, X=None, stream=None):
+    """Enqueue X = R_d(t A) V; returns (ticket, X).
+
+    mat: a registered matrix id, or an (n, n) complex128 device tensor read in place (kept alive
+    here until the ticket completes).  V: (n, m) complex128 device tensor, m <= 16.  The request is
+    ordered after the work already enqueued on `stream` (default: the current stream)."""
     import torch
 
     Vc, ldv = _colmajor(V, torch)
     n, m = Vc.shape
     if X is None:
         X = torch.empty((m, n), dtype=torch.complex128, device=Vc.device).t()
-    torch.cuda.current_stream().synchronize()  # V must be written before the queue's streams read it
     tk = ctypes.c_uint64()
-    _check(load_library().expm_pfd_submit(q.handle, int(mat_id), float(t), Vc.data_ptr(), m, ldv, X.data_ptr(),
-                                          X.stride(1), ctypes.byref(tk)), "expm_pfd_submit")
-    q._live[tk.value] = (Vc, X)
+    if isinstance(mat, int):
+        Ac, ap, lda = None, None, n
+        mid = int(mat)
+    else:
+        Ac, lda = _colmajor(mat, torch)
+        if Ac.shape != (n, n):
+            raise ValueError("A must be n x n with n the rows of V")
+        ap, mid = Ac.data_ptr(), -1
+    _check(load_library().expm_pfd_submit(q.handle, mid, ap, n, lda, float(t), Vc.data_ptr(), m, ldv, X.data_ptr(),
+                                          X.stride(1), _stream_ptr(stream, torch), ctypes.byref(tk)),
+           "expm_pfd_submit")
+    q._live[tk.value] = (Vc, X, Ac)
     return tk.value, X
 
 
-def expm_pfd_poll(q: Queue, ticket: int) -> bool:
-    d = ctypes.c_int()
-    _check(load_library().expm_pfd_poll(q.handle, ctypes.c_uint64(ticket), ctypes.byref(d)), "expm_pfd_poll")
+def expm_pfd_poll(q: Queue, ticket: int):
+    """(done, info): done is True once the ticket's result is in X; info its status then
+    (0, 1: solved again on the FP64 path after the refinement missed its tolerance, 2: non-finite)."""
+    d, info = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().expm_pfd_poll(q.handle, ctypes.c_uint64(ticket), ctypes.byref(d), ctypes.byref(info)),
+           "expm_pfd_poll")
     if d.value:
         q._live.pop(ticket, None)
-    return bool(d.value)
+    return bool(d.value), int(info.value)
 
 
-def expm_pfd_wait(q: Queue, ticket: int):
-    _check(load_library().expm_pfd_wait(q.handle, ctypes.c_uint64(ticket)), "expm_pfd_wait")
+def expm_pfd_wait(q: Queue, ticket: int) -> int:
+    """Block until the ticket completes; returns its status (as expm_pfd_poll's info)."""
+    info = ctypes.c_int()
+    _check(load_library().expm_pfd_wait(q.handle, ctypes.c_uint64(ticket), ctypes.byref(info)), "expm_pfd_wait")
     q._live.pop(ticket, None)
+    return int(info.value)
 
 
 def expm_pfd_queue_drain(q: Queue):
@@ -536,3 +587,4 @@ def expm_pfd_queue_destroy(q: Queue):
         _check(load_library().expm_pfd_queue_destroy(q.handle), "expm_pfd_queue_destroy")
         q.handle = None
         q._live.clear()
+        q._sources = []

@@ -124,11 +124,17 @@ def laplacian_like_spectrum(n: int, scale: float = 4e3) -> np.ndarray:
     return -scale * (np.pi * k / (n + 1)) ** 2
 
 
-def config3_precision(n: int = 4096) -> Problem:
-    """Dense Hermitian A, n = 4096, 1D-Laplacian-like spectrum scaled by 4e3; V = I; degree 32."""
+def config3_precision(n: int = 4096, with_eigenvectors: bool = False):
+    """Dense Hermitian A, n = 4096, 1D-Laplacian-like spectrum scaled by 4e3; V = I; degree 32.
+
+    with_eigenvectors: also return the unitary U with A = U diag(lambda) U^H (before the
+    final symmetrisation), as (problem, U)."""
     rng = rng_for(3)
     lam = laplacian_like_spectrum(n)
-    return Problem(hermitian_with_spectrum(rng, lam), None, 1.0, 32, lam, f"lap_n{n}_d32_VI")
+    U = random_unitary(rng, n)
+    A = (U * lam[None, :]) @ U.conj().T
+    prob = Problem(0.5 * (A + A.conj().T), None, 1.0, 32, lam, f"lap_n{n}_d32_VI")
+    return (prob, U) if with_eigenvectors else prob
 
 
 def config4_batch(count: int = 512, n_lo: int = 32, n_hi: int = 512, m: int = 4):
@@ -191,6 +197,23 @@ def config5_matrix(spec) -> np.ndarray:
     return hermitian_with_spectrum(r, lam, cheap=True)
 
 
+def config5_eigenpairs(spec):
+    """(lambda, U) of the config-5 matrix of ``spec``: the spectrum and the unitary
+    U = D H_1 H_2 H_3 it is built from (same seeded draws as ``config5_matrix``),
+    so that results can be checked without an eigensolver at any order."""
+    n, idx = spec
+    r = rng_for(5, idx + 1)
+    lam = r.uniform(-200.0, 0.0, n)
+    vs = [complex_gaussian(r, n) for _ in range(3)]
+    phase = np.exp(2j * np.pi * r.random(n))
+    U = np.eye(n, dtype=np.complex128)
+    for v in reversed(vs):
+        v = v / np.linalg.norm(v)
+        U -= 2.0 * np.outer(v, v.conj() @ U)
+    U *= phase[:, None]
+    return lam, U
+
+
 def config5_matrix_device(spec, device="cuda"):
     """The config-5 matrix of ``spec`` assembled on the GPU with torch (same seeded
     draws as ``config5_matrix``: spectrum uniform in [-200, 0], three Householder
@@ -203,7 +226,7 @@ def config5_matrix_device(spec, device="cuda"):
     lam = r.uniform(-200.0, 0.0, n)
     vs = [complex_gaussian(r, n) for _ in range(3)]
     phase = np.exp(2j * np.pi * r.random(n))
-    X = torch.diag(torch.from_numpy(lam.astype(np.complex128))).to(device)
+    X = torch.diag(torch.from_numpy(lam.astype(np.complex128)).to(device))
     for v in reversed(vs):
         v = torch.from_numpy(v / np.linalg.norm(v)).to(device)
         X = X - 2.0 * torch.outer(v, v.conj() @ X)

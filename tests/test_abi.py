@@ -128,7 +128,31 @@ def test_batch_and_option_validation_without_device():
     assert lib.expm_pfd_batch_info(None, None, None, None) == -3
     # option names of the binding map onto the C struct
     assert mod._opts("mixed", 0, graph=True, autotune=True, lu_tile="64x128").lu_tile == 3
-    assert ctypes.sizeof(mod._Opts) == 4 * 8 + 8
+    assert ctypes.sizeof(mod._Opts) == 56
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a struct of include/expm_pfd.h, from the C compiler."""
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("{f} %zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text(f'#include <stddef.h>\n#include <stdio.h>\n#include "expm_pfd.h"\n'
+                   f'int main(void) {{\n  printf("sizeof %zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+@pytest.mark.parametrize("cname,pyname", [("expm_pfd_opts", "_Opts"), ("expm_pfd_queue_stats", "_QueueStats")])
+def test_binding_structs_match_the_c_layout(cname, pyname, tmp_path):
+    """The ctypes mirrors of the option and statistics structs have the C layout."""
+    mod, _ = _lib()
+    cls = getattr(mod, pyname)
+    names = [f for f, _ in cls._fields_]
+    lay = _c_layout(cname, names, tmp_path)
+    assert lay["sizeof"] == ctypes.sizeof(cls)
+    for f in names:
+        assert lay[f] == getattr(cls, f).offset, f
 
 
 def test_noalloc_rejects_before_device_work():

@@ -204,31 +204,33 @@ def _real_symmetric(rng, n, lo, hi):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
 def test_batched_shift_and_real_data(ep, precision, tol):
     """The shifting method (Remark rem:shift) and the real-data mode (Remark
-    rem:two_time_real_part) through the batched entry points.  Spectra in [0, 20],
-    t in [0.9, 1] and c = 20 against the oracle's e^c R_d(tA - cI)V, by the one-shot call and a
-    batch plan (same bits); real symmetric problems with real V in real-data mode
-    against R_d(tA)V, with the imaginary parts of the inputs ignored."""
+    rem:two_time_real_part) through the batched entry points.  Spectra of A in
+    [0, 20], t in [0.1, 1] and one c = 20 in units of A (option shift_scale_t: problem
+    i is shifted by t_i c, the top of its spectrum of t_i A) against the oracle's
+    e^{tc} R_d(tA - tcI)V, by the one-shot call and a batch plan (same bits); real
+    symmetric problems with real V in real-data mode against R_d(tA)V, with the
+    imaginary parts of the inputs ignored."""
     import torch
     rng = np.random.default_rng(31)
     probs = []
-    # one shift for the whole batch: t near 1 keeps c close to the top of every
-    # spectrum of tA (a shift far above it loses accuracy as e^{c - alpha})
-    for n, m in [(40, 3), (100, 4), (130, None), (64, 2)]:
+    for n, m in [(40, 3), (100, 4), (130, None), (64, 2), (90, 1)]:
         lam = rng.uniform(0.0, 20.0, n)
         A = wl.hermitian_with_spectrum(rng, lam)
         V = None if m is None else wl.complex_gaussian(rng, n, m)
-        probs.append((A, V, float(rng.uniform(0.9, 1.0))))
+        probs.append((A, V, float(rng.uniform(0.1, 1.0))))
     c = 20.0
     As = [_dev(A) for A, _, _ in probs]
     Vs = [None if V is None else _dev(V) for _, V, _ in probs]
     ts = [t for _, _, t in probs]
-    _announce(f"batched shift {precision} c={c}")
-    Xs = ep.expm_pfd_apply_batched(As, Vs, ts, 16, precision, shift=c)
+    assert min(ts) < 0.5  # spectra of t_i A far apart: one shift in tA units would not fit them all
+    _announce(f"batched shift {precision} c={c} (units of A)")
+    Xs = ep.expm_pfd_apply_batched(As, Vs, ts, 16, precision, shift=c, shift_scale_t=True)
     torch.cuda.synchronize()
     for (A, V, t), X in zip(probs, Xs):
-        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R_shifted(A, V, t, 16, c)) < tol
+        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R_shifted(A, V, t, 16, t * c)) < tol
     bp = ep.expm_pfd_batch_plan([A.shape[0] for A, _, _ in probs],
-                                [0 if V is None else V.shape[1] for _, V, _ in probs], 16, precision, shift=c)
+                                [0 if V is None else V.shape[1] for _, V, _ in probs], 16, precision, shift=c,
+                                shift_scale_t=True)
     Xp = ep.expm_pfd_batch_apply(bp, As, Vs, ts)
     torch.cuda.synchronize()
     ep.expm_pfd_batch_check(bp)
@@ -250,3 +252,77 @@ def test_batched_shift_and_real_data(ep, precision, tol):
     for (A, V, t), X, XJ in zip(real, Xr, Xj):
         assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16)) < tol
         assert torch.equal(X, XJ)
+
+
+def test_refinement_nonconvergence_falls_back_to_fp64(ep):
+    """Refinement convergence control (mixed path): with a tolerance no refinement
+    can meet (1e-300) the one-shot batched call reports status 1 for every
+    problem and returns the FP64 path's result (within the FP64 gate, 1e-12);
+    with no refinement sweep at all (ir_max_iter < 0) likewise.  The asynchronous
+    batch plan reports the same status without re-solving, and a single plan
+    reports it through expm_pfd_plan_check."""
+    import torch
+    rng = np.random.default_rng(41)
+    probs = []
+    for n, m in [(70, 2), (150, 5), (64, None)]:
+        A = wl.hermitian_with_spectrum(rng, rng.uniform(-60.0, 0.0, n))
+        V = None if m is None else wl.complex_gaussian(rng, n, m)
+        probs.append((A, V, float(rng.uniform(0.3, 1.0))))
+    As = [_dev(A) for A, _, _ in probs]
+    Vs = [None if V is None else _dev(V) for _, V, _ in probs]
+    ts = [t for _, _, t in probs]
+    for max_iter in (1, -1):
+        _announce(f"ir non-convergence ir_max_iter={max_iter} tol=1e-300")
+        info = np.full(len(probs), -5, dtype=np.int32)
+        Xs = ep.expm_pfd_apply_batched(As, Vs, ts, 16, "mixed", ir_max_iter=max_iter, ir_tol=1e-300, info=info)
+        torch.cuda.synchronize()
+        assert list(info) == [1] * len(probs)
+        X64 = ep.expm_pfd_apply_batched(As, Vs, ts, 16, "fp64")
+        torch.cuda.synchronize()
+        for (A, V, t), X, Y in zip(probs, Xs, X64):
+            assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16)) < 1e-12
+            assert torch.equal(X, Y)  # the FP64 path's bits
+    # the default tolerance is met: status 0, no re-solve
+    info = np.full(len(probs), -5, dtype=np.int32)
+    ep.expm_pfd_apply_batched(As, Vs, ts, 16, "mixed", info=info)
+    assert list(info) == [0] * len(probs)
+    _announce("ir non-convergence: batch plan status, plan check")
+    bp = ep.expm_pfd_batch_plan([A.shape[0] for A, _, _ in probs],
+                                [0 if V is None else V.shape[1] for _, V, _ in probs], 16, "mixed", ir_tol=1e-300)
+    dinfo = torch.full((len(probs),), -5, dtype=torch.int32, device="cuda")
+    ep.expm_pfd_batch_apply(bp, As, Vs, ts, info=dinfo)
+    torch.cuda.synchronize()
+    assert dinfo.tolist() == [1] * len(probs)
+    A, V, t = probs[1]
+    plan = ep.expm_pfd_plan(A.shape[0], 16, t, V.shape[1], "mixed", ir_tol=1e-300)
+    ep.expm_pfd_apply(plan, As[1], Vs[1])
+    assert ep.expm_pfd_plan_check(plan) == 1
+    plan = ep.expm_pfd_plan(A.shape[0], 16, t, V.shape[1], "mixed")
+    ep.expm_pfd_apply(plan, As[1], Vs[1])
+    assert ep.expm_pfd_plan_check(plan) == 0
+
+
+def test_refinement_stops_once_converged(ep):
+    """Sweeps after convergence are skipped on the device: with up to six sweeps and
+    the default tolerance, a problem whose solves converge at the second sweep gives
+    the same bits as with two sweeps, while a third sweep forced with the test off
+    changes them (so skipped sweeps are really not run)."""
+    import torch
+    rng = np.random.default_rng(43)
+    n, m, t = 300, 6, 0.8
+    A = wl.hermitian_with_spectrum(rng, rng.uniform(-80.0, 0.0, n))
+    V = wl.complex_gaussian(rng, n, m)
+    Ad, Vd = _dev(A), _dev(V)
+    out = {}
+    for key, kw in (("two", dict(ir_max_iter=2)), ("six", dict(ir_max_iter=6)),
+                    ("three_no_test", dict(ir_max_iter=3, ir_tol=-1.0))):
+        _announce(f"ir sweeps {key}")
+        plan = ep.expm_pfd_plan(n, 16, t, m, "mixed", **kw)
+        X = ep.expm_pfd_apply(plan, Ad, Vd)
+        assert ep.expm_pfd_plan_check(plan) == 0
+        out[key] = X.cpu().numpy()
+    assert np.array_equal(out["two"], out["six"])
+    assert not np.array_equal(out["two"], out["three_no_test"])
+    Y = matrix.expm_R(A, V, t, 16)
+    for X in out.values():
+        assert matrix.rel_fro(X, Y) < 1e-10

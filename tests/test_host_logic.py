@@ -122,3 +122,15 @@ def test_stage_rates():
     b["panel"] = {"launches": 4, "ms": 1.0, "flops": 1.0e9, "bytes": 1.0e8}
     assert bench.stage_rates(b, "mixed")["panel"] == {"tflops": 1.0, "gb_per_s": 100.0, "bound": "latency",
                                                       "frac": None}
+
+
+def test_serving_eigenpairs_rebuild_the_matrix():
+    """The eigenpairs the serving checks use are those the serving matrix is built
+    from: U unitary and U diag(lam) U^H equal to the host-assembled matrix."""
+    from paper_2306_16778_amd import workloads as wl
+
+    spec = (150, 4)
+    lam, U = wl.config5_eigenpairs(spec)
+    assert np.allclose(U.conj().T @ U, np.eye(150), atol=1e-13)
+    A = wl.config5_matrix(spec)
+    assert np.abs((U * lam) @ U.conj().T - A).max() < 1e-12 * np.abs(A).max()

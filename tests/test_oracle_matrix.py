@@ -173,3 +173,39 @@ def test_shifted_oracle_pins():
         assert rel2 <= max(scalar.err_shape(d, np.arange(-(d + 2), -d / 2, 0.01))) * (1 + 1e-6)
         R0 = matrix.expm_R(P, None, 1.0, d)
         assert np.linalg.norm(R0 - E, 2) / np.linalg.norm(E, 2) > 1e-3
+
+
+def test_pfd_amplification_pins():
+    """The residue-weighted amplification factor of the oracle (the factor by which
+    rounding of the shifted solves reaches the pole sum, Prop. prop:digit):
+    * degree 2, closed form: theta = -1 +- i, a = +-i, R_2(x) = 1/(1 - x + x^2/2),
+      so for one eigenvalue x the factor is (2/sqrt((x-1)^2 + 1)) / R_2(x)
+      = sqrt((1 - x)^2 + 1);
+    * it never goes below 1 (triangle inequality) and is unitarily invariant;
+    * a result small against V (a spectrum far below 0) makes it large."""
+    for x in (0.0, -0.5, -3.0, -12.0):
+        A = np.array([[x]], dtype=np.complex128)
+        got = matrix.pfd_amplification(A, np.ones((1, 1)), 1.0, 2)
+        assert abs(got - math.sqrt((1.0 - x) ** 2 + 1.0)) < 1e-14 * got
+    rng = np.random.default_rng(11)
+    lam = rng.uniform(-40.0, 0.0, 30)
+    D = np.diag(lam).astype(np.complex128)
+    V = wl.complex_gaussian(rng, 30, 2)
+    U = wl.random_unitary(rng, 30)
+    a0 = matrix.pfd_amplification(D, V, 0.7, 16)
+    a1 = matrix.pfd_amplification(U @ D @ U.conj().T, U @ V, 0.7, 16)
+    assert a0 >= 1.0 and abs(a0 - a1) < 1e-10 * a0
+    far = matrix.pfd_amplification(D - 100 * np.eye(30), V, 0.7, 16)
+    assert far > 100 * a0
+    # brute force at n = 4: exact inverses at 50 digits (no eigendecomposition)
+    import mpmath
+    B = wl.hermitian_with_spectrum(rng, rng.uniform(-15.0, 0.0, 4))
+    W = wl.complex_gaussian(rng, 4, 2)
+    th, a = scalar.pfd_full_mp(16)
+    with mpmath.workdps(50):
+        tB = matrix._mp_matrix(B) * mpmath.mpf(0.9)
+        Wm = matrix._mp_matrix(W)
+        num = sum(abs(ak) * mpmath.mnorm(matrix._solve_cols(tB + tk * mpmath.eye(4), Wm), "f")
+                  for tk, ak in zip(th, a))
+    ref = float(num) / np.linalg.norm(matrix.expm_R_pfd_mp(B, W, 0.9, 16))
+    assert abs(matrix.pfd_amplification(B, W, 0.9, 16) - ref) < 1e-12 * ref

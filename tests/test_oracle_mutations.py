@@ -73,3 +73,15 @@ def test_wrong_pair_member_is_caught(monkeypatch):
 
     monkeypatch.setattr(scalar, "pfd_pairs", pairs_bad)
     _fails(pins_s.test_degree2_closed_form)
+
+
+def test_amplification_without_residue_weights_is_caught(monkeypatch):
+    """The amplification factor with every |a_k| taken as 1 (residues dropped)."""
+    orig = scalar.pfd_all
+
+    def unit_residues(d):
+        t, r = orig(d)
+        return t, np.ones_like(r)
+
+    monkeypatch.setattr(scalar, "pfd_all", unit_residues)
+    _fails(pins_m.test_pfd_amplification_pins)
