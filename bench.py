@@ -395,6 +395,40 @@ def serving_section(requests, qps, check, sat_requests=1000, budget_gb=64):
     return out
 
 
+def tridiag_section(ep, torch, prob, Y, check, reps=10):
+    """The tridiagonal route on the benchmarked workload (n = 2048, V 2048 x 16,
+    degree 24): the reduction A = Q T Q^H once (first-t cost, reduction plus one
+    apply) and each further t (repeat-t cost), against the oracle at t = 1."""
+    import numpy as np
+
+    n, m = prob.V.shape
+    Ad = torch.from_numpy(np.asfortranarray(prob.A)).cuda()
+    Vd = torch.from_numpy(np.asfortranarray(prob.V)).cuda()
+    tri = ep.expm_pfd_tridiag_plan(n, prob.degree, m)
+    ep.expm_pfd_tridiag_factor(tri, Ad)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ep.expm_pfd_tridiag_factor(tri, Ad)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X = ep.expm_pfd_tridiag_apply(tri, prob.t, Vd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(reps):
+        ep.expm_pfd_tridiag_apply(tri, 0.1 + 0.9 * k / reps, Vd)
+    torch.cuda.synchronize()
+    rep_ms = (time.perf_counter() - t2) * 1e3 / reps
+    Xt = ep.expm_pfd_tridiag_apply(tri, prob.t, Vd)
+    torch.cuda.synchronize()
+    out = {"workload": "as the headline workload, one reduction A = Q T Q^H then several t",
+           "reduction_ms": (t1 - t0) * 1e3, "first_t_ms": (t2 - t0) * 1e3, "repeat_t_ms": rep_ms,
+           "repeat_t_solves_per_s": 1e3 / rep_ms,
+           "break_even_t_values_vs_lu_mixed": None}
+    if Y is not None:
+        out["rel_err_vs_oracle_t1"] = check.rel_fro(Xt.cpu().numpy(), Y)
+    return out
+
+
 def config3_section(ep, torch, check):
     """The precision workload: n = 4096, 1D-Laplacian-like spectrum scaled by 4e3,
     V = I (the full R_32(A)), degree 32, one apply per path; errors against the
@@ -482,6 +516,7 @@ def main():
     ap.add_argument("--serving-qps", type=float, default=None,
                     help="arrival rate of the serving replay (default: 0.8 x the FP64 path's measured saturation)")
     ap.add_argument("--no-config3", action="store_true")
+    ap.add_argument("--no-tridiag", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64", help="precision paths to time (mixed first: the reported value)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed, autotuned variant of the main paths")
@@ -525,11 +560,21 @@ def main():
 
     cpu = None
     errs = {}
+    Y = None
     if not args.no_cpu_baseline:
         from oracle import matrix
         Y, cpu = cpu_baseline(prob)
         errs = {p: matrix.rel_fro(r["X"], Y) for p, r in res.items()}
         print(f"[bench] oracle done: rel errs {errs}", file=sys.stderr, flush=True)
+
+    tri = None
+    if not args.no_tridiag:
+        from oracle import matrix as tcheck
+        tri = tridiag_section(ep, torch, prob, Y if not args.no_cpu_baseline else None, tcheck)
+        lu_ms = res["mixed"]["ms_per_step"]
+        if tri["repeat_t_ms"] < lu_ms:
+            tri["break_even_t_values_vs_lu_mixed"] = tri["reduction_ms"] / (lu_ms - tri["repeat_t_ms"])
+        print("[bench] tridiagonal route done", file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -592,6 +637,7 @@ def main():
         "real_symmetric": real,
         "batched": batched,
         "precision_n4096": config3,
+        "tridiagonal_route": tri,
         "serving": served,
     }
     print(json.dumps(out), flush=True)

@@ -325,6 +325,48 @@ int expm_pfd_batch_info(expm_pfd_batch_t b, int* groups, int* schedule, int* lu_
 /* Release a batch plan (synchronizes the device first). */
 int expm_pfd_batch_destroy(expm_pfd_batch_t b);
 
+/* ---- tridiagonal route: one reduction of A, many t ------------------------ */
+/*
+ * The partial fractions combined with a reduction of A to tridiagonal form
+ * (the paper's Sec. 1 names such reductions as a complement of the method):
+ * A = Q T Q^H once, T real symmetric tridiagonal and Q unitary, then for each t
+ *   R_d(tA) V = Q [ sum_k a_k (tT + theta_k I)^{-1} ] Q^H V      (eq. equ:expAx),
+ * with one tridiagonal solve (partial pivoting) per pole pair and column for
+ * Q^H V and one for its conjugate (T real: (tT + conj(theta) I)^{-1} b =
+ * conj((tT + theta I)^{-1} conj(b))), a residue-weighted FP64 sum and one
+ * product with Q.  The reduction costs O(n^3) once per matrix; every later t
+ * costs O(n^2 m) (two products with the explicit Q) plus O(n d m).  Everything
+ * runs in FP64 (opts.precision is accepted and does not change the route).
+ */
+typedef struct expm_pfd_tri_s* expm_pfd_tri_t;
+
+/* Plan for matrices of order n (1..EXPM_PFD_MAX_N), degree d, right-hand sides
+ * of at most m_max columns (1..min(64, n)).  opts: uplo, shift and shift_scale_t
+ * apply (see expm_pfd_opts); others are ignored.  Allocates about 2 n^2 x 16
+ * bytes (the matrix being reduced and Q) plus O(n d m_max) on the current device.
+ * Errors: EXPM_PFD_ERR_DEGREE, _DIM, _ARG, _NULL, _OOM, _HIP. */
+int expm_pfd_tridiag_plan(expm_pfd_tri_t* out, int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts);
+
+/* A = Q T Q^H for the n x n column-major device matrix A (lower triangle read, or
+ * the upper one with opts.uplo); A is not kept.  Asynchronous on `stream`; the
+ * plan's previous reduction is replaced.  Errors: _NULL, _LD, _HIP. */
+int expm_pfd_tridiag_factor(expm_pfd_tri_t tri, const void* A, int64_t lda, void* stream);
+
+/* X = R_d(tA) V with the reduction of the last expm_pfd_tridiag_factor (same
+ * stream or ordered after it).  V: device n x m column-major (ldv >= n),
+ * 1 <= m <= m_max; X: device n x m (ldx >= n).  Asynchronous on `stream`; calls
+ * on one plan must not overlap.  Errors: _NULL, _ARG (not factored, t not
+ * finite, e^shift overflows), _DIM, _LD, _HIP. */
+int expm_pfd_tridiag_apply(expm_pfd_tri_t tri, double t, const void* V, int64_t ldv, int64_t m, void* X,
+                           int64_t ldx, void* stream);
+
+/* Host copies of T: d[0..n) (diagonal) and e[0..n-1) (subdiagonal).  Waits for
+ * the device.  Errors: _NULL, _ARG (not factored), _HIP. */
+int expm_pfd_tridiag_diagonals(expm_pfd_tri_t tri, double* d, double* e);
+
+/* Release the plan (synchronizes the device first). */
+int expm_pfd_tridiag_destroy(expm_pfd_tri_t tri);
+
 /* ---- tracing ------------------------------------------------------------ */
 /* Kernel classes timed by the tracer (one HIP event pair per launch, recorded on
  * the stream the kernel is launched on). */

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libexpm_pfd.so")
 
-HIP_SOURCES = ["expm_pfd.hip"]
+HIP_SOURCES = ["expm_pfd.hip", "tridiag.hip"]
 HOST_SOURCES = ["constants.cpp"]
 ARCH = "gfx950"
 
@@ -48,13 +48,25 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", "-O2", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    hip_objs = []
+    # the HIP translation units compile in parallel
+    hip_objs, procs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
-              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-Wno-unused-result", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmd = [_hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-result", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         hip_objs.append(obj)
+    failed = False
+    for cmd, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    if failed:
+        raise RuntimeError("build step failed: hipcc")
     tmp = LIB + ".tmp"
     _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *hip_objs, *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "../../include/expm_pfd.h"
+#include "host_common.h"
 #include "kernels.h"
 
 using namespace expm;
@@ -49,8 +50,6 @@ constexpr int CHAIN_MP_MAX = 64;  // widest right-hand-side block solved by one-
 // from this many 16-column chains on, a sweep runs one workgroup per chain
 // (k_sweep_whole) instead of one per tile position (k_sweep_chain)
 constexpr int WHOLE_CHAIN_MIN = 256;
-
-inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // ---- per-launch event tracing (expm_pfd_trace) ---------------------------------
 namespace trace {
@@ -195,7 +194,7 @@ void panel(hipStream_t st, int IB, int S, const PanelArgs& g, cx<R>* W) {
 // order, same matrix-core instruction), so the choice never changes a bit of
 // the result; it is a speed knob only (built-in: 64 x 64; the autotuner times
 // all of them).
-constexpr int LU_TILES = 3;
+constexpr int LU_TILES = LU_TILE_COUNT;
 const char* const LU_TILE_NAMES[LU_TILES] = {"64x64", "128x64", "64x128"};
 
 // The plain and (GATABLE) the gated kernel of one k_gemm instantiation.
@@ -416,25 +415,6 @@ Sizes plan_sizes(int64_t npad, int G, int degree, int64_t mp_max, bool full_ok, 
   // two per workgroup of the per-block refinement kernels (at most max(2048, 2 PB) workgroups)
   s.irm = fp64 ? 0 : (size_t)2 * std::max<int64_t>(2048, 2 * PB) * sizeof(unsigned long long);
   return s;
-}
-
-int check_opts(const expm_pfd_opts* o) {
-  if (!o) return 0;
-  if (o->precision != EXPM_PFD_FP64 && o->precision != EXPM_PFD_MIXED) return EXPM_PFD_ERR_ARG;
-  if (o->lu_tile < 0 || o->lu_tile > LU_TILES) return EXPM_PFD_ERR_ARG;
-  if (o->uplo != EXPM_PFD_LOWER && o->uplo != EXPM_PFD_UPPER) return EXPM_PFD_ERR_ARG;
-  if (!std::isfinite(o->shift)) return EXPM_PFD_ERR_ARG;
-  if (!o->shift_scale_t && !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
-  if (std::isnan(o->ir_tol)) return EXPM_PFD_ERR_ARG;
-  return 0;
-}
-
-// Shift of one problem in units of its tA (c = shift, or t * shift when the
-// shift is given in units of A) and e^c; EXPM_PFD_ERR_ARG if e^c overflows.
-int problem_shift(double shift, int scale_t, double t, ProblemDesc& d) {
-  d.c = scale_t ? t * shift : shift;
-  d.ec = std::exp(d.c);
-  return std::isfinite(d.c) && std::isfinite(d.ec) ? 0 : EXPM_PFD_ERR_ARG;
 }
 
 void free_plan(expm_pfd_plan_t p) {
@@ -1052,10 +1032,6 @@ int validate_apply(expm_pfd_plan_t pl, const void* A, int64_t lda, const void* V
     if (m < 1 || m > cap) return EXPM_PFD_ERR_DIM;
   }
   return 0;
-}
-
-int check_degree(int degree) {
-  return (degree < 2 || degree > EXPM_PFD_MAX_DEGREE || (degree & 1)) ? EXPM_PFD_ERR_DEGREE : 0;
 }
 
 }  // namespace

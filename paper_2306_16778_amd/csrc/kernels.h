@@ -11,6 +11,9 @@
 #include "device_common.h"
 
 namespace expm {
+// Internal linkage: every translation unit that includes this file gets its own
+// copies of the kernels it uses.
+namespace {
 
 // ---------------------------------------------------------------------------
 // Stores one problem descriptor into device memory (the single-problem path
@@ -1591,4 +1594,5 @@ __global__ __launch_bounds__(256) void k_residual_dd(const double2* __restrict__
   }
 }
 
+}  // namespace
 }  // namespace expm

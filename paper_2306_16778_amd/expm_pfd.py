@@ -43,6 +43,11 @@ EXPORTED = (
     "expm_pfd_batch_check",
     "expm_pfd_batch_info",
     "expm_pfd_batch_destroy",
+    "expm_pfd_tridiag_plan",
+    "expm_pfd_tridiag_factor",
+    "expm_pfd_tridiag_apply",
+    "expm_pfd_tridiag_diagonals",
+    "expm_pfd_tridiag_destroy",
     "expm_pfd_strerror",
     "expm_pfd_trace",
     "expm_pfd_trace_summary",
@@ -114,6 +119,11 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_batch_check.argtypes = [vp]
     lib.expm_pfd_batch_info.argtypes = [vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     lib.expm_pfd_batch_destroy.argtypes = [vp]
+    lib.expm_pfd_tridiag_plan.argtypes = [ctypes.POINTER(vp), i64, c_int, i64, ctypes.POINTER(_Opts)]
+    lib.expm_pfd_tridiag_factor.argtypes = [vp, vp, i64, vp]
+    lib.expm_pfd_tridiag_apply.argtypes = [vp, c_double, vp, i64, i64, vp, i64, vp]
+    lib.expm_pfd_tridiag_diagonals.argtypes = [vp, vp, vp]
+    lib.expm_pfd_tridiag_destroy.argtypes = [vp]
     lib.expm_pfd_trace.argtypes = [c_int]
     lib.expm_pfd_trace_summary.argtypes = [c_int, ctypes.POINTER(c_double), ctypes.POINTER(i64),
                                            ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
@@ -453,6 +463,76 @@ def expm_pfd_batch_destroy(b: BatchPlan):
         _check(load_library().expm_pfd_batch_destroy(b.handle), "expm_pfd_batch_destroy")
         b.handle = None
         b._keep = None
+
+
+class TridiagPlan:
+    """Owns an expm_pfd_tri_t (the tridiagonal route: one reduction of A, many t)."""
+
+    def __init__(self, handle, n, degree, m_max):
+        self.handle = handle
+        self.n, self.degree, self.m_max = n, degree, m_max
+        self._keep = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                expm_pfd_tridiag_destroy(self)
+        except Exception:
+            pass
+
+
+def expm_pfd_tridiag_plan(n: int, degree: int, m_max: int = 16, uplo="L", shift: float = 0.0,
+                          shift_scale_t: bool = False) -> TridiagPlan:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    o = _opts("fp64", 0, shift=shift, uplo=uplo, shift_scale_t=shift_scale_t)
+    _check(lib.expm_pfd_tridiag_plan(ctypes.byref(h), int(n), int(degree), int(m_max), ctypes.byref(o)),
+           "expm_pfd_tridiag_plan")
+    return TridiagPlan(h.value, n, degree, m_max)
+
+
+def expm_pfd_tridiag_factor(tri: TridiagPlan, A, stream=None):
+    """A = Q T Q^H on the device (asynchronous on `stream`, default the current one)."""
+    import torch
+
+    Ac, lda = _colmajor(A, torch)
+    if Ac.shape[0] != tri.n:
+        raise ValueError("A must be n x n")
+    _check(load_library().expm_pfd_tridiag_factor(tri.handle, Ac.data_ptr(), lda, _stream_ptr(stream, torch)),
+           "expm_pfd_tridiag_factor")
+    tri._keep = Ac
+
+
+def expm_pfd_tridiag_apply(tri: TridiagPlan, t: float, V, X=None, stream=None):
+    """X = R_d(tA)V from the plan's reduction of A.  V: (n, m) complex128 device tensor."""
+    import torch
+
+    Vc, ldv = _colmajor(V, torch)
+    n, m = Vc.shape
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.complex128, device=Vc.device).t()
+    if not (X.stride(0) == 1 and X.stride(1) >= n and tuple(X.shape) == (n, m)):
+        raise ValueError("X must be a column-major (n, m) complex128 tensor")
+    _check(load_library().expm_pfd_tridiag_apply(tri.handle, float(t), Vc.data_ptr(), ldv, m, X.data_ptr(),
+                                                 X.stride(1), _stream_ptr(stream, torch)), "expm_pfd_tridiag_apply")
+    X._expm_keepalive = Vc
+    return X
+
+
+def expm_pfd_tridiag_diagonals(tri: TridiagPlan):
+    """(d, e): diagonal and subdiagonal of T (host float64 arrays)."""
+    d = np.zeros(tri.n)
+    e = np.zeros(max(tri.n - 1, 1))
+    _check(load_library().expm_pfd_tridiag_diagonals(tri.handle, d.ctypes.data, e.ctypes.data),
+           "expm_pfd_tridiag_diagonals")
+    return d, e[: tri.n - 1]
+
+
+def expm_pfd_tridiag_destroy(tri: TridiagPlan):
+    if tri.handle:
+        _check(load_library().expm_pfd_tridiag_destroy(tri.handle), "expm_pfd_tridiag_destroy")
+        tri.handle = None
+        tri._keep = None
 
 
 def expm_pfd_trace(classes=()):

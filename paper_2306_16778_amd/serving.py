@@ -94,7 +94,7 @@ def replay(count: int, qps: float, precision: str = "mixed", degree: int = 16, n
                 resident_sum += nbytes
                 pins = 0
             resident[r.matrix_id] = (mid, nbytes, pins + 1)  # most recently used last
-            V = torch.from_numpy(np.asfortranarray(r.v)).to("cuda", non_blocking=True)
+            V = torch.from_numpy(np.asfortranarray(r.v)).pin_memory().to("cuda", non_blocking=True)
             X = torch.empty((r.v.shape[1], r.n), dtype=torch.complex128, device="cuda").t()
             ev = torch.cuda.Event()
             ev.record(prep)

@@ -226,11 +226,14 @@ def config5_matrix_device(spec, device="cuda"):
     lam = r.uniform(-200.0, 0.0, n)
     vs = [complex_gaussian(r, n) for _ in range(3)]
     phase = np.exp(2j * np.pi * r.random(n))
-    X = torch.diag(torch.from_numpy(lam.astype(np.complex128)).to(device))
-    for v in reversed(vs):
-        v = torch.from_numpy(v / np.linalg.norm(v)).to(device)
+    # one pinned staging array and one asynchronous copy for all the draws
+    host = torch.from_numpy(np.stack([lam.astype(np.complex128)] + [v / np.linalg.norm(v) for v in vs] + [phase]))
+    draws = host.pin_memory().to(device, non_blocking=True) if str(device).startswith("cuda") else host
+    X = torch.diag(draws[0])
+    for k in (3, 2, 1):
+        v = draws[k]
         X = X - 2.0 * torch.outer(v, v.conj() @ X)
         X = X - 2.0 * torch.outer(X @ v, v.conj())
-    ph = torch.from_numpy(phase).to(device)
+    ph = draws[4]
     X = ph[:, None] * X * ph.conj()[None, :]
     return 0.5 * (X + X.conj().T)

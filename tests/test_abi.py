@@ -177,3 +177,18 @@ def test_noalloc_rejects_before_device_work():
     text = open(HEADER).read()
     size = re.search(r"#define EXPM_PFD_NOALLOC_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
     assert int(size.group(1)) << int(size.group(2)) == mod.NOALLOC_BYTES
+
+
+def test_tridiag_validation_without_device():
+    """The tridiagonal route's plan rejects bad arguments before any device work."""
+    mod, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.expm_pfd_tridiag_plan(None, 10, 16, 1, None) == -3
+    assert lib.expm_pfd_tridiag_plan(ctypes.byref(h), 10, 15, 1, None) == -1
+    assert lib.expm_pfd_tridiag_plan(ctypes.byref(h), 0, 16, 1, None) == -2
+    assert lib.expm_pfd_tridiag_plan(ctypes.byref(h), 10, 16, 0, None) == -2
+    assert lib.expm_pfd_tridiag_plan(ctypes.byref(h), 10, 16, 11, None) == -2
+    assert lib.expm_pfd_tridiag_plan(ctypes.byref(h), 100, 16, 65, None) == -2
+    assert lib.expm_pfd_tridiag_apply(None, 1.0, None, 1, 1, None, 1, None) == -3
+    assert lib.expm_pfd_tridiag_factor(None, None, 1, None) == -3
+    assert lib.expm_pfd_tridiag_destroy(None) == -3
