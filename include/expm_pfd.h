@@ -133,6 +133,10 @@ typedef struct expm_pfd_opts {
                       batch or queue): e^(t_i c) R_d(t_i (A_i - cI)) V_i.
                       e^(t_i c) must be finite for every apply (otherwise
                       EXPM_PFD_ERR_ARG from the apply or submit). */
+  int tridiag_reuse; /* queue only: a registered matrix named by this many
+                      requests is reduced once to tridiagonal form (the route of
+                      expm_pfd_tridiag_*), and its later requests are served by
+                      that route (FP64, O(n^2) per request).  0: never. */
 } expm_pfd_opts;
 
 /* ---- constants (host only) ---------------------------------------------- */
@@ -432,6 +436,8 @@ typedef struct expm_pfd_queue_s* expm_pfd_queue_t;
 
 typedef struct expm_pfd_queue_stats {
   int64_t submitted;
+  int64_t tridiag_requests;  /* requests served by the tridiagonal route (opts.tridiag_reuse) */
+  int64_t reductions;        /* matrices reduced to tridiagonal form */
   int64_t completed;         /* requests whose result is in X */
   int64_t failed;            /* requests failed (budget or sweep fault); not in `completed` */
   int64_t fallbacks;         /* requests solved again on the FP64 path (status 1) */

@@ -1661,7 +1661,11 @@ extern "C" int expm_pfd_apply_batched(int count, const int64_t* n, const double*
 // ============================================================================
 struct expm_pfd_queue_s {
   using clock = std::chrono::steady_clock;
-  enum { PENDING = 1, DONE = 2, FAIL_BUDGET = 3, FAIL_SYNC = 4 };
+  enum { PENDING = 1, DONE = 2, FAIL_BUDGET = 3, FAIL_SYNC = 4, FAIL_HIP = 5 };
+  // tridiagonal form of a registered matrix: none yet, wanted (its requests
+  // wait for it), being reduced, ready, or not made (no room in the budget)
+  enum { TRI_NONE = 0, TRI_WANTED, TRI_REDUCING, TRI_READY, TRI_SKIP };
+  enum { FLIGHT_LU = 0, FLIGHT_REDUCE, FLIGHT_TRI };
   struct Req {
     uint64_t ticket = 0;
     int64_t mat = -1;                // registered matrix, or -1: the caller's A read in place
@@ -1681,11 +1685,20 @@ struct expm_pfd_queue_s {
     double2* A = nullptr;
     int64_t n = 0;
     size_t bytes = 0;
-    int refs = 0;           // requests submitted and not yet completed
+    int refs = 0;           // requests submitted and not yet completed, and a reduction in flight
     bool released = false;  // unregistered: freed once refs is 0
     hipEvent_t ready = nullptr;
+    int64_t uses = 0;             // requests submitted for it
+    int tri_state = TRI_NONE;
+    expm_pfd_tri_t tri = nullptr;  // its tridiagonal form, once reduced
+    size_t tri_bytes = 0;          // device bytes of `tri` (counted with the matrices)
+    bool tri_busy = false;         // a flight of tridiagonal applies on it is in progress
   };
   struct Flight {
+    int kind = FLIGHT_LU;
+    int64_t mat = -1;              // FLIGHT_REDUCE, FLIGHT_TRI: the registered matrix
+    expm_pfd_tri_t tri = nullptr;  // ... and its tridiagonal plan
+    std::vector<int> rc;           // FLIGHT_TRI: launch status of each request's apply
     std::vector<Req> reqs;
     std::vector<ProblemDesc> descs;  // source of the descriptor upload, kept until completion
     expm_pfd_plan_t plan = nullptr;
@@ -1705,6 +1718,7 @@ struct expm_pfd_queue_s {
   std::unordered_map<uint64_t, Ticket> tickets;
   std::map<int64_t, Mat> mats;
   int64_t next_mat = 0;
+  std::deque<int64_t> want_tri;  // matrices whose reduction is to be launched, in order
   std::vector<std::unique_ptr<Flight>> flight;  // per worker stream: the flight in progress (or null)
   std::map<std::tuple<int64_t, int, int>, std::vector<expm_pfd_plan_t>> free_plans;  // (npad, Gcap, precision)
   std::vector<hipStream_t> streams;
@@ -1722,6 +1736,7 @@ struct expm_pfd_queue_s {
   int degree = 16, max_group = 64, device = 0;
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, fallbacks = 0, groups = 0, grouped = 0, padded_up = 0;
+  int64_t tri_requests = 0, reductions = 0;
   std::vector<double> lat_ms;
   clock::time_point first_submit, last_done;
   bool any_submit = false;
@@ -1774,8 +1789,10 @@ struct expm_pfd_queue_s {
     // the copy may still be in flight on the registering stream
     (void)hipStreamWaitEvent(aux, mt.ready, 0);
     (void)hipFreeAsync(mt.A, aux);
+    // every reduction and apply on the tridiagonal plan has completed (refs is 0)
+    if (mt.tri) tri_release(mt.tri, aux);
     give_event(mt.ready);
-    mat_bytes -= mt.bytes;
+    mat_bytes -= mt.bytes + mt.tri_bytes;
     mats.erase(it);
   }
   void drop_ref(int64_t mat) {
@@ -1783,6 +1800,16 @@ struct expm_pfd_queue_s {
     auto it = mats.find(mat);
     if (it == mats.end()) return;
     if (--it->second.refs == 0 && it->second.released) free_matrix(it);
+  }
+  // columns a tridiagonal plan of order n is made for (the requests' limit)
+  static int64_t tri_columns(int64_t n) { return std::min<int64_t>(16, n); }
+  // the request waits for, or is served on, its matrix's tridiagonal form
+  bool tri_routed(const Req& r) const {
+    if (r.mat < 0) return false;
+    auto it = mats.find(r.mat);
+    if (it == mats.end()) return false;
+    const int st = it->second.tri_state;
+    return (st == TRI_WANTED || st == TRI_REDUCING || st == TRI_READY) && r.m <= tri_columns(r.n);
   }
   void finish(Req& r, int state, int info, clock::time_point now) {
     Ticket& tk = tickets[r.ticket];
@@ -1805,6 +1832,22 @@ struct expm_pfd_queue_s {
   void retire(int s) {
     Flight& f = *flight[s];
     const auto now = clock::now();
+    if (f.kind != FLIGHT_LU) {
+      if (f.kind == FLIGHT_REDUCE) {
+        Mat& mt = mats[f.mat];
+        mt.tri = f.tri;
+        mt.tri_state = TRI_READY;
+        ++reductions;
+        drop_ref(f.mat);
+      } else {
+        mats[f.mat].tri_busy = false;  // (before the last request may free the matrix)
+        for (size_t k = 0; k < f.reqs.size(); ++k) finish(f.reqs[k], f.rc[k] ? FAIL_HIP : DONE, 0, now);
+      }
+      flight[s].reset();
+      cv_done.notify_all();
+      cv.notify_all();
+      return;
+    }
     const int* st = host_status + (size_t)s * max_group;
     bool sync_fault = false;
     std::vector<Req> redo;
@@ -1848,15 +1891,21 @@ struct expm_pfd_queue_s {
         s = i;
         break;
       }
-    if (s < 0 || pending.empty()) return false;
-    const int prec = pending.front().fp64 ? EXPM_PFD_FP64 : opts.precision;
+    if (s < 0) return false;
+    if (!want_tri.empty()) return launch_reduction(lk, s);
+    if (launch_tri(lk, s)) return true;
+    // the oldest request on the LU route
+    size_t i0 = 0;
+    while (i0 < pending.size() && tri_routed(pending[i0])) ++i0;
+    if (i0 == pending.size()) return false;
+    const int prec = pending[i0].fp64 ? EXPM_PFD_FP64 : opts.precision;
     // the group: the oldest request, then later ones (same precision) in arrival
     // order while the orders stay compatible
     std::vector<size_t> pick;
-    int64_t lo = round_up(pending.front().n, NB), hi = lo;
-    for (size_t i = 0; i < pending.size() && (int)pick.size() < max_group; ++i) {
+    int64_t lo = round_up(pending[i0].n, NB), hi = lo;
+    for (size_t i = i0; i < pending.size() && (int)pick.size() < max_group; ++i) {
       const Req& r = pending[i];
-      if ((r.fp64 ? EXPM_PFD_FP64 : opts.precision) != prec) continue;
+      if ((r.fp64 ? EXPM_PFD_FP64 : opts.precision) != prec || tri_routed(r)) continue;
       const int64_t np = round_up(r.n, NB);
       const int64_t nlo = std::min(lo, np), nhi = std::max(hi, np);
       if (!orders_compatible(nlo, nhi)) continue;
@@ -1970,6 +2019,113 @@ struct expm_pfd_queue_s {
     cv_flight.notify_all();
     return true;
   }
+  // Reduction of the oldest wanted matrix to tridiagonal form on stream s; its
+  // plan memory is counted with the matrices. Without room in the budget the
+  // matrix keeps the LU route. True: the queue's state changed.
+  bool launch_reduction(std::unique_lock<std::mutex>& lk, int s) {
+    const int64_t id = want_tri.front();
+    want_tri.pop_front();
+    auto it = mats.find(id);
+    if (it == mats.end()) return true;
+    Mat& mt = it->second;
+    if (mt.released) {
+      mt.tri_state = TRI_SKIP;
+      return true;
+    }
+    const int64_t cols = tri_columns(mt.n);
+    const size_t bytes = tri_bytes(mt.n, degree, cols);
+    release_cached(bytes);
+    if (mat_bytes + flight_bytes + bytes > budget) {
+      mt.tri_state = TRI_SKIP;
+      return true;
+    }
+    mt.tri_state = TRI_REDUCING;
+    mt.tri_bytes = bytes;
+    mat_bytes += bytes;
+    ++mt.refs;
+    note_peak();
+    auto f = std::make_unique<Flight>();
+    f->kind = FLIGHT_REDUCE;
+    f->mat = id;
+    Flight* fl = f.get();
+    flight[s] = std::move(f);
+    const double2* A = mt.A;
+    const int64_t n = mt.n;
+    hipEvent_t mat_ready = mt.ready;
+    lk.unlock();
+    // ---- enqueue without the lock ----
+    hipStream_t st = streams[s];
+    expm_pfd_tri_t tri = nullptr;
+    bool ok = tri_create(&tri, n, degree, cols, &opts, st) == 0;
+    ok = ok && hipStreamWaitEvent(st, mat_ready, 0) == hipSuccess;
+    ok = ok && expm_pfd_tridiag_factor(tri, A, n, st) == 0;
+    ok = ok && hipEventRecord(stream_ev[s], st) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      if (tri) {
+        (void)hipStreamSynchronize(st);
+        tri_release(tri, st);
+      }
+    }
+    lk.lock();
+    if (!ok) {
+      Mat& m2 = mats[id];
+      m2.tri_state = TRI_SKIP;
+      mat_bytes -= m2.tri_bytes;
+      m2.tri_bytes = 0;
+      flight[s].reset();
+      drop_ref(id);
+      return true;
+    }
+    fl->tri = tri;
+    fl->launched = true;
+    cv_flight.notify_all();
+    return true;
+  }
+  // The waiting requests of one reduced matrix (oldest first, up to max_group)
+  // applied one after another on stream s; one such flight per matrix at a time,
+  // as the applies share the plan's buffers. False: none to launch.
+  bool launch_tri(std::unique_lock<std::mutex>& lk, int s) {
+    int64_t id = -1;
+    std::vector<size_t> pick;
+    for (size_t i = 0; i < pending.size() && (int)pick.size() < max_group; ++i) {
+      const Req& r = pending[i];
+      if (!tri_routed(r)) continue;
+      const Mat& mt = mats.find(r.mat)->second;
+      if (mt.tri_state != TRI_READY || mt.tri_busy) continue;
+      if (id < 0) id = r.mat;
+      if (r.mat == id) pick.push_back(i);
+    }
+    if (pick.empty()) return false;
+    Mat& mt = mats[id];
+    mt.tri_busy = true;
+    auto f = std::make_unique<Flight>();
+    f->kind = FLIGHT_TRI;
+    f->mat = id;
+    f->tri = mt.tri;
+    for (auto g = pick.rbegin(); g != pick.rend(); ++g) {
+      f->reqs.push_back(pending[*g]);
+      pending.erase(pending.begin() + (int64_t)*g);
+    }
+    std::reverse(f->reqs.begin(), f->reqs.end());
+    f->rc.assign(f->reqs.size(), 0);
+    tri_requests += (int64_t)f->reqs.size();
+    Flight* fl = f.get();
+    flight[s] = std::move(f);
+    lk.unlock();
+    // ---- enqueue without the lock ----
+    hipStream_t st = streams[s];
+    for (size_t k = 0; k < fl->reqs.size(); ++k) {
+      const Req& r = fl->reqs[k];
+      if (r.ready) (void)hipStreamWaitEvent(st, r.ready, 0);
+      fl->rc[k] = expm_pfd_tridiag_apply(fl->tri, r.t, r.V, r.ldv, r.m, r.X, r.ldx, st);
+    }
+    (void)hipEventRecord(stream_ev[s], st);
+    lk.lock();
+    fl->launched = true;
+    cv_flight.notify_all();
+    return true;
+  }
   void loop() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
@@ -2014,6 +2170,8 @@ extern "C" int expm_pfd_queue_create(expm_pfd_queue_t* out, size_t hbm_budget, i
   *out = nullptr;
   if (int e = check_degree(degree)) return e;
   if (int e = check_opts(opts)) return e;
+  // the tridiagonal route reads imaginary parts: not with real_data
+  if (opts && opts->tridiag_reuse > 0 && opts->real_data) return EXPM_PFD_ERR_ARG;
   auto* q = new expm_pfd_queue_s();
   q->budget = hbm_budget;
   q->degree = degree;
@@ -2141,7 +2299,16 @@ extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, const void* A
     q->give_event(r.ready);
     return EXPM_PFD_ERR_HIP;
   }
-  if (r.mat >= 0) ++q->mats[r.mat].refs;
+  if (r.mat >= 0) {
+    expm_pfd_queue_s::Mat& mt = q->mats[r.mat];
+    ++mt.refs;
+    // the request that brings a matrix to its reuse threshold asks for its
+    // reduction; it and the later requests wait for the tridiagonal form
+    if (q->opts.tridiag_reuse > 0 && ++mt.uses >= q->opts.tridiag_reuse && mt.tri_state == expm_pfd_queue_s::TRI_NONE) {
+      mt.tri_state = expm_pfd_queue_s::TRI_WANTED;
+      q->want_tri.push_back(r.mat);
+    }
+  }
   r.ticket = q->next_ticket++;
   r.t = t;
   r.V = V;
@@ -2165,6 +2332,7 @@ extern "C" int expm_pfd_submit(expm_pfd_queue_t q, int64_t mat_id, const void* A
 static int state_error(int st) {
   return st == expm_pfd_queue_s::FAIL_BUDGET ? EXPM_PFD_ERR_BUDGET
          : st == expm_pfd_queue_s::FAIL_SYNC ? EXPM_PFD_ERR_SYNC
+         : st == expm_pfd_queue_s::FAIL_HIP  ? EXPM_PFD_ERR_HIP
                                               : 0;
 }
 
@@ -2205,6 +2373,8 @@ extern "C" int expm_pfd_queue_stats_get(expm_pfd_queue_t q, expm_pfd_queue_stats
   std::lock_guard<std::mutex> lk(q->mu);
   expm_pfd_queue_stats s{};
   s.submitted = q->submitted;
+  s.tridiag_requests = q->tri_requests;
+  s.reductions = q->reductions;
   s.completed = q->completed;
   s.failed = q->failed;
   s.fallbacks = q->fallbacks;
@@ -2248,7 +2418,10 @@ extern "C" int expm_pfd_queue_destroy(expm_pfd_queue_t q) {
   (void)hipDeviceSynchronize();
   for (auto& kv : q->free_plans)
     for (expm_pfd_plan_t p : kv.second) free_plan(p);
-  for (auto& kv : q->mats) (void)hipFreeAsync(kv.second.A, q->aux);
+  for (auto& kv : q->mats) {
+    (void)hipFreeAsync(kv.second.A, q->aux);
+    if (kv.second.tri) tri_release(kv.second.tri, q->aux);
+  }
   (void)hipStreamSynchronize(q->aux);
   for (auto& kv : q->mats) q->give_event(kv.second.ready);
   for (hipStream_t s : q->streams) (void)hipStreamSynchronize(s);

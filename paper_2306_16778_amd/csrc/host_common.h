@@ -26,6 +26,7 @@ inline int check_opts(const expm_pfd_opts* o) {
   if (!std::isfinite(o->shift)) return EXPM_PFD_ERR_ARG;
   if (!o->shift_scale_t && !std::isfinite(std::exp(o->shift))) return EXPM_PFD_ERR_ARG;
   if (std::isnan(o->ir_tol)) return EXPM_PFD_ERR_ARG;
+  if (o->tridiag_reuse < 0) return EXPM_PFD_ERR_ARG;
   return 0;
 }
 
@@ -36,5 +37,15 @@ inline int problem_shift(double shift, int scale_t, double t, ProblemDesc& d) {
   d.ec = std::exp(d.c);
   return std::isfinite(d.c) && std::isfinite(d.ec) ? 0 : EXPM_PFD_ERR_ARG;
 }
+
+// Tridiagonal-route plans with their device memory from the stream-ordered
+// pool on `pool` (the serving queue's use; nullptr: hipMalloc), and their
+// release on a stream (the plan's work must be complete or ordered before it).
+// Defined with the route (tridiag.hip).
+int tri_create(expm_pfd_tri_t* out, int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
+               hipStream_t pool);
+void tri_release(expm_pfd_tri_t tri, hipStream_t stream);
+// device bytes tri_create allocates
+size_t tri_bytes(int64_t n, int degree, int64_t m_max);
 
 }  // namespace expm

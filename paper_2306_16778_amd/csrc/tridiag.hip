@@ -528,6 +528,7 @@ void tri_gemm(hipStream_t st, int M, int N, int K, const double2* A, int64_t lda
 }  // namespace
 
 struct expm_pfd_tri_s {
+  bool pooled = false;  // memory from the stream-ordered pool
   int64_t n = 0, npad = 0, m_max = 0;
   int degree = 0, P = 0, upper = 0, shift_t = 0;
   double shift = 0.0;
@@ -561,16 +562,36 @@ struct expm_pfd_tri_s {
 
 namespace {
 
-void tri_free(expm_pfd_tri_t p) {
+void tri_free(expm_pfd_tri_t p, hipStream_t stream = nullptr) {
   if (!p) return;
   void* ptrs[] = {p->Aw, p->Q, p->d, p->e, p->tau, p->vbuf, p->y, p->part, p->yv, p->done, p->Vp, p->Tf,
                   p->Z1, p->Z2, p->Zp, p->theta, p->a, p->B, p->Xr, p->Ysol, p->Kp, p->U, p->F, p->desc};
   for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) (void)(p->pooled ? hipFreeAsync(q, stream) : hipFree(q));
   delete p;
 }
 
+// byte counts of the plan's arrays, in allocation order
+std::vector<size_t> tri_sizes(int64_t n, int degree, int64_t m_max) {
+  const int64_t np = round_up(n, 64), P = degree / 2, nt = P * 2 * m_max;
+  const int64_t nwg = (n + ROWS_PER_WG - 1) / ROWS_PER_WG;
+  return {(size_t)np * np * 16, (size_t)(np + TRI_PAD) * np * 16, (size_t)n * 8, (size_t)n * 8, (size_t)n * 16,
+          (size_t)2 * n * 16, (size_t)n * 16, (size_t)nwg * 16, 16, 16, (size_t)(n + TRI_PAD) * TRI_NB * 16,
+          (size_t)TRI_NB * TRI_NB * 16, (size_t)TRI_NB * n * 16, (size_t)TRI_NB * n * 16,
+          (size_t)TRI_KS * TRI_NB * n * 16, (size_t)P * 16, (size_t)P * 16, (size_t)np * m_max * 16,
+          (size_t)np * m_max * 16, (size_t)n * nt * 16, (size_t)TRI_KS * n * m_max * 16, (size_t)n * nt * 16,
+          (size_t)n * P * 2 * 3 * 16, sizeof(ProblemDesc)};
+}
+
 }  // namespace
+
+size_t expm::tri_bytes(int64_t n, int degree, int64_t m_max) {
+  size_t b = 0;
+  for (size_t x : tri_sizes(n, degree, m_max)) b += std::max<size_t>(x, 16);
+  return b;
+}
+
+void expm::tri_release(expm_pfd_tri_t tri, hipStream_t stream) { tri_free(tri, stream); }
 
 extern "C" int expm_pfd_tridiag_plan(expm_pfd_tri_t* out, int64_t n, int degree, int64_t m_max,
                                      const expm_pfd_opts* opts) {
@@ -579,7 +600,13 @@ extern "C" int expm_pfd_tridiag_plan(expm_pfd_tri_t* out, int64_t n, int degree,
   if (int e = check_degree(degree)) return e;
   if (n < 1 || n > EXPM_PFD_MAX_N || m_max < 1 || m_max > 64 || m_max > n) return EXPM_PFD_ERR_DIM;
   if (int e = check_opts(opts)) return e;
+  return tri_create(out, n, degree, m_max, opts, nullptr);
+}
+
+int expm::tri_create(expm_pfd_tri_t* out, int64_t n, int degree, int64_t m_max, const expm_pfd_opts* opts,
+                     hipStream_t pool) {
   auto* p = new expm_pfd_tri_s();
+  p->pooled = pool != nullptr;
   p->n = n;
   p->npad = round_up(n, 64);
   p->m_max = m_max;
@@ -594,44 +621,51 @@ extern "C" int expm_pfd_tridiag_plan(expm_pfd_tri_t* out, int64_t n, int degree,
     delete p;
     return rc;
   }
-  const int64_t np = p->npad, nt = (int64_t)p->P * 2 * m_max;
-  const int64_t nwg = (n + ROWS_PER_WG - 1) / ROWS_PER_WG;
+  const int64_t np = p->npad;
   bool ok = true;
-  auto dm = [&](auto** q, size_t bytes) { ok = ok && hipMalloc((void**)q, std::max<size_t>(bytes, 16)) == hipSuccess; };
-  dm(&p->Aw, (size_t)np * np * 16);
-  dm(&p->Q, (size_t)(np + TRI_PAD) * np * 16);
-  dm(&p->d, (size_t)n * 8);
-  dm(&p->e, (size_t)n * 8);
-  dm(&p->tau, (size_t)n * 16);
-  dm(&p->vbuf, (size_t)2 * n * 16);
-  dm(&p->y, (size_t)n * 16);
-  dm(&p->part, (size_t)nwg * 16);
-  dm(&p->yv, 16);
-  dm(&p->done, 16);
-  dm(&p->Vp, (size_t)(n + TRI_PAD) * TRI_NB * 16);
-  dm(&p->Zp, (size_t)TRI_KS * TRI_NB * n * 16);
-  dm(&p->Tf, (size_t)TRI_NB * TRI_NB * 16);
-  dm(&p->Z1, (size_t)TRI_NB * n * 16);
-  dm(&p->Z2, (size_t)TRI_NB * n * 16);
-  dm(&p->theta, (size_t)p->P * 16);
-  dm(&p->a, (size_t)p->P * 16);
+  const std::vector<size_t> sz = tri_sizes(n, degree, m_max);
+  size_t k = 0;
+  auto dm = [&](auto** q) {
+    const size_t bytes = std::max<size_t>(sz[k++], 16);
+    ok = ok && (pool ? hipMallocAsync((void**)q, bytes, pool) : hipMalloc((void**)q, bytes)) == hipSuccess;
+  };
+  // (order and sizes: tri_sizes)
+  dm(&p->Aw);
+  dm(&p->Q);
+  dm(&p->d);
+  dm(&p->e);
+  dm(&p->tau);
+  dm(&p->vbuf);
+  dm(&p->y);
+  dm(&p->part);
+  dm(&p->yv);
+  dm(&p->done);
+  dm(&p->Vp);
+  dm(&p->Tf);
+  dm(&p->Z1);
+  dm(&p->Z2);
+  dm(&p->Zp);
+  dm(&p->theta);
+  dm(&p->a);
   // B and Xr have npad rows, zero past n: the K slices of the products with Q
   // run over all npad rows (Q is zero there too)
-  dm(&p->B, (size_t)np * m_max * 16);
-  dm(&p->Xr, (size_t)np * m_max * 16);
-  dm(&p->Kp, (size_t)TRI_KS * n * m_max * 16);
-  dm(&p->Ysol, (size_t)n * nt * 16);
-  dm(&p->U, (size_t)n * nt * 16);
-  dm(&p->F, (size_t)n * p->P * 2 * 3 * 16);  // one copy per workgroup of a pole (at most 2: 2 m_max <= 128)
-  dm(&p->desc, sizeof(ProblemDesc));
-  if (ok) ok = hipMemcpy(p->theta, p->h_theta.data(), p->P * 16, hipMemcpyHostToDevice) == hipSuccess;
-  if (ok) ok = hipMemcpy(p->a, p->h_a.data(), p->P * 16, hipMemcpyHostToDevice) == hipSuccess;
-  if (ok) ok = hipMemset(p->done, 0, 16) == hipSuccess;
-  if (ok) ok = hipMemset(p->B, 0, (size_t)np * m_max * 16) == hipSuccess;
-  if (ok) ok = hipMemset(p->Xr, 0, (size_t)np * m_max * 16) == hipSuccess;
+  dm(&p->B);
+  dm(&p->Xr);
+  dm(&p->Ysol);
+  dm(&p->Kp);
+  dm(&p->U);
+  dm(&p->F);  // one copy per workgroup of a pole (at most 2: 2 m_max <= 128)
+  dm(&p->desc);
+  // the constants' host copies live in the plan, so the copies may complete later
+  if (ok) ok = hipMemcpyAsync(p->theta, p->h_theta.data(), p->P * 16, hipMemcpyHostToDevice, pool) == hipSuccess;
+  if (ok) ok = hipMemcpyAsync(p->a, p->h_a.data(), p->P * 16, hipMemcpyHostToDevice, pool) == hipSuccess;
+  if (ok) ok = hipMemsetAsync(p->done, 0, 16, pool) == hipSuccess;
+  if (ok) ok = hipMemsetAsync(p->B, 0, (size_t)np * m_max * 16, pool) == hipSuccess;
+  if (ok) ok = hipMemsetAsync(p->Xr, 0, (size_t)np * m_max * 16, pool) == hipSuccess;
+  if (ok && !pool) ok = hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     const bool oom = hipGetLastError() == hipErrorOutOfMemory;
-    tri_free(p);
+    tri_free(p, pool);
     return oom ? EXPM_PFD_ERR_OOM : EXPM_PFD_ERR_HIP;
   }
   *out = p;

@@ -74,7 +74,8 @@ class ExpmPfdError(RuntimeError):
 
 
 class _QueueStats(ctypes.Structure):
-    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+    _fields_ = [("submitted", ctypes.c_int64), ("tridiag_requests", ctypes.c_int64), ("reductions", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("fallbacks", ctypes.c_int64), ("groups", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
@@ -86,7 +87,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("ir_max_iter", ctypes.c_int), ("ir_extended", ctypes.c_int),
                 ("real_data", ctypes.c_int), ("graph", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("lu_tile", ctypes.c_int), ("uplo", ctypes.c_int), ("shift", ctypes.c_double),
-                ("ir_tol", ctypes.c_double), ("shift_scale_t", ctypes.c_int)]
+                ("ir_tol", ctypes.c_double), ("shift_scale_t", ctypes.c_int), ("tridiag_reuse", ctypes.c_int)]
 
 # tile shapes of the LU trailing update, in the order of expm_pfd_opts.lu_tile - 1
 LU_TILES = ("64x64", "128x64", "64x128")
@@ -573,11 +574,13 @@ class Queue:
 
 def expm_pfd_queue_create(hbm_budget: int, degree: int, precision="fp64", ir_max_iter: int = 0, max_group: int = 64,
                           streams: int = 3, shift: float = 0.0, real_data: bool = False,
-                          ir_extended: int = 0, uplo="L", ir_tol: float = 0.0, shift_scale_t: bool = False) -> Queue:
+                          ir_extended: int = 0, uplo="L", ir_tol: float = 0.0, shift_scale_t: bool = False,
+                          tridiag_reuse: int = 0) -> Queue:
     lib = load_library()
     h = ctypes.c_void_p()
     o = _opts(precision, ir_max_iter, ir_extended, shift, real_data, uplo=uplo, ir_tol=ir_tol,
               shift_scale_t=shift_scale_t)
+    o.tridiag_reuse = int(tridiag_reuse)
     _check(lib.expm_pfd_queue_create(ctypes.byref(h), int(hbm_budget), int(degree), ctypes.byref(o), int(max_group),
                                      int(streams)), "expm_pfd_queue_create")
     return Queue(h.value)

@@ -192,3 +192,10 @@ def test_tridiag_validation_without_device():
     assert lib.expm_pfd_tridiag_apply(None, 1.0, None, 1, 1, None, 1, None) == -3
     assert lib.expm_pfd_tridiag_factor(None, None, 1, None) == -3
     assert lib.expm_pfd_tridiag_destroy(None) == -3
+    # the queue's reuse threshold: not negative, and not with real_data (the
+    # tridiagonal route reads imaginary parts)
+    o = mod._Opts()
+    o.tridiag_reuse = -1
+    assert lib.expm_pfd_queue_create(ctypes.byref(h), 1 << 30, 16, ctypes.byref(o), 8, 1) == -7
+    o.tridiag_reuse, o.real_data = 2, 1
+    assert lib.expm_pfd_queue_create(ctypes.byref(h), 1 << 30, 16, ctypes.byref(o), 8, 1) == -7

@@ -267,6 +267,69 @@ def test_queue_shift_and_real_data(ep, precision, tol):
     assert matrix.rel_fro(res[0], matrix.expm_R(B, ws[0], 0.5, 16)) < tol
 
 
+def test_queue_tridiagonal_reuse(ep):
+    """A mixed-precision queue with a reuse threshold of 3: the request that brings a
+    registered matrix to 3 uses asks for its reduction to tridiagonal form, and it
+    and every later request of that matrix are served by tridiagonal solves (FP64
+    throughout: the FP64 gate); requests before it may have gone the LU route
+    (mixed tolerance). A matrix below the threshold and a matrix read in place keep
+    the LU route. Then an FP64 queue with threshold 1 and the shift in units of A:
+    every request of the matrix on the tridiagonal route, against the oracle's
+    e^{tc} R_d(tA - tcI)v."""
+    import torch
+    from paper_2306_16778_amd import workloads as wl
+
+    rng = np.random.default_rng(63)
+    n, nb = 300, 97
+    A = wl.hermitian_with_spectrum(rng, rng.uniform(-150.0, 0.0, n))
+    B = wl.hermitian_with_spectrum(rng, rng.uniform(-90.0, 0.0, nb))
+    q = ep.expm_pfd_queue_create(4 << 30, 16, "mixed", tridiag_reuse=3)
+    mid = ep.expm_pfd_register_matrix(q, _dev(A))
+    bid = ep.expm_pfd_register_matrix(q, _dev(B))
+    _announce(f"queue tridiagonal reuse n={n}")
+    cols = [1, 3, 16, 2, 1, 5, 16, 1, 4, 2]
+    ts = [0.1 * (k + 1) for k in range(len(cols))]
+    vs = [wl.complex_gaussian(rng, n, m) for m in cols]
+    outs = [ep.expm_pfd_submit(q, mid, t, _dev(v)) for t, v in zip(ts, vs)]
+    ws = [wl.complex_gaussian(rng, nb, 2) for _ in range(2)]
+    bouts = [ep.expm_pfd_submit(q, bid, 0.5 + 0.2 * k, _dev(w)) for k, w in enumerate(ws)]
+    _, Xin = ep.expm_pfd_submit(q, _dev(B), 0.9, _dev(ws[0]))
+    ep.expm_pfd_queue_drain(q)
+    for k, (t, (tk, X), v) in enumerate(zip(ts, outs, vs)):
+        assert ep.expm_pfd_poll(q, tk) == (True, 0)
+        err = matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, v, t, 16))
+        assert err < 1e-10 if k < 2 else _within(err, 1e-12, A, v, t), (k, err)
+    for k, ((_, X), w) in enumerate(zip(bouts, ws)):
+        assert matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(B, w, 0.5 + 0.2 * k, 16)) < 1e-10
+    assert matrix.rel_fro(Xin.cpu().numpy(), matrix.expm_R(B, ws[0], 0.9, 16)) < 1e-10
+    st = ep.expm_pfd_queue_stats_get(q)
+    assert st["reductions"] == 1 and 8 <= st["tridiag_requests"] <= 10, st
+    assert st["completed"] == 13 and st["failed"] == 0
+    # the registered bytes hold both matrices and the tridiagonal plan
+    assert st["registered"] == 2 and st["registered_bytes"] > (n * n + nb * nb) * 16
+    ep.expm_pfd_unregister_matrix(q, mid)
+    st = ep.expm_pfd_queue_stats_get(q)
+    assert st["registered"] == 1 and st["registered_bytes"] == nb * nb * 16
+    ep.expm_pfd_queue_destroy(q)
+
+    c = 15.0
+    C = wl.hermitian_with_spectrum(rng, rng.uniform(0.0, c, n))
+    q = ep.expm_pfd_queue_create(4 << 30, 16, "fp64", tridiag_reuse=1, shift=c, shift_scale_t=True)
+    mid = ep.expm_pfd_register_matrix(q, _dev(C))
+    _announce(f"queue tridiagonal reuse with shift n={n} c={c} (units of A)")
+    ts = [1.0, 0.4, 0.15]
+    vs = [wl.complex_gaussian(rng, n, 2) for _ in ts]
+    outs = [ep.expm_pfd_submit(q, mid, t, _dev(v)) for t, v in zip(ts, vs)]
+    ep.expm_pfd_queue_drain(q)
+    for t, (_, X), v in zip(ts, outs, vs):
+        Y = matrix.expm_R_shifted(C, v, t, 16, t * c)
+        assert matrix.rel_fro(X.cpu().numpy(), Y) < 1e-12
+    st = ep.expm_pfd_queue_stats_get(q)
+    assert st["reductions"] == 1 and st["tridiag_requests"] == 3
+    ep.expm_pfd_queue_destroy(q)
+    torch.cuda.synchronize()
+
+
 def test_budget_admission(ep):
     """A budget too small for one workspace rejects the request; a budget for one
     group at a time still completes every request (they queue, never run out of
