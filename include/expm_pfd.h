@@ -371,6 +371,67 @@ int expm_pfd_tridiag_diagonals(expm_pfd_tri_t tri, double* d, double* e);
 /* Release the plan (synchronizes the device first). */
 int expm_pfd_tridiag_destroy(expm_pfd_tri_t tri);
 
+/* ---- banded route: Hermitian band matrices -------------------------------- */
+/*
+ * R_d(tA) V for Hermitian A with kd sub- and superdiagonals: the finite-difference
+ * Laplacians of the paper's experiments (Sec. 5: B = 1D, kd = 1; C = 2D on an
+ * s x s grid numbered row by row, kd = s) and any other band matrix.  For each
+ * pole theta_k the band matrix tA + theta_k I is factored by Gaussian elimination
+ * with partial pivoting inside the band (the upper factor gains kd diagonals of
+ * fill), the elimination applied to V as it goes, followed by a banded back
+ * substitution; then Y = sum_k a_k X_k in FP64 in a fixed pole order
+ * (eq. equ:expAx).  Each conjugate pole is solved on its own (tA + conj(theta) I
+ * is a different band matrix), or, with opts.real_data, not at all: the result is
+ * 2 Re(sum over one member per pair) (Remark rem:two_time_real_part).  Work per
+ * pole O(n kd (kd + m)); everything in FP64 (opts.precision is accepted and does
+ * not change the route).
+ *
+ * Band storage (LAPACK's layout), column-major AB with ldab >= kd + 1:
+ *   lower (default):  AB[(i - j) + j*ldab] = A(i, j),  j <= i <= min(n-1, j+kd);
+ *   upper (opts.uplo): AB[(kd + i - j) + j*ldab] = A(i, j),  max(0, j-kd) <= i <= j.
+ * The other triangle is its conjugate and the imaginary part of the diagonal is
+ * not read.
+ */
+typedef struct expm_pfd_band_s* expm_pfd_band_t;
+
+#define EXPM_PFD_BAND_MAX_KD 63       /* widest band (one row per lane of a wave) */
+#define EXPM_PFD_BAND_MAX_N  16777216 /* largest order of the banded route */
+
+/* Plan for band matrices of order n (1..EXPM_PFD_BAND_MAX_N) with kd
+ * (0..EXPM_PFD_BAND_MAX_KD) sub- and superdiagonals, degree d, right-hand sides of
+ * at most m_max columns (1..64).  opts: uplo, real_data, shift and shift_scale_t
+ * apply; others are ignored.  Allocates (d, or d/2 with real_data) x n x
+ * (2 min(kd, n-1) + 1 + m_max) x 16 bytes on the current device.
+ * Errors: EXPM_PFD_ERR_DEGREE, _DIM, _ARG, _NULL, _OOM, _HIP. */
+int expm_pfd_band_plan(expm_pfd_band_t* out, int64_t n, int64_t kd, int degree, int64_t m_max,
+                       const expm_pfd_opts* opts);
+
+/* X = R_d(tA) V (with the shift: e^c R_d(tA - cI) V).  AB: device band storage
+ * as above (ldab >= kd + 1); V: device n x m column-major (ldv >= n),
+ * 1 <= m <= m_max; X: device n x m (ldx >= n), not overlapping AB or V.
+ * Asynchronous on `stream`; calls on one plan must not overlap.
+ * Errors: _NULL, _ARG (t not finite, e^shift overflows), _DIM, _LD, _HIP. */
+int expm_pfd_band_apply(expm_pfd_band_t plan, double t, const void* AB, int64_t ldab, const void* V,
+                        int64_t ldv, int64_t m, void* X, int64_t ldx, void* stream);
+
+/* Release the plan (synchronizes the device first). */
+int expm_pfd_band_destroy(expm_pfd_band_t plan);
+
+/* ---- degree adapted to the arithmetic ------------------------------------ */
+/*
+ * Sec. 4 (Fig. fig:maple, Prop. prop:digit): with D significant digits the
+ * evaluated partial fractions differ from e^x on x <= 0 by at most
+ * M_1(d) + M_2(d, D), with M_1(d) = 2^-d (Prop. pro:err) and
+ * M_2(d, D) = (C_1(D) + C_2(d, D)) sum_k |a_k| (eq. eq:upper_bound).  M_1 falls
+ * and M_2 grows with d, so the precision fixes a best degree.
+ *
+ * *degree: the smallest even d in [2, EXPM_PFD_MAX_DEGREE] whose bound is at most
+ * tol (return 0), or, if none is, the even d with the smallest bound (return 1).
+ * *bound (may be NULL): that d's bound.  digits: D, 4..34 (16 for FP64 results,
+ * which both precisions deliver).  Host only, no device work.
+ * Errors: _NULL, _ARG (digits out of range, tol NaN), _CONST. */
+int expm_pfd_choose_degree(double tol, int digits, int* degree, double* bound);
+
 /* ---- tracing ------------------------------------------------------------ */
 /* Kernel classes timed by the tracer (one HIP event pair per launch, recorded on
  * the stream the kernel is launched on). */

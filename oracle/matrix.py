@@ -108,6 +108,58 @@ def pfd_amplification(A, V, t: float, d: int, eig=None) -> float:
     return float(num / den)
 
 
+def band_to_dense(AB, kd: int, upper: bool = False) -> np.ndarray:
+    """The Hermitian matrix stored in band form (the Laplacians of Sec. 5 and any
+    Hermitian matrix with kd sub- and superdiagonals), written out by plain loops.
+
+    Storage (LAPACK's band layout, column j of AB holding column j of A):
+    lower: AB[i - j, j] = A[i, j] for j <= i <= min(n - 1, j + kd);
+    upper: AB[kd + i - j, j] = A[i, j] for max(0, j - kd) <= i <= j.
+    The other triangle follows by conjugation and the diagonal's imaginary part is
+    dropped, as for the dense operand.
+    """
+    AB = np.asarray(AB, dtype=np.complex128)
+    n = AB.shape[1]
+    T = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):
+        if upper:
+            for i in range(max(0, j - kd), j + 1):
+                T[j, i] = np.conj(AB[kd + i - j, j])  # the lower triangle's (j, i)
+        else:
+            for i in range(j, min(n, j + kd + 1)):
+                T[i, j] = AB[i - j, j]
+    return hermitian_from_lower(T)
+
+
+def expm_R_band(AB, kd: int, V, t: float, d: int, c: float = 0.0, upper: bool = False):
+    """R_d(tA)V (or e^c R_d(tA - cI)V with the shift) for A in band storage: the
+    dense definition applied to the matrix the band stores."""
+    A = band_to_dense(AB, kd, upper)
+    return expm_R_shifted(A, V, t, d, c) if c else expm_R(A, V, t, d)
+
+
+def expm_R_laplacian(s: int, dim: int, V, t: float, d: int):
+    """R_d(tL)V for the Dirichlet finite-difference Laplacian L of Sec. 5 on s
+    points per axis (dim = 1: B, order s; dim = 2: C, order s^2, unknowns numbered
+    row by row), through its eigendecomposition in closed form: the orthonormal
+    sine transform (DST-I) diagonalizes L with eigenvalues -(4/h^2) sin^2(k pi h/2)
+    per axis, h = 1/(s+1), summed over the axes in 2D.  The transform is a library
+    FFT, so any order the product path takes is within reach."""
+    from scipy import fft
+
+    h = 1.0 / (s + 1)
+    lam1 = -4.0 / h ** 2 * np.sin(np.arange(1, s + 1) * np.pi * h / 2) ** 2
+    V = np.asarray(V, dtype=np.complex128)
+    m = V.shape[1]
+    if dim == 1:
+        W = fft.dst(V, type=1, norm="ortho", axis=0)
+        return fft.dst(scalar.R_direct(t * lam1, d)[:, None] * W, type=1, norm="ortho", axis=0)
+    lam = lam1[:, None] + lam1[None, :]  # (grid row, grid column)
+    G = V.reshape(s, s, m)  # unknown i*s + j at grid row i, column j
+    W = fft.dstn(G, type=1, norm="ortho", axes=(0, 1))
+    return fft.dstn(scalar.R_direct(t * lam, d)[:, :, None] * W, type=1, norm="ortho", axes=(0, 1)).reshape(s * s, m)
+
+
 def rel_fro(X, Y) -> float:
     """||X - Y||_F / ||Y||_F."""
     X = np.asarray(X)

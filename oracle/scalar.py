@@ -194,6 +194,30 @@ def M2(d: int, D: int, abs_residue_sum: float) -> float:
     return (c1 + c2) * abs_residue_sum
 
 
+def choose_degree(tol: float, D: int, d_max: int = 64):
+    """Degree adapted to the arithmetic (Sec. 4: the precision must be adapted to
+    the degree, Fig. fig:maple; the bound of Prop. prop:digit).
+
+    With D significant digits the evaluated partial fractions differ from e^x on
+    x <= 0 by at most M_1(d) + M_2(d, D): Prop. pro:err bounds R_d - e^x, Prop.
+    prop:digit bounds the rounded sum against R_d, and the two add.  M_1 falls
+    with d and M_2 grows with sum_k |a_k|, so the total has a smallest value.
+
+    Returns (d, bound, guaranteed): the smallest even d in [2, d_max] whose total
+    bound is at most tol (guaranteed True); when no degree meets tol, the even
+    degree with the smallest total bound (guaranteed False).
+    """
+    best = None
+    for d in range(2, d_max + 1, 2):
+        _, a = pfd_all(d)
+        b = M1(d) + M2(d, D, float(np.sum(np.abs(a))))
+        if b <= tol:
+            return d, b, True
+        if best is None or b < best[1]:
+            best = (d, b)
+    return best[0], best[1], False
+
+
 def err_shape(d: int, x):
     """err_d(x) = R_d(x) - e^x on x <= 0 (Prop. pro:wxcv1), at extended precision."""
     # near 0 the difference is O(x^{d+2}) (eq. equ:pade), hence the generous precision

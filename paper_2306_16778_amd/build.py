@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libexpm_pfd.so")
 
-HIP_SOURCES = ["expm_pfd.hip", "tridiag.hip"]
+HIP_SOURCES = ["expm_pfd.hip", "tridiag.hip", "band.hip"]
 HOST_SOURCES = ["constants.cpp"]
 ARCH = "gfx950"
 

@@ -178,3 +178,38 @@ int compute_constants(int degree, double* theta, double* a) {
   return EXPM_PFD_OK;
 }
 }  // namespace
+
+// Degree adapted to D significant digits (Sec. 4, Prop. prop:digit): the smallest
+// even d whose bound M_1(d) + M_2(d, D) on the evaluated partial fractions'
+// distance from e^x (x <= 0) is at most tol, else the even d with the smallest
+// bound.  M_1(d) = 2^-d (Prop. pro:err); M_2 = (C_1 + C_2) sum_k |a_k| over all d
+// residues, i.e. twice the sum over the pair representatives.
+extern "C" int expm_pfd_choose_degree(double tol, int digits, int* degree, double* bound) {
+  if (!degree) return EXPM_PFD_ERR_NULL;
+  if (digits < 4 || digits > 34 || std::isnan(tol)) return EXPM_PFD_ERR_ARG;
+  const double gamma = 0.29044;  // eq. eq:ecart
+  const double eps = std::pow(10.0, 1 - digits);
+  int best_d = 0;
+  double best_b = 0.0;
+  for (int d = 2; d <= EXPM_PFD_MAX_DEGREE; d += 2) {
+    std::vector<double> th(d), a(d);
+    if (int rc = expm_pfd_constants(d, th.data(), a.data())) return rc;
+    double sum = 0.0;
+    for (int k = 0; k < d / 2; ++k) sum += 2.0 * std::hypot(a[2 * k], a[2 * k + 1]);
+    const double c1 = 2.0 * eps / (gamma * (1.0 - eps));
+    const double c2 = 4.0 * d * eps / (gamma * (gamma - d * eps));  // gamma > d eps for digits >= 4
+    const double b = std::ldexp(1.0, -d) + (c1 + c2) * sum;
+    if (b <= tol) {
+      *degree = d;
+      if (bound) *bound = b;
+      return 0;
+    }
+    if (best_d == 0 || b < best_b) {
+      best_d = d;
+      best_b = b;
+    }
+  }
+  *degree = best_d;
+  if (bound) *bound = best_b;
+  return 1;
+}

@@ -48,6 +48,10 @@ EXPORTED = (
     "expm_pfd_tridiag_apply",
     "expm_pfd_tridiag_diagonals",
     "expm_pfd_tridiag_destroy",
+    "expm_pfd_band_plan",
+    "expm_pfd_band_apply",
+    "expm_pfd_band_destroy",
+    "expm_pfd_choose_degree",
     "expm_pfd_strerror",
     "expm_pfd_trace",
     "expm_pfd_trace_summary",
@@ -125,6 +129,10 @@ def load_library() -> ctypes.CDLL:
     lib.expm_pfd_tridiag_apply.argtypes = [vp, c_double, vp, i64, i64, vp, i64, vp]
     lib.expm_pfd_tridiag_diagonals.argtypes = [vp, vp, vp]
     lib.expm_pfd_tridiag_destroy.argtypes = [vp]
+    lib.expm_pfd_band_plan.argtypes = [ctypes.POINTER(vp), i64, i64, c_int, i64, ctypes.POINTER(_Opts)]
+    lib.expm_pfd_band_apply.argtypes = [vp, c_double, vp, i64, vp, i64, i64, vp, i64, vp]
+    lib.expm_pfd_band_destroy.argtypes = [vp]
+    lib.expm_pfd_choose_degree.argtypes = [c_double, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]
     lib.expm_pfd_trace.argtypes = [c_int]
     lib.expm_pfd_trace_summary.argtypes = [c_int, ctypes.POINTER(c_double), ctypes.POINTER(i64),
                                            ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
@@ -534,6 +542,69 @@ def expm_pfd_tridiag_destroy(tri: TridiagPlan):
         _check(load_library().expm_pfd_tridiag_destroy(tri.handle), "expm_pfd_tridiag_destroy")
         tri.handle = None
         tri._keep = None
+
+
+class BandPlan:
+    """Owns an expm_pfd_band_t (the banded route)."""
+
+    def __init__(self, handle, n, kd, degree, m_max):
+        self.handle = handle
+        self.n, self.kd, self.degree, self.m_max = n, kd, degree, m_max
+
+    def __del__(self):
+        try:
+            if self.handle:
+                expm_pfd_band_destroy(self)
+        except Exception:
+            pass
+
+
+def expm_pfd_band_plan(n: int, kd: int, degree: int, m_max: int = 16, uplo="L", real_data: bool = False,
+                       shift: float = 0.0, shift_scale_t: bool = False) -> BandPlan:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    o = _opts("fp64", 0, shift=shift, real_data=real_data, uplo=uplo, shift_scale_t=shift_scale_t)
+    _check(lib.expm_pfd_band_plan(ctypes.byref(h), int(n), int(kd), int(degree), int(m_max), ctypes.byref(o)),
+           "expm_pfd_band_plan")
+    return BandPlan(h.value, n, kd, degree, m_max)
+
+
+def expm_pfd_band_apply(plan: BandPlan, t: float, AB, V, X=None, stream=None):
+    """X = R_d(tA)V for A in band storage.  AB: (ldab >= kd + 1, n) complex128 device
+    tensor in LAPACK band layout (column j of AB holds column j's band); V: (n, m)."""
+    import torch
+
+    ABc, ldab = _colmajor(AB, torch)
+    Vc, ldv = _colmajor(V, torch)
+    n, m = Vc.shape
+    if ABc.shape[1] != plan.n or n != plan.n:
+        raise ValueError("AB must have n columns and V n rows")
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.complex128, device=Vc.device).t()
+    if not (X.stride(0) == 1 and X.stride(1) >= n and tuple(X.shape) == (n, m)):
+        raise ValueError("X must be a column-major (n, m) complex128 tensor")
+    _check(load_library().expm_pfd_band_apply(plan.handle, float(t), ABc.data_ptr(), ldab, Vc.data_ptr(), ldv, m,
+                                              X.data_ptr(), X.stride(1), _stream_ptr(stream, torch)),
+           "expm_pfd_band_apply")
+    X._expm_keepalive = (ABc, Vc)
+    return X
+
+
+def expm_pfd_band_destroy(plan: BandPlan):
+    if plan.handle:
+        _check(load_library().expm_pfd_band_destroy(plan.handle), "expm_pfd_band_destroy")
+        plan.handle = None
+
+
+def expm_pfd_choose_degree(tol: float, digits: int = 16):
+    """(degree, bound, guaranteed): the degree adapted to `digits` significant digits
+    for the uniform tolerance `tol` (host only)."""
+    d = ctypes.c_int()
+    b = ctypes.c_double()
+    rc = load_library().expm_pfd_choose_degree(float(tol), int(digits), ctypes.byref(d), ctypes.byref(b))
+    if rc < 0:
+        _check(rc, "expm_pfd_choose_degree")
+    return d.value, b.value, rc == 0
 
 
 def expm_pfd_trace(classes=()):

@@ -237,3 +237,51 @@ def config5_matrix_device(spec, device="cuda"):
     ph = draws[4]
     X = ph[:, None] * X * ph.conj()[None, :]
     return 0.5 * (X + X.conj().T)
+
+
+# --------------------------------------------------------------------------
+# banded workloads: the finite-difference Laplacians of Sec. 5 (B = 1D, C = 2D)
+# and random Hermitian band matrices, in lower band storage (kd + 1, n):
+# AB[i - j, j] = A[i, j] for j <= i <= j + kd
+# --------------------------------------------------------------------------
+
+def laplacian_1d_band(n: int):
+    """(AB, kd) of the 1D Dirichlet finite-difference Laplacian on n interior
+    points of [0, 1]: (u_{i-1} - 2 u_i + u_{i+1}) / h^2, h = 1 / (n + 1)."""
+    h2 = float(n + 1) ** 2
+    AB = np.zeros((2, n), dtype=np.complex128)
+    AB[0, :] = -2.0 * h2
+    AB[1, : n - 1] = h2
+    return AB, 1
+
+
+def laplacian_2d_band(s: int):
+    """(AB, kd) of the 2D five-point Dirichlet Laplacian on an s x s grid of the
+    unit square, unknowns numbered row by row (n = s^2, kd = s), h = 1 / (s + 1)."""
+    n = s * s
+    h2 = float(s + 1) ** 2
+    AB = np.zeros((s + 1, n), dtype=np.complex128)
+    AB[0, :] = -4.0 * h2
+    for j in range(n):
+        if (j + 1) % s != 0:  # east neighbour in the same grid row
+            AB[1, j] = h2
+        if j + s < n:  # north neighbour
+            AB[s, j] = h2
+    return AB, s
+
+
+def random_hermitian_band(rng: np.random.Generator, n: int, kd: int, spread: float = 10.0, real: bool = False):
+    """Random Hermitian band matrix with spectrum in roughly [-(R + spread), 0]:
+    Gaussian entries in the band, each diagonal entry set to minus its row's
+    off-diagonal absolute sum (Gershgorin) minus uniform(0, spread)."""
+    AB = np.zeros((kd + 1, n), dtype=np.complex128)
+    kw = min(kd, n - 1)  # diagonals that exist
+    for k in range(1, kw + 1):
+        g = rng.standard_normal(n - k) if real else complex_gaussian(rng, n - k)
+        AB[k, : n - k] = g
+    rad = np.zeros(n)
+    for k in range(1, kw + 1):
+        rad[: n - k] += np.abs(AB[k, : n - k])  # A[j + k, j] in column j ...
+        rad[k:] += np.abs(AB[k, : n - k])  # ... and its conjugate in row j
+    AB[0, :] = -rad - rng.uniform(0.0, spread, n)
+    return AB, kd

@@ -199,3 +199,43 @@ def test_tridiag_validation_without_device():
     assert lib.expm_pfd_queue_create(ctypes.byref(h), 1 << 30, 16, ctypes.byref(o), 8, 1) == -7
     o.tridiag_reuse, o.real_data = 2, 1
     assert lib.expm_pfd_queue_create(ctypes.byref(h), 1 << 30, 16, ctypes.byref(o), 8, 1) == -7
+
+
+def test_band_validation_without_device():
+    """The banded route's plan rejects bad arguments before any device work."""
+    mod, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.expm_pfd_band_plan(None, 10, 1, 16, 1, None) == -3
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 10, 1, 15, 1, None) == -1
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 0, 1, 16, 1, None) == -2
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 10, -1, 16, 1, None) == -2
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 10, 64, 16, 1, None) == -2  # kd above EXPM_PFD_BAND_MAX_KD
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 10, 1, 16, 65, None) == -2
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), (1 << 24) + 1, 1, 16, 1, None) == -2
+    o = mod._Opts()
+    o.uplo = 3
+    assert lib.expm_pfd_band_plan(ctypes.byref(h), 10, 1, 16, 1, ctypes.byref(o)) == -7
+    assert lib.expm_pfd_band_apply(None, 1.0, None, 2, None, 10, 1, None, 10, None) == -3
+    assert lib.expm_pfd_band_destroy(None) == -3
+    text = open(HEADER).read()
+    assert int(re.search(r"#define EXPM_PFD_BAND_MAX_KD\s+(\d+)", text).group(1)) == 63
+
+
+@pytest.mark.parametrize("digits", [7, 16, 24, 34])
+def test_choose_degree_matches_oracle(digits):
+    """expm_pfd_choose_degree (host, from the library's binary128 residues) picks the
+    oracle's degree for tolerances away from the thresholds, with the same flag and
+    bound to a few ulps of the residue sums."""
+    from oracle import scalar
+    mod, lib = _lib()
+    d = ctypes.c_int()
+    b = ctypes.c_double()
+    for tol in (1e-3, 1e-5, 3e-7, 3e-9, 1e-11, 1e-14, 0.0):
+        rc = lib.expm_pfd_choose_degree(tol, digits, ctypes.byref(d), ctypes.byref(b))
+        want_d, want_b, ok = scalar.choose_degree(tol, digits)
+        assert (rc, d.value) == (0 if ok else 1, want_d), (digits, tol)
+        assert abs(b.value - want_b) <= 1e-9 * want_b
+    assert lib.expm_pfd_choose_degree(1e-8, 3, ctypes.byref(d), None) == -7
+    assert lib.expm_pfd_choose_degree(float("nan"), 16, ctypes.byref(d), None) == -7
+    assert lib.expm_pfd_choose_degree(1e-8, 16, None, None) == -3
+
