@@ -102,6 +102,20 @@ __device__ __forceinline__ double pivot_mag(double2 z) {
   return m != m ? INFINITY : m;
 }
 
+// maximum over the wave of a 64-bit integer, returned in every lane
+__device__ __forceinline__ long long wave_max_i64(long long x) {
+  auto step = [](long long v, long long o) { return o > v ? o : v; };
+  x = step(x, __double_as_longlong(dpp_move<0xB1, 0xF>(__longlong_as_double(x))));
+  x = step(x, __double_as_longlong(dpp_move<0x4E, 0xF>(__longlong_as_double(x))));
+  x = step(x, __double_as_longlong(dpp_move<0x141, 0xF>(__longlong_as_double(x))));
+  x = step(x, __double_as_longlong(dpp_move<0x140, 0xF>(__longlong_as_double(x))));
+  x = step(x, __double_as_longlong(dpp_move<0x142, 0xA>(__longlong_as_double(x))));
+  x = step(x, __double_as_longlong(dpp_move<0x143, 0xC>(__longlong_as_double(x))));
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return ((long long)hi << 32) | (unsigned int)lo;
+}
+
 // sum over the wave, valid in lane 63 and returned in every lane
 __device__ __forceinline__ double wave_sum_dpp(double x) {
   x += dpp_move<0xB1, 0xF>(x);
@@ -127,185 +141,236 @@ __global__ __launch_bounds__(256) void k_band_rows(BandDesc b, double2* __restri
     Vr[e] = rhs_at(b, (int)(e / b.m), (int)(e % b.m));
 }
 
-// A wave's stream over a device array read in chunks of 64 complex values (one
-// per lane), two chunks ahead of use, in rising (UP) or falling index order.
-// Values come out by readlane (an index shared by the wave) or by a lane shuffle
-// (an index per lane); every index asked for lies in the current chunk or the
-// next one.
-template <bool UP>
-struct ChunkStream {
-  const double2* p;
-  int64_t len, X;  // X: the current chunk
-  double2 c0, c1, c2;
-  __device__ __forceinline__ double2 ld(int64_t ci, int lane) const {
-    const int64_t f = ci * 64 + lane;
-    return (ci >= 0 && f < len) ? p[f] : czero<double2>();
-  }
-  __device__ __forceinline__ void init(const double2* p_, int64_t len_, int64_t first, int lane) {
-    constexpr int D = UP ? 1 : -1;
-    p = p_;
-    len = len_;
-    X = first >> 6;
-    c0 = ld(X, lane);
-    c1 = ld(X + D, lane);
-    c2 = ld(X + 2 * D, lane);
-  }
-  // make the chunk of index f (the lowest index still needed going up, the
-  // highest going down) the current one
-  __device__ __forceinline__ void reach(int64_t f, int lane) {
-    constexpr int D = UP ? 1 : -1;
-    const int64_t ci = f >> 6;
-    while (UP ? ci > X : ci < X) {
-      c0 = c1;
-      c1 = c2;
-      X += D;
-      c2 = ld(X + 2 * D, lane);
-    }
-  }
-  __device__ __forceinline__ double2 uni(int64_t f) const {
-    const int l = (int)(f & 63);
-    return (f >> 6) == X ? lane_bcast2(c0, l) : lane_bcast2(c1, l);
-  }
-  __device__ __forceinline__ double2 per(int64_t f) const {
-    const int l = (int)(f & 63);
-    double2 a, b;
-    a.x = __shfl(c0.x, l);
-    a.y = __shfl(c0.y, l);
-    b.x = __shfl(c1.x, l);
-    b.y = __shfl(c1.y, l);
-    return (f >> 6) == X ? a : b;
-  }
-};
-
-// ---- narrow bands: one wave per pole -----------------------------------------
-// U: row j of pole k at U + k*ustride + j*(2KD+1): [1/pivot, U(j, j+1), ..., U(j, j+2KD)]
-// Y: pole k's n x m solution, row-major (element (j, r) at Y + k*ystride + j*m + r)
-template <int KD>
-__global__ __launch_bounds__(64) void k_band_narrow(int n, int m, const double2* __restrict__ R,
-                                                    const double2* __restrict__ Vr, const double2* __restrict__ pole,
-                                                    double2* __restrict__ U, double2* __restrict__ Y,
-                                                    int64_t ustride, int64_t ystride) {
-  constexpr int W = 2 * KD + 1;
-  const int k = blockIdx.x, lane = threadIdx.x;
-  const bool act = lane < m;
-  const double2 th = pole[k];
-  double2* Uk = U + k * ustride;
-  double2* Yk = Y + k * ystride;
-  ChunkStream<true> rs, vs;  // rows of the matrix, rows of V
-  rs.init(R, (int64_t)n * W, 0, lane);
-  vs.init(Vr, (int64_t)n * m, 0, lane);
-  // row q of tA - cI + theta I at column q - KD + c
-  auto row_at = [&](int q, int c) {
-    double2 v = q < n ? rs.uni((int64_t)q * W + c) : czero<double2>();
-    if (c == KD && q < n) {
-      v.x += th.x;
-      v.y += th.y;
-    }
-    return v;
-  };
-  auto rhs = [&](int q) {
-    const double2 v = vs.per((int64_t)q * m + lane);
-    return (act && q < n) ? v : czero<double2>();
-  };
-  double2 w[KD + 1][W], bb[KD + 1];
-#pragma unroll
-  for (int i = 0; i <= KD; ++i) {
-    rs.reach((int64_t)min(i, n - 1) * W, lane);
-    vs.reach((int64_t)min(i, n - 1) * m, lane);
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      const int off = c - i + KD;  // column c of row i
-      w[i][c] = (off >= 0 && off < W) ? row_at(i, off) : czero<double2>();
-    }
-    bb[i] = rhs(i);
-  }
-  for (int j = 0; j < n; ++j) {
-    const int alive = min(KD + 1, n - j);  // rows of the window that hold matrix rows
-    int p = 0;
-    double best = pivot_mag(w[0][0]);
-#pragma unroll
-    for (int i = 1; i <= KD; ++i) {
-      const double mg = pivot_mag(w[i][0]);
-      if (i < alive && mg > best) {
-        best = mg;
-        p = i;
-      }
-    }
-#pragma unroll
-    for (int i = 1; i <= KD; ++i)
-      if (p == i) {
-#pragma unroll
-        for (int c = 0; c < W; ++c) {
-          const double2 x = w[0][c];
-          w[0][c] = w[i][c];
-          w[i][c] = x;
-        }
-        const double2 x = bb[0];
-        bb[0] = bb[i];
-        bb[i] = x;
-      }
-    const double2 rp = crecip(w[0][0]);
-#pragma unroll
-    for (int i = 1; i <= KD; ++i) {
-      const double2 l = cmul(w[i][0], rp);
-#pragma unroll
-      for (int c = 1; c < W; ++c) w[i][c] = cfms(w[i][c], l, w[0][c]);
-      bb[i] = cfms(bb[i], l, bb[0]);
-    }
-    if (lane == 0) {
-      Uk[(int64_t)j * W] = rp;
-#pragma unroll
-      for (int c = 1; c < W; ++c) Uk[(int64_t)j * W + c] = w[0][c];
-    }
-    if (act) Yk[(int64_t)j * m + lane] = bb[0];
-    // the window moves one row down and one column right; the new row is matrix
-    // row j + KD + 1 over columns j + 1 .. j + 1 + 2KD
-#pragma unroll
-    for (int i = 0; i < KD; ++i) {
-#pragma unroll
-      for (int c = 0; c + 1 < W; ++c) w[i][c] = w[i + 1][c + 1];
-      w[i][W - 1] = czero<double2>();
-      bb[i] = bb[i + 1];
-    }
-    const int q = j + KD + 1;
-    rs.reach((int64_t)min(q, n - 1) * W, lane);
-    vs.reach((int64_t)min(q, n - 1) * m, lane);
-#pragma unroll
-    for (int c = 0; c < W; ++c) w[KD][c] = row_at(q, c);
-    bb[KD] = rhs(q);
-  }
-  __syncthreads();  // U and Y rows written above, read back by other lanes below
-  ChunkStream<false> us, ys;
-  us.init(Uk, (int64_t)n * W, (int64_t)n * W - 1, lane);
-  ys.init(Yk, (int64_t)n * m, (int64_t)n * m - 1, lane);
-  double2 xs[2 * KD + 1];  // xs[c - 1] = x_{j + c}
-#pragma unroll
-  for (int c = 0; c < 2 * KD + 1; ++c) xs[c] = czero<double2>();
-  for (int j = n - 1; j >= 0; --j) {
-    us.reach((int64_t)j * W + W - 1, lane);
-    ys.reach((int64_t)j * m + m - 1, lane);
-    double2 s = ys.per((int64_t)j * m + lane);
-    if (!act) s = czero<double2>();
-#pragma unroll
-    for (int c = 1; c < W; ++c) s = cfms(s, us.uni((int64_t)j * W + c), xs[c - 1]);
-    const double2 x = cmul(us.uni((int64_t)j * W), s);
-#pragma unroll
-    for (int c = 2 * KD; c >= 1; --c) xs[c] = xs[c - 1];
-    xs[0] = x;
-    if (act) Yk[(int64_t)j * m + lane] = x;
-  }
-}
-
-// LDS-only wait and workgroup barrier: outstanding global loads (the next row)
-// and stores (rows of U and Y) stay in flight across it
+// LDS-only wait and workgroup barrier: global loads (the next block's inputs) and
+// stores (the previous block's outputs) stay in flight across it
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left at their maxima
   __builtin_amdgcn_s_barrier();
 }
 
+// ---- narrow bands: one wave per (pole, block of 16 right-hand sides) -----------
+// The chain touches only registers and LDS.  Every NB_B columns the wave moves
+// the next block's inputs (rows of R and of V, loaded a whole block earlier) into
+// LDS, writes the previous block's outputs (rows of U and Y) back, and issues the
+// loads of the block after; so every wait on memory covers operations issued a
+// block earlier.
+// U: row j at U + (k*chunks + chunk)*ustride + j*(2KD+1): [1/pivot, U(j, j+1), ...,
+// U(j, j+2KD)] (each block of right-hand sides keeps its own copy)
+// Y: pole k's n x m solution, row-major (element (j, r) at Y + k*ystride + j*m + r)
+constexpr int NB_B = 32;   // columns per block
+constexpr int NB_MC = 16;  // right-hand sides per wave
+template <int KD>
+__global__ __launch_bounds__(64) void k_band_narrow(int n, int m, const double2* __restrict__ R,
+                                                    const double2* __restrict__ Vr, const double2* __restrict__ pole,
+                                                    double2* __restrict__ U, double2* __restrict__ Y,
+                                                    int64_t ustride, int64_t ystride) {
+  constexpr int W = 2 * KD + 1, B = NB_B, MC = NB_MC;
+  constexpr int RCH = (B * W + 63) / 64;  // 64-value pieces of a block of R (or U) rows
+  constexpr int VCH = B * MC / 64;        // ... of a block of V (or Y) rows
+  __shared__ double2 sR[B * W], sV[B * MC], sU[B * W], sY[B * MC];
+  const int k = blockIdx.x, lane = threadIdx.x;
+  const int rc = blockIdx.y * MC, r = rc + lane;
+  const bool act = lane < MC && r < m;
+  const double2 th = pole[k];
+  double2* Uk = U + ((int64_t)k * gridDim.y + blockIdx.y) * ustride;
+  double2* Yk = Y + k * ystride;
+  const int nblk = (n + B - 1) / B;
+  double2 gR[RCH], gV[VCH];
+  // rows q0 .. q0+B-1 of R and of this wave's columns of a row-major n x m array
+  auto load_rows = [&](const double2* src, int64_t q0, int64_t ld_src) {
+#pragma unroll
+    for (int c = 0; c < RCH; ++c) {
+      const int f = c * 64 + lane;
+      const int64_t e = q0 * W + f;
+      gR[c] = (f < B * W && q0 + f / W < n) ? src[e] : czero<double2>();
+    }
+    (void)ld_src;
+  };
+  auto load_cols = [&](const double2* src, int64_t q0) {
+#pragma unroll
+    for (int c = 0; c < VCH; ++c) {
+      const int f = c * 64 + lane, i = f / MC, cc = f % MC;
+      const int64_t q = q0 + i;
+      gV[c] = (q < n && rc + cc < m) ? src[q * m + rc + cc] : czero<double2>();
+    }
+  };
+  auto stage = [&](double2* dR, double2* dV) {
+#pragma unroll
+    for (int c = 0; c < RCH; ++c)
+      if (c * 64 + lane < B * W) dR[c * 64 + lane] = gR[c];
+#pragma unroll
+    for (int c = 0; c < VCH; ++c) dV[c * 64 + lane] = gV[c];
+  };
+  // rows j0 .. j0+rows-1 of U (from sU, if given) and of this wave's columns of Y
+  auto flush = [&](const double2* srcU, const double2* srcY, int j0, int rows) {
+    if (srcU) {
+#pragma unroll
+      for (int c = 0; c < RCH; ++c) {
+        const int f = c * 64 + lane;
+        if (f < rows * W) Uk[(int64_t)j0 * W + f] = srcU[f];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < VCH; ++c) {
+      const int f = c * 64 + lane, i = f / MC, cc = f % MC;
+      if (i < rows && rc + cc < m) Yk[(int64_t)(j0 + i) * m + rc + cc] = srcY[f];
+    }
+  };
+
+  // ---- forward: elimination with partial pivoting, V transformed alongside ----
+  double2 w[KD + 1][W], bb[KD + 1];
+#pragma unroll
+  for (int i = 0; i <= KD; ++i) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      const int off = c - i + KD;  // column c of row i
+      double2 v = czero<double2>();
+      if (i < n && off >= 0 && off < W) {
+        v = R[(int64_t)i * W + off];
+        if (c == i) {
+          v.x += th.x;
+          v.y += th.y;
+        }
+      }
+      w[i][c] = v;
+    }
+    bb[i] = (act && i < n) ? Vr[(int64_t)i * m + r] : czero<double2>();
+  }
+  // block b inserts rows b*B + KD + 1 .. b*B + KD + B
+  load_rows(R, KD + 1, 0);
+  load_cols(Vr, KD + 1);
+  for (int b = 0; b < nblk; ++b) {
+    const int j0 = b * B;
+    stage(sR, sV);
+    if (b > 0) flush(sU, sY, j0 - B, B);
+    if (b + 1 < nblk) {
+      load_rows(R, (int64_t)j0 + B + KD + 1, 0);
+      load_cols(Vr, (int64_t)j0 + B + KD + 1);
+    }
+    const int jn = min(B, n - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int j = j0 + jj;
+      const bool qin = j + KD + 1 < n;
+      // the row inserted at the end of this step (read now, used last)
+      double2 nr[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) nr[c] = sR[jj * W + c];
+      const double2 nb = sV[jj * MC + (lane & (MC - 1))];
+      const int alive = min(KD + 1, n - j);  // window rows that hold matrix rows
+      int p = 0;
+      double best = pivot_mag(w[0][0]);
+#pragma unroll
+      for (int i = 1; i <= KD; ++i) {
+        const double mg = pivot_mag(w[i][0]);
+        if (i < alive && mg > best) {
+          best = mg;
+          p = i;
+        }
+      }
+#pragma unroll
+      for (int i = 1; i <= KD; ++i)
+        if (p == i) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            const double2 x = w[0][c];
+            w[0][c] = w[i][c];
+            w[i][c] = x;
+          }
+          const double2 x = bb[0];
+          bb[0] = bb[i];
+          bb[i] = x;
+        }
+      const double2 rp = crecip_fast(w[0][0]);
+#pragma unroll
+      for (int i = 1; i <= KD; ++i) {
+        const double2 l = cmul(w[i][0], rp);
+#pragma unroll
+        for (int c = 1; c < W; ++c) w[i][c] = cfms(w[i][c], l, w[0][c]);
+        bb[i] = cfms(bb[i], l, bb[0]);
+      }
+      if (lane < W) {  // row j of U: lane c writes entry c
+        double2 u = rp;
+#pragma unroll
+        for (int c = 1; c < W; ++c)
+          if (lane == c) u = w[0][c];
+        sU[jj * W + lane] = u;
+      }
+      if (lane < MC) sY[jj * MC + lane] = bb[0];
+      // the window moves one row down and one column right; the new row is matrix
+      // row j + KD + 1 over columns j + 1 .. j + 1 + 2KD (row jj of the block's R)
+#pragma unroll
+      for (int i = 0; i < KD; ++i) {
+#pragma unroll
+        for (int c = 0; c + 1 < W; ++c) w[i][c] = w[i + 1][c + 1];
+        w[i][W - 1] = czero<double2>();
+        bb[i] = bb[i + 1];
+      }
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double2 v = qin ? nr[c] : czero<double2>();
+        if (c == KD && qin) {
+          v.x += th.x;
+          v.y += th.y;
+        }
+        w[KD][c] = v;
+      }
+      bb[KD] = (qin && lane < MC) ? nb : czero<double2>();
+    }
+  }
+  flush(sU, sY, (nblk - 1) * B, n - (nblk - 1) * B);
+  __syncthreads();  // the rows written above are read back below (other lanes)
+
+  // ---- back substitution, blocks from the last to the first --------------------
+  // x_j = (1/u_jj)(y_j - sum_c u_{j,j+c} x_{j+c}), in place in Y
+  double2 xs[2 * KD + 1];  // xs[c - 1] = x_{j + c}
+#pragma unroll
+  for (int c = 0; c < 2 * KD + 1; ++c) xs[c] = czero<double2>();
+  load_rows(Uk, (int64_t)(nblk - 1) * B, 0);
+  load_cols(Yk, (int64_t)(nblk - 1) * B);
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * B;
+    stage(sR, sV);  // U rows and y of block b
+    if (b + 1 < nblk) flush(nullptr, sY, j0 + B, min(B, n - j0 - B));
+    if (b > 0) {
+      load_rows(Uk, (int64_t)j0 - B, 0);
+      load_cols(Yk, (int64_t)j0 - B);
+    }
+    const int jn = min(B, n - j0);
+    // each step's row of U and y are read one step ahead
+    double2 un[W], yn;
+#pragma unroll
+    for (int c = 0; c < W; ++c) un[c] = sR[(jn - 1) * W + c];
+    yn = sV[(jn - 1) * MC + (lane & (MC - 1))];
+    for (int jj = jn - 1; jj >= 0; --jj) {
+      double2 u[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) u[c] = un[c];
+      double2 s = lane < MC ? yn : czero<double2>();
+      if (jj > 0) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) un[c] = sR[(jj - 1) * W + c];
+        yn = sV[(jj - 1) * MC + (lane & (MC - 1))];
+      }
+#pragma unroll
+      for (int c = 1; c < W; ++c) s = cfms(s, u[c], xs[c - 1]);
+      const double2 x = cmul(u[0], s);
+#pragma unroll
+      for (int c = 2 * KD; c >= 1; --c) xs[c] = xs[c - 1];
+      xs[0] = x;
+      if (lane < MC) sY[jj * MC + lane] = x;
+    }
+  }
+  flush(nullptr, sY, 0, min(B, n));
+}
+
 // ---- wide bands: one workgroup per (pole, block of right-hand sides) ----------
-// Same U and Y layouts as the narrow kernel (W = 2 kw + 1); only the first block
-// of right-hand sides writes U.
+// Same U and Y layouts as the narrow kernel (W = 2 kw + 1; one U copy, written by
+// the first block of right-hand sides).  Block-staged like the narrow kernel: the
+// rows inserted during a block of WB_B columns (R and V) sit in LDS, and the rows
+// of U and Y it produces collect in LDS until the block boundary.
+constexpr int WB_B = 16;                                   // columns per block
+constexpr int WB_ROW = 2 * EXPM_PFD_BAND_MAX_KD + 1 + BAND_MC;  // largest staged row
+constexpr int WB_G = 5;  // staging values per thread (16 rows x 143 over >= 448 threads)
 template <int CPW>
 __global__ __launch_bounds__(512) void k_band_factor(int n, int kw, int m, const double2* __restrict__ R,
                                                      const double2* __restrict__ Vr,
@@ -313,27 +378,57 @@ __global__ __launch_bounds__(512) void k_band_factor(int n, int kw, int m, const
                                                      double2* __restrict__ Y, int64_t ustride, int64_t ystride) {
   __shared__ double2 lbuf[2][64];
   __shared__ int pbuf[2];
-  const int k = blockIdx.x, lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int NW = blockDim.x >> 6;
+  __shared__ double2 sIn[WB_B * WB_ROW], sOut[WB_B * WB_ROW], sRinv[2][WB_B];
+  const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int NW = blockDim.x >> 6, NT = blockDim.x;
   const int W = 2 * kw + 1;
-  const int r0 = blockIdx.y * BAND_MC;
-  const int slots = W + min(BAND_MC, m - r0);
+  const int r0 = blockIdx.y * BAND_MC, mc = min(BAND_MC, m - r0);
+  const int slots = W + mc, RW = W + BAND_MC;  // RW: staged row length
   const bool writeU = blockIdx.y == 0;
   const double2 th = pole[k];
   double2* Uk = U + k * ustride;
   double2* Yk = Y + k * ystride;
-  // row q of tA - cI + theta I at column q - kw + c
-  auto row_at = [&](int q, int c) {
-    double2 v = q < n ? R[(int64_t)q * W + c] : czero<double2>();
-    if (c == kw && q < n) {
-      v.x += th.x;
-      v.y += th.y;
+  const int nblk = (n + WB_B - 1) / WB_B;
+
+  double2 g[WB_G];
+  // staged row i of block b: matrix row q = b*B + kw + 1 + i: R entries, then V
+  auto load_in = [&](int b) {
+#pragma unroll
+    for (int c = 0; c < WB_G; ++c) {
+      const int f = tid + c * NT, i = f / RW, e = f % RW;
+      const int64_t q = (int64_t)b * WB_B + kw + 1 + i;
+      g[c] = czero<double2>();
+      if (f < WB_B * RW && q < n) {
+        if (e < W) g[c] = R[q * W + e];
+        else if (e - W < mc) g[c] = Vr[q * m + r0 + e - W];
+      }
     }
-    return v;
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int c = 0; c < WB_G; ++c) {
+      const int f = tid + c * NT;
+      if (f < WB_B * RW) sIn[f] = g[c];
+    }
+  };
+  auto flush = [&](int b) {  // rows of block b from sOut and sRinv
+    const int j0 = b * WB_B, rows = min(WB_B, n - j0);
+#pragma unroll
+    for (int c = 0; c < WB_G; ++c) {
+      const int f = tid + c * NT, i = f / RW, e = f % RW;
+      if (f < WB_B * RW && i < rows) {
+        const int64_t j = j0 + i;
+        if (e < W) {
+          if (writeU) Uk[j * W + e] = e == 0 ? sRinv[b & 1][i] : sOut[f];
+        } else if (e - W < mc) {
+          Yk[j * m + r0 + e - W] = sOut[f];
+        }
+      }
+    }
   };
 
-  double2 a[CPW], pf[CPW];
+  double2 a[CPW];
   bool alive = lane <= kw && lane < n;  // active-row slot `lane` holds matrix row `lane`
   // window at column 0: slot s holds column s; right-hand side slots W + r
 #pragma unroll
@@ -342,142 +437,170 @@ __global__ __launch_bounds__(512) void k_band_factor(int n, int kw, int m, const
     a[i] = czero<double2>();
     if (alive && s < W) {
       const int off = s - lane + kw;
-      if (off >= 0 && off < W) a[i] = row_at(lane, off);
+      if (off >= 0 && off < W) {
+        a[i] = R[(int64_t)lane * W + off];
+        if (off == kw) {
+          a[i].x += th.x;
+          a[i].y += th.y;
+        }
+      }
     } else if (alive && s < slots) {
       a[i] = Vr[(int64_t)lane * m + r0 + s - W];
     }
   }
-  // the row inserted at the end of step j is row q = j + kw + 1, over the columns
-  // of step j + 1: slot s then holds column (j+1) + ((s - (j+1)) mod W), which is
-  // entry (s - (j+1)) mod W of the row
-  auto prefetch = [&](int j) {
-    const int q = j + kw + 1;
-    const int s1 = (j + 1) % W;
-#pragma unroll
-    for (int i = 0; i < CPW; ++i) {
-      const int s = wv + i * NW;
-      pf[i] = czero<double2>();
-      if (q < n && s < W) pf[i] = row_at(q, s >= s1 ? s - s1 : s - s1 + W);
-      else if (q < n && s < slots) pf[i] = Vr[(int64_t)q * m + r0 + s - W];
-    }
-  };
   // pivot and multipliers of column j, held in z (run by the wave holding it)
   auto pivot = [&](double2 z, int nb, int j) {
-    double mg = alive ? pivot_mag(z) : -1.0;
-    const double mx = wave_max(mg);
-    int pl = wave_min(mg == mx ? lane : 64);
-    if (pl >= 64) pl = 0;  // (mx is one of the lanes' values)
+    // one reduction over keys: the magnitude's bits (a non-negative double orders
+    // as an integer) with the low 6 bits replaced by 63 - lane, so the largest key
+    // is a largest magnitude (to 2^-46 relative) at the lowest such lane
+    long long key = -1;
+    if (alive) key = (__double_as_longlong(pivot_mag(z)) & ~63ll) | (63 - lane);
+    const int pl = 63 - (int)(wave_max_i64(key) & 63);
     const double2 piv = lane_bcast2(z, pl);
-    const double2 rp = crecip(piv);
+    const double2 rp = crecip_fast(piv);
     lbuf[nb][lane] = (alive && lane != pl) ? cmul(z, rp) : czero<double2>();
     if (lane == 0) {
       pbuf[nb] = pl;
-      if (writeU) Uk[(int64_t)j * W] = rp;
+      sRinv[(j / WB_B) & 1][j % WB_B] = rp;
     }
   };
-  prefetch(0);
 #pragma unroll
   for (int i = 0; i < CPW; ++i)
     if (wv + i * NW == 0) pivot(a[i], 0, 0);
-  lds_barrier();
-  for (int j = 0; j < n; ++j) {
-    const int buf = j & 1;
-    const int p = __builtin_amdgcn_readfirstlane(pbuf[buf]);
-    const double2 l = lbuf[buf][lane];
-    const bool qin = j + kw + 1 < n;
-    const int sj = j % W;  // slot of column j: it leaves, and takes column j + W
+  load_in(0);
+  for (int b = 0; b < nblk; ++b) {
+    lds_barrier();  // the last block's reads of sIn and writes of sOut are done
+    stage();
+    if (b > 0) flush(b - 1);
+    if (b + 1 < nblk) load_in(b + 1);
+    lds_barrier();
+    const int j0 = b * WB_B, jn = min(WB_B, n - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int j = j0 + jj;
+      const int buf = j & 1;
+      const int p = __builtin_amdgcn_readfirstlane(pbuf[buf]);
+      const double2 l = lbuf[buf][lane];
+      const bool qin = j + kw + 1 < n;
+      const int sj = j % W;        // slot of column j: it leaves, and takes column j + W
+      const int s1 = (j + 1) % W;  // slot of column j + 1
+      const double2* in = sIn + jj * RW;
+      double2* out = sOut + jj * RW;
 #pragma unroll
-    for (int i = 0; i < CPW; ++i) {
-      const int s = wv + i * NW;
-      if (s >= slots) continue;
-      const double2 pv = lane_bcast2(a[i], p);
-      if (s < W) {
-        const int cofs = s >= sj ? s - sj : s - sj + W;  // column - j
-        if (lane == p) {
-          if (writeU && cofs > 0) Uk[(int64_t)j * W + cofs] = a[i];
-          a[i] = pf[i];
+      for (int i = 0; i < CPW; ++i) {
+        const int s = wv + i * NW;
+        if (s >= slots) continue;
+        const double2 pv = lane_bcast2(a[i], p);
+        if (s < W) {
+          const int cofs = s >= sj ? s - sj : s - sj + W;  // column - j
+          if (lane == p) {
+            if (cofs > 0) out[cofs] = a[i];
+            // the new row's entry at this slot's column in step j + 1
+            const int e1 = s >= s1 ? s - s1 : s - s1 + W;
+            a[i] = qin ? in[e1] : czero<double2>();
+            if (qin && e1 == kw) {
+              a[i].x += th.x;
+              a[i].y += th.y;
+            }
+          } else {
+            // column j + W is zero in the remaining rows (they end before it)
+            a[i] = cofs == 0 ? czero<double2>() : cfms(a[i], l, pv);
+          }
         } else {
-          // column j + W is zero in the remaining rows (they end before it)
-          a[i] = cofs == 0 ? czero<double2>() : cfms(a[i], l, pv);
-        }
-      } else {
-        if (lane == p) {
-          Yk[(int64_t)j * m + r0 + s - W] = a[i];
-          a[i] = pf[i];
-        } else {
-          a[i] = cfms(a[i], l, pv);
+          if (lane == p) {
+            out[s] = a[i];
+            a[i] = qin ? in[s] : czero<double2>();
+          } else {
+            a[i] = cfms(a[i], l, pv);
+          }
         }
       }
-    }
-    if (lane == p) alive = qin;
-    if (j + 1 < n) {
-      prefetch(j + 1);
-      const int s1 = (j + 1) % W;
+      if (lane == p) alive = qin;
+      if (j + 1 < n) {
 #pragma unroll
-      for (int i = 0; i < CPW; ++i)
-        if (wv + i * NW == s1) pivot(a[i], buf ^ 1, j + 1);
+        for (int i = 0; i < CPW; ++i)
+          if (wv + i * NW == s1) pivot(a[i], buf ^ 1, j + 1);
+      }
+      lds_barrier();
     }
-    lds_barrier();
   }
+  flush(nblk - 1);
 }
 
 // back substitution x_j = (1/u_jj) (y_j - sum_{c=1..2kw} u_{j,j+c} x_{j+c}), in place
-// in Y; one wave per right-hand side.  Each lane's two coefficients, the pivot's
-// reciprocal and y_j are loaded BACK_AHEAD rows ahead (a register queue, the
-// loop unrolled by its length).
-constexpr int BACK_AHEAD = 4;
+// in Y; one wave per right-hand side (at least four waves, for the staging).  The
+// ring holds x_i at position i mod 128 (positions lane and lane + 64); blocks of
+// WB_B rows of U and y are staged in LDS a block ahead, and the block's x rows are
+// written back at the next boundary.
+constexpr int BK_G = 8;  // staging values per thread (16 rows x 127 over >= 256 threads)
 __global__ __launch_bounds__(1024) void k_band_back(int n, int kw, int m, const double2* __restrict__ U,
                                                     double2* __restrict__ Y, int64_t ustride, int64_t ystride) {
-  const int k = blockIdx.x, lane = threadIdx.x & 63;
-  const int r = blockIdx.y * BAND_MC + (threadIdx.x >> 6);
-  if (r >= m) return;
+  __shared__ double2 sU[WB_B * (2 * EXPM_PFD_BAND_MAX_KD + 1)], sYin[BAND_MC][WB_B], sX[BAND_MC][WB_B];
+  const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, NT = blockDim.x;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r0 = blockIdx.y * BAND_MC, mc = min(BAND_MC, m - r0);
+  const bool act = wv < mc;
   const int W = 2 * kw + 1;
   const double2* Uk = U + k * ustride;
   double2* Yk = Y + k * ystride;
-  // ring: x_i at position i mod 128, positions lane and lane + 64
+  const int nblk = (n + WB_B - 1) / WB_B;
+  double2 g[BK_G], gy;
+  auto load_in = [&](int b) {
+    const int j0 = b * WB_B, rows = min(WB_B, n - j0);
+#pragma unroll
+    for (int c = 0; c < BK_G; ++c) {
+      const int f = tid + c * NT;
+      g[c] = f < rows * W ? Uk[(int64_t)j0 * W + f] : czero<double2>();
+    }
+    const int i = tid / BAND_MC, cc = tid % BAND_MC;
+    gy = (i < rows && cc < mc) ? Yk[(int64_t)(j0 + i) * m + r0 + cc] : czero<double2>();
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int c = 0; c < BK_G; ++c) {
+      const int f = tid + c * NT;
+      if (f < WB_B * W) sU[f] = g[c];
+    }
+    const int i = tid / BAND_MC, cc = tid % BAND_MC;
+    if (i < WB_B) sYin[cc][i] = gy;
+  };
+  auto flush = [&](int b) {
+    const int j0 = b * WB_B, rows = min(WB_B, n - j0);
+    const int i = tid / BAND_MC, cc = tid % BAND_MC;
+    if (i < rows && cc < mc) Yk[(int64_t)(j0 + i) * m + r0 + cc] = sX[cc][i];
+  };
   double2 x0 = czero<double2>(), x1 = czero<double2>();
-  struct Row {
-    double2 u0, u1, rp, y;
-  };
-  auto load = [&](int j) {
-    Row q;
-    q.u0 = q.u1 = q.rp = q.y = czero<double2>();
-    if (j >= 0) {
-      const int c0 = (lane - j) & 127, c1 = (lane + 64 - j) & 127;
-      if (c0 >= 1 && c0 < W && j + c0 < n) q.u0 = Uk[(int64_t)j * W + c0];
-      if (c1 >= 1 && c1 < W && j + c1 < n) q.u1 = Uk[(int64_t)j * W + c1];
-      q.rp = Uk[(int64_t)j * W];
-      q.y = Yk[(int64_t)j * m + r];
-    }
-    return q;
-  };
-  auto step = [&](int j, const Row& q) {
-    double2 t = cmul(q.u0, x0);
-    t.x += q.u1.x * x1.x - q.u1.y * x1.y;
-    t.y += q.u1.x * x1.y + q.u1.y * x1.x;
-    double2 s;
-    s.x = q.y.x - wave_sum_dpp(t.x);
-    s.y = q.y.y - wave_sum_dpp(t.y);
-    const double2 x = cmul(q.rp, s);
-    if ((j & 63) == lane) {
-      if (j & 64) x1 = x;
-      else x0 = x;
-    }
-    if (lane == 0) Yk[(int64_t)j * m + r] = x;
-  };
-  Row qu[BACK_AHEAD];
-#pragma unroll
-  for (int i = 0; i < BACK_AHEAD; ++i) qu[i] = load(n - 1 - i);
-  for (int j0 = n - 1; j0 >= 0; j0 -= BACK_AHEAD) {
-#pragma unroll
-    for (int i = 0; i < BACK_AHEAD; ++i) {
-      const int j = j0 - i;
-      if (j >= 0) {
-        step(j, qu[i]);
-        qu[i] = load(j - BACK_AHEAD);
+  load_in(nblk - 1);
+  for (int b = nblk - 1; b >= 0; --b) {
+    lds_barrier();
+    stage();
+    if (b + 1 < nblk) flush(b + 1);
+    if (b > 0) load_in(b - 1);
+    lds_barrier();
+    const int j0 = b * WB_B, jn = min(WB_B, n - j0);
+    if (act) {
+      for (int jj = jn - 1; jj >= 0; --jj) {
+        const int j = j0 + jj;
+        const int c0 = (lane - j) & 127, c1 = (lane + 64 - j) & 127;
+        const double2 u0 = (c0 >= 1 && c0 < W && j + c0 < n) ? sU[jj * W + c0] : czero<double2>();
+        const double2 u1 = (c1 >= 1 && c1 < W && j + c1 < n) ? sU[jj * W + c1] : czero<double2>();
+        double2 t = cmul(u0, x0);
+        t.x += u1.x * x1.x - u1.y * x1.y;
+        t.y += u1.x * x1.y + u1.y * x1.x;
+        const double2 y = sYin[wv][jj];
+        double2 s;
+        s.x = y.x - wave_sum_dpp(t.x);
+        s.y = y.y - wave_sum_dpp(t.y);
+        const double2 x = cmul(sU[jj * W], s);
+        if ((j & 63) == lane) {
+          if (j & 64) x1 = x;
+          else x0 = x;
+        }
+        if (lane == 0) sX[wv][jj] = x;
       }
     }
   }
+  lds_barrier();
+  flush(0);
 }
 
 // X(:, r) = sum_k w_k Y_k(:, r) over the S solves in order (real: 2 Re(...))
@@ -563,11 +686,13 @@ extern "C" int expm_pfd_band_plan(expm_pfd_band_t* out, int64_t n, int64_t kd, i
     }
   }
   const int64_t W = 2 * p->kw + 1;
+  // the one-wave kernel keeps a copy of U per block of 16 right-hand sides
+  const int64_t ucopies = p->kw <= BAND_NARROW_KD ? (m_max + NB_MC - 1) / NB_MC : 1;
   p->ustride = n * W;
   p->ystride = n * m_max;
   bool ok = hipMalloc((void**)&p->pole, p->S * sizeof(double2)) == hipSuccess &&
             hipMalloc((void**)&p->w, p->S * sizeof(double2)) == hipSuccess &&
-            hipMalloc((void**)&p->U, (size_t)p->S * p->ustride * sizeof(double2)) == hipSuccess &&
+            hipMalloc((void**)&p->U, (size_t)p->S * ucopies * p->ustride * sizeof(double2)) == hipSuccess &&
             hipMalloc((void**)&p->Y, (size_t)p->S * p->ystride * sizeof(double2)) == hipSuccess &&
             hipMalloc((void**)&p->R, (size_t)n * W * sizeof(double2)) == hipSuccess &&
             hipMalloc((void**)&p->Vr, (size_t)n * m_max * sizeof(double2)) == hipSuccess;
@@ -614,7 +739,7 @@ extern "C" int expm_pfd_band_apply(expm_pfd_band_t p, double t, const void* AB, 
   bd.upper = p->upper;
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_band_rows, dim3(grid_for(p->n * (2 * p->kw + 1))), dim3(256), 0, st, bd, p->R, p->Vr);
-  const dim3 g1((unsigned)p->S);
+  const dim3 g1((unsigned)p->S, (unsigned)((m + NB_MC - 1) / NB_MC));
   const int n = bd.n, mm = bd.m;
   if (p->kw <= BAND_NARROW_KD) {
 #define EXPM_BAND_NARROW(KD) \
@@ -632,7 +757,10 @@ extern "C" int expm_pfd_band_apply(expm_pfd_band_t p, double t, const void* AB, 
     const int slots = (int)(2 * p->kw + 1 + std::min<int64_t>(BAND_MC, m));
     // fewest slots per wave that keep the workgroup within 8 waves
     const int cpw = slots <= 16 ? 2 : slots <= 32 ? 4 : slots <= 64 ? 8 : slots <= 96 ? 12 : 18;
-    const int nw = (slots + cpw - 1) / cpw;
+    // enough waves for the slots, and for staging a block of rows (WB_G values per thread)
+    const int stage_w = (int)((WB_B * (2 * p->kw + 1 + BAND_MC) + 64 * WB_G - 1) / (64 * WB_G));
+    const int nw = std::max((slots + cpw - 1) / cpw, stage_w);
+    if (nw > 8) return EXPM_PFD_ERR_HIP;  // (cannot happen: kw <= 63)
     const dim3 grid((unsigned)p->S, (unsigned)chunks);
     switch (cpw) {
       case 2: launch_factor<2>(grid, nw, st, bd, p); break;
@@ -641,7 +769,8 @@ extern "C" int expm_pfd_band_apply(expm_pfd_band_t p, double t, const void* AB, 
       case 12: launch_factor<12>(grid, nw, st, bd, p); break;
       default: launch_factor<18>(grid, nw, st, bd, p); break;
     }
-    const int waves = (int)std::min<int64_t>(BAND_MC, m);
+    // one wave per right-hand side, at least four for the staging
+    const int waves = (int)std::max<int64_t>(4, std::min<int64_t>(BAND_MC, m));
     hipLaunchKernelGGL(k_band_back, grid, dim3(64 * waves), 0, st, n, bd.kw, mm, p->U, p->Y, p->ustride,
                        p->ystride);
   }
