@@ -318,13 +318,14 @@ def serving_cpu_baseline(reqs, specs, budget_s=20.0):
                                                                        a, b, len(reqs), total)}
 
 
-def serving_section(requests, qps, check, sat_requests=1000, budget_gb=64):
+def serving_section(requests, qps, check, sat_requests=2000, budget_gb=160):
     """The serving workload: a Poisson trace of `requests` exp(t_i A_i) v_i requests
     (n log-uniform in [64, 4096], spectrum U[-200, 0], one vector, t U[0.1, 1], 20%
-    reuse of an earlier matrix with a new t, degree 16).  First a closed-loop
-    saturation run of the FP64 path (the first `sat_requests` requests all submitted
-    at once) gives its capacity C64; the identical trace is then replayed at
-    QPS = 0.8 C64 (or `qps` if given) on both precision paths.  A stratified sample
+    reuse of an earlier matrix with a new t, degree 16), in an HBM budget of
+    `budget_gb` of the device's 288 GB.  First a saturation run of the FP64 path
+    (the first `sat_requests` requests all due at time 0, prepared and submitted by
+    the same replay loop as fast as it goes) gives its capacity C64; the trace is
+    then replayed at QPS = 0.8 C64 (or `qps` if given) on both precision paths.  A stratified sample
     of 100 requests (ten per order decile) is checked against the oracle with the
     eigenpairs the matrices are built from."""
     from paper_2306_16778_amd import serving, workloads
@@ -337,8 +338,10 @@ def serving_section(requests, qps, check, sat_requests=1000, budget_gb=64):
     reqs1, specs = workloads.config5_requests(requests, 1.0)
     sat_requests = min(sat_requests, requests)
     if qps is None:
-        st, _, wall, _ = serving.replay(sat_requests, 1.0, "fp64", budget_bytes=budget, at_once=True,
-                                        reqs=reqs1, specs=specs, progress_s=progress)
+        # arrival times 1 s apart are all past due at once when every request arrives at 0
+        sat = [workloads.Request(0.0, r.matrix_id, r.n, r.t, r.v, r.reuse) for r in reqs1[:sat_requests]]
+        st, _, wall, _ = serving.replay(sat_requests, 1.0, "fp64", budget_bytes=budget, reqs=sat, specs=specs,
+                                        progress_s=progress)
         assert st["failed"] == 0, st
         c64 = st["solves_per_s"]
         out["fp64_saturation"] = {"requests": sat_requests, "solves_per_s": c64, "p50_ms": st["p50_ms"],
@@ -426,6 +429,56 @@ def tridiag_section(ep, torch, prob, Y, check, reps=10):
            "break_even_t_values_vs_lu_mixed": None}
     if Y is not None:
         out["rel_err_vs_oracle_t1"] = check.rel_fro(Xt.cpu().numpy(), Y)
+    return out
+
+
+def band_section(ep, torch, check, reps=3):
+    """The banded route on the paper's Laplacian workloads (Sec. 5.4): exp(tB)v for
+    the 1D finite-difference Laplacian B and exp(tC)v for the 2D one C, v of norm 1,
+    at the paper's orders (about 10^3, degree 32, t = 1, the paper's setting) and
+    at GPU scale (B of order 10^6 with a heat-equation time step; C on the 63 x 63
+    grid, the widest band taken).
+    Errors against the oracle's sine-transform closed form; the paper reports
+    absolute errors for these matrices.  ns_per_column: time per column of the
+    poles' elimination chains (forward and back substitution), which bounds the
+    route."""
+    import numpy as np
+
+    from paper_2306_16778_amd import workloads
+
+    # (name, points per axis, degree, columns, t): the paper's orders at t = 1; at
+    # GPU scale t puts the spectrum of tB in [-400, 0] (a heat-equation time step:
+    # at t = 1 an order of 10^6 makes the shifted matrices' condition about 10^12
+    # and no FP64 evaluation of the partial fractions keeps a digit of the result)
+    rows = [("laplacian_1d", 1000, 32, 1, 1.0), ("laplacian_2d", 32, 32, 1, 1.0),
+            ("laplacian_1d", 1_000_000, 16, 1, 100.0 / 1_000_001 ** 2), ("laplacian_2d", 63, 32, 1, 1.0)]
+    out = {"degree_for_1e-10_fp64": ep.expm_pfd_choose_degree(1e-10, 16)[0]}
+    for name, s, d, m, t in rows:
+        AB, kd = workloads.laplacian_1d_band(s) if name == "laplacian_1d" else workloads.laplacian_2d_band(s)
+        n = AB.shape[1]
+        rng = np.random.default_rng([20230629, 9, s])
+        v = workloads.complex_gaussian(rng, n, m)
+        v /= np.linalg.norm(v)
+        ABd = torch.from_numpy(np.asfortranarray(AB)).cuda()
+        vd = torch.from_numpy(np.asfortranarray(v)).cuda()
+        plan = ep.expm_pfd_band_plan(n, kd, d, m)
+        X = ep.expm_pfd_band_apply(plan, t, ABd, vd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ep.expm_pfd_band_apply(plan, t, ABd, vd, X=X)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res = {"n": n, "kd": kd, "degree": d, "m": m, "t": t, "ms_per_apply": ms, "solves_per_s": 1e3 / ms,
+               "ns_per_column": ms * 1e6 / n}
+        if check is not None:
+            Y = check.expm_R_laplacian(s, 1 if name == "laplacian_1d" else 2, v, t, d)
+            Xh = X.cpu().numpy()
+            res["abs_err_vs_oracle"] = float(np.linalg.norm(Xh - Y))
+            res["rel_err_vs_oracle"] = check.rel_fro(Xh, Y)
+        out[f"{name}_n{n}_d{d}"] = res
+        del plan, X, ABd, vd
+        torch.cuda.empty_cache()
     return out
 
 
@@ -517,6 +570,7 @@ def main():
                     help="arrival rate of the serving replay (default: 0.8 x the FP64 path's measured saturation)")
     ap.add_argument("--no-config3", action="store_true")
     ap.add_argument("--no-tridiag", action="store_true")
+    ap.add_argument("--no-band", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64", help="precision paths to time (mixed first: the reported value)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed, autotuned variant of the main paths")
@@ -591,6 +645,11 @@ def main():
         from oracle import matrix as c3check
         config3 = config3_section(ep, torch, None if args.no_cpu_baseline else c3check)
         print("[bench] config-3 precision section done", file=sys.stderr, flush=True)
+    band = None
+    if not args.no_band:
+        from oracle import matrix as bcheck
+        band = band_section(ep, torch, None if args.no_cpu_baseline else bcheck)
+        print("[bench] banded route done", file=sys.stderr, flush=True)
     served = None
     if args.serving_requests > 0:
         check = None
@@ -638,6 +697,7 @@ def main():
         "batched": batched,
         "precision_n4096": config3,
         "tridiagonal_route": tri,
+        "banded_route": band,
         "serving": served,
     }
     print(json.dumps(out), flush=True)

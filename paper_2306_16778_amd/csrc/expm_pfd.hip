@@ -1746,7 +1746,7 @@ struct expm_pfd_queue_s {
   // 2 of each other in LU work (hi^3 <= 2 lo^3), or when every order is at
   // most SMALL_PAD, where a pass is bound by its launch sequence rather than
   // by its arithmetic.
-  static constexpr int64_t SMALL_PAD = 512;
+  static constexpr int64_t SMALL_PAD = 256;
   static bool orders_compatible(int64_t lo, int64_t hi) { return hi <= SMALL_PAD || hi * hi * hi <= 2 * lo * lo * lo; }
 
   size_t plan_bytes(int64_t npad, int Gcap, int prec) const {

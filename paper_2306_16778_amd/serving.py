@@ -144,4 +144,8 @@ def replay(count: int, qps: float, precision: str = "mixed", degree: int = 16, n
     stats = ep.expm_pfd_queue_stats_get(q)
     out = [(r, r.v, r.t, X.cpu().numpy()) for r, X in kept]
     ep.expm_pfd_queue_destroy(q)
+    # hand torch's cached blocks (assembled matrices, vectors) back to the device
+    # so that a later queue's stream-ordered pool finds the memory
+    del window, resident
+    torch.cuda.empty_cache()
     return stats, out, wall, late

@@ -215,10 +215,14 @@ def config5_eigenpairs(spec):
 
 
 def config5_matrix_device(spec, device="cuda"):
-    """The config-5 matrix of ``spec`` assembled on the GPU with torch (same seeded
-    draws as ``config5_matrix``: spectrum uniform in [-200, 0], three Householder
-    reflections and a phase diagonal).  Rounding differs from the CPU assembly,
-    so checks must copy these bytes back rather than rebuild them on the host."""
+    """The config-5 matrix of ``spec`` assembled on the GPU with torch, from the same
+    seeded draws as ``config5_matrix`` (spectrum uniform in [-200, 0], three
+    Householder reflections and a phase diagonal), in two device passes: with the
+    reflections in compact WY form H_1 H_2 H_3 = I - V T V^H (T from the 3 x 3 inner
+    products, LAPACK's forward accumulation), U diag(lam) U^H is diag(lam) plus a
+    rank-6 product P Q^H whose factors take O(n) host work.  Rounding differs from
+    the CPU assembly and the result is Hermitian to rounding (the library reads
+    one triangle), so checks must copy these bytes back rather than rebuild them."""
     import torch
 
     n, idx = spec
@@ -226,17 +230,23 @@ def config5_matrix_device(spec, device="cuda"):
     lam = r.uniform(-200.0, 0.0, n)
     vs = [complex_gaussian(r, n) for _ in range(3)]
     phase = np.exp(2j * np.pi * r.random(n))
-    # one pinned staging array and one asynchronous copy for all the draws
-    host = torch.from_numpy(np.stack([lam.astype(np.complex128)] + [v / np.linalg.norm(v) for v in vs] + [phase]))
+    V = np.stack([v / np.linalg.norm(v) for v in vs], axis=1)
+    G = V.conj().T @ V
+    T = np.zeros((3, 3), dtype=np.complex128)
+    for j in range(3):  # tau = 2 for unit reflectors
+        T[:j, j] = -2.0 * (T[:j, :j] @ G[:j, j])
+        T[j, j] = 2.0
+    LV = lam[:, None] * V
+    M = T @ (V.conj().T @ LV) @ T.conj().T
+    # U L U^H = L - V T (LV)^H - (LV) T^H V^H + V M V^H = L + P Q^H, then D (.) D^H
+    P = phase[:, None] * np.concatenate([V, LV], axis=1)
+    Q = phase[:, None] * np.concatenate([V @ M.conj().T - LV @ T.conj().T, -(V @ T)], axis=1)
+    host = torch.from_numpy(np.concatenate([P, np.ascontiguousarray(Q.conj().T).T, lam[:, None] + 0j], axis=1))
     draws = host.pin_memory().to(device, non_blocking=True) if str(device).startswith("cuda") else host
-    X = torch.diag(draws[0])
-    for k in (3, 2, 1):
-        v = draws[k]
-        X = X - 2.0 * torch.outer(v, v.conj() @ X)
-        X = X - 2.0 * torch.outer(X @ v, v.conj())
-    ph = draws[4]
-    X = ph[:, None] * X * ph.conj()[None, :]
-    return 0.5 * (X + X.conj().T)
+    Pd, Qhd = draws[:, :6], draws[:, 6:12].T
+    A = Pd @ Qhd.contiguous()
+    A.diagonal().add_(draws[:, 12])
+    return A
 
 
 # --------------------------------------------------------------------------
