@@ -71,7 +71,11 @@ q factorial_q(int d) {
 // Aberth-Ehrlich iteration on exp_d; returns false if it fails to converge.
 bool roots_expd(int d, std::vector<cq>& z) {
   z.resize(d);
-  const double r0 = std::exp(std::lgamma(d + 1.0) / d);
+  // (d!)^(1/d) from a sum of logarithms: lgamma writes the global signgam, and
+  // plans are created from several threads at once
+  double logfact = 0.0;
+  for (int k = 2; k <= d; ++k) logfact += std::log((double)k);
+  const double r0 = std::exp(logfact / d);
   for (int k = 0; k < d; ++k) {
     const double ang = 2.0 * M_PI * (k + 0.5) / d + 0.25;
     z[k] = {(q)(r0 * std::cos(ang)), (q)(r0 * std::sin(ang))};
