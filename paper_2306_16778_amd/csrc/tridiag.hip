@@ -30,6 +30,7 @@
 
 #include "host_common.h"
 #include "kernels.h"
+#include "spike.h"
 
 using namespace expm;
 
@@ -558,6 +559,7 @@ struct expm_pfd_tri_s {
   double2* U = nullptr;     // n x (P 2 m_max): eliminated right-hand sides
   double2* F = nullptr;     // P x 2 x n x 3: the poles' tridiagonal factors
   ProblemDesc* desc = nullptr;
+  double2* spk = nullptr;   // from order SPIKE_MIN_N: the spike solver's workspace
 };
 
 namespace {
@@ -565,7 +567,7 @@ namespace {
 void tri_free(expm_pfd_tri_t p, hipStream_t stream = nullptr) {
   if (!p) return;
   void* ptrs[] = {p->Aw, p->Q, p->d, p->e, p->tau, p->vbuf, p->y, p->part, p->yv, p->done, p->Vp, p->Tf,
-                  p->Z1, p->Z2, p->Zp, p->theta, p->a, p->B, p->Xr, p->Ysol, p->Kp, p->U, p->F, p->desc};
+                  p->Z1, p->Z2, p->Zp, p->theta, p->a, p->B, p->Xr, p->Ysol, p->Kp, p->U, p->F, p->desc, p->spk};
   for (void* q : ptrs)
     if (q) (void)(p->pooled ? hipFreeAsync(q, stream) : hipFree(q));
   delete p;
@@ -580,7 +582,8 @@ std::vector<size_t> tri_sizes(int64_t n, int degree, int64_t m_max) {
           (size_t)TRI_NB * TRI_NB * 16, (size_t)TRI_NB * n * 16, (size_t)TRI_NB * n * 16,
           (size_t)TRI_KS * TRI_NB * n * 16, (size_t)P * 16, (size_t)P * 16, (size_t)np * m_max * 16,
           (size_t)np * m_max * 16, (size_t)n * nt * 16, (size_t)TRI_KS * n * m_max * 16, (size_t)n * nt * 16,
-          (size_t)n * P * 2 * 3 * 16, sizeof(ProblemDesc)};
+          (size_t)n * P * 2 * 3 * 16, sizeof(ProblemDesc),
+          n >= SPIKE_MIN_N ? spike_bytes(spike_plan(n, (int)P, (int)(2 * m_max)), (int)P) : 0};
 }
 
 }  // namespace
@@ -656,10 +659,13 @@ int expm::tri_create(expm_pfd_tri_t* out, int64_t n, int degree, int64_t m_max, 
   dm(&p->U);
   dm(&p->F);  // one copy per workgroup of a pole (at most 2: 2 m_max <= 128)
   dm(&p->desc);
+  dm(&p->spk);
   // the constants' host copies live in the plan, so the copies may complete later
   if (ok) ok = hipMemcpyAsync(p->theta, p->h_theta.data(), p->P * 16, hipMemcpyHostToDevice, pool) == hipSuccess;
   if (ok) ok = hipMemcpyAsync(p->a, p->h_a.data(), p->P * 16, hipMemcpyHostToDevice, pool) == hipSuccess;
   if (ok) ok = hipMemsetAsync(p->done, 0, 16, pool) == hipSuccess;
+  if (ok && n >= SPIKE_MIN_N)  // the spike solver's zero poles
+    ok = hipMemsetAsync(p->spk, 0, (size_t)p->P * 16, pool) == hipSuccess;
   if (ok) ok = hipMemsetAsync(p->B, 0, (size_t)np * m_max * 16, pool) == hipSuccess;
   if (ok) ok = hipMemsetAsync(p->Xr, 0, (size_t)np * m_max * 16, pool) == hipSuccess;
   if (ok && !pool) ok = hipDeviceSynchronize() == hipSuccess;
@@ -769,8 +775,23 @@ extern "C" int expm_pfd_tridiag_apply(expm_pfd_tri_t p, double t, const void* V,
   hipLaunchKernelGGL(k_tri_sum_slices, dim3(grid_for((int64_t)n * mm)), dim3(256), 0, st, p->Kp, ks,
                      (int64_t)n * mm, (int64_t)n * mm, p->B);
   const int nt = p->P * 2 * mm;
-  hipLaunchKernelGGL(k_tri_solve, dim3((unsigned)p->P, (unsigned)((2 * mm + 63) / 64)), dim3(64), 0, st, p->d, p->e,
-                     n, t, p->theta, p->P, sh.c, p->B, mm, p->F, p->U, p->Ysol);
+  if (n >= SPIKE_MIN_N) {
+    SpikeSrc src{};
+    src.kind = 1;
+    src.d = p->d;
+    src.e = p->e;
+    src.t = t;
+    src.c = sh.c;
+    src.V = p->B;
+    src.mv = mm;
+    src.ncol = 2 * mm;
+    src.n = n;
+    const SpikePlan q = spike_plan(n, p->P, 2 * mm);
+    spike_solve(src, p->theta, p->P, q, spike_carve(p->spk, q, p->P), SpikeOutInterleaved{p->Ysol, nt, 2 * mm}, st);
+  } else {
+    hipLaunchKernelGGL(k_tri_solve, dim3((unsigned)p->P, (unsigned)((2 * mm + 63) / 64)), dim3(64), 0, st, p->d,
+                       p->e, n, t, p->theta, p->P, sh.c, p->B, mm, p->F, p->U, p->Ysol);
+  }
   hipLaunchKernelGGL(k_tri_accum, dim3(grid_for((int64_t)n * mm)), dim3(256), 0, st, p->Ysol, n, mm, p->P, p->a,
                      sh.ec, p->B);
   tri_gemm<1>(st, n, mm, Ks, p->Q, ld, false, p->B, mm, p->Kp, mm,
