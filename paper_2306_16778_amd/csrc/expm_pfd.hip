@@ -1920,6 +1920,13 @@ struct expm_pfd_queue_s {
       auto it = free_plans.find(std::make_tuple(hi, cap, prec));
       return it != free_plans.end() && !it->second.empty();
     };
+    // a group's workspace stays within a quarter of the budget, so that several
+    // flights run side by side (large orders gain nothing from wider groups: their
+    // LU is bound by its arithmetic)
+    while (Gcap > 1 && plan_bytes(hi, Gcap, prec) > budget / 4) {
+      Gcap /= 2;
+      G = std::min(G, Gcap);
+    }
     for (;;) {
       if (reusable(Gcap) || mat_bytes + flight_bytes + plan_bytes(hi, Gcap, prec) <= budget) break;
       if (Gcap == 1) return false;
@@ -1986,6 +1993,18 @@ struct expm_pfd_queue_s {
       expm_pfd_opts o = opts;
       o.precision = prec;
       ok = create_plan(&pl, npad, Gcap, degree, 16, false, prec, &o, &pa) == 0;
+      if (!ok) {
+        // the device is short although the budget is not: release the idle cached
+        // plans, hand the pool's unused memory back and try once more
+        (void)hipGetLastError();
+        lk.lock();
+        release_cached((size_t)-1 / 2);
+        lk.unlock();
+        (void)hipDeviceSynchronize();  // the released plans' frees are ordered on their own streams
+        hipMemPool_t mpool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&mpool, device) == hipSuccess) (void)hipMemPoolTrimTo(mpool, 0);
+        ok = create_plan(&pl, npad, Gcap, degree, 16, false, prec, &o, &pa) == 0;
+      }
       if (ok) pl->lu_tile = opts.lu_tile > 0 ? opts.lu_tile - 1 : 0;
     }
     if (ok) {
@@ -2229,7 +2248,19 @@ extern "C" int expm_pfd_register_matrix(expm_pfd_queue_t q, const void* A, int64
   hipEvent_t ev = q->take_event();
   // stream-ordered: the copy follows the caller's work that wrote A; requests
   // wait for `ev` before they read the copy
-  if (!ev || hipMallocAsync((void**)&d, bytes, st) != hipSuccess) {
+  bool got = ev && hipMallocAsync((void**)&d, bytes, st) == hipSuccess;
+  if (!got && ev) {
+    // the device is short although the budget is not (the pool's free blocks do
+    // not fit this size): release the idle cached plans, hand the pool's unused
+    // memory back and try once more
+    (void)hipGetLastError();
+    q->release_cached((size_t)-1 / 2);
+    (void)hipDeviceSynchronize();
+    hipMemPool_t mpool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&mpool, q->device) == hipSuccess) (void)hipMemPoolTrimTo(mpool, 0);
+    got = hipMallocAsync((void**)&d, bytes, st) == hipSuccess;
+  }
+  if (!got) {
     (void)hipGetLastError();
     q->give_event(ev);
     return EXPM_PFD_ERR_OOM;

@@ -84,9 +84,9 @@ def replay(count: int, qps: float, precision: str = "mixed", degree: int = 16, n
                         mid = ep.expm_pfd_register_matrix(q, A, stream=prep)
                         break
                     except ep.ExpmPfdError as e:
-                        # the budget is full of work in flight: release what can be
-                        # released and let some of it complete
-                        if e.code != -9 or attempt == 99999:
+                        # the budget (or the device) is full of work in flight: release
+                        # what can be released and let some of it complete
+                        if e.code not in (-9, -5) or attempt == 99999:
                             raise
                         evict(0)
                         time.sleep(1e-3)
