@@ -192,15 +192,20 @@ def stage_rates(breakdown, precision):
     return out
 
 
+def _host_threads():
+    """Threads the oracle's BLAS/LAPACK uses on the host."""
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()]))
+    except Exception:
+        return int(os.cpu_count())
+
+
 def cpu_baseline(prob):
     """The oracle as it stands on the host cores: one full R_d(tA)V of the workload."""
     from oracle import matrix
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        threads = os.cpu_count()
+    threads = _host_threads()
     t0 = time.perf_counter()
     Y = matrix.expm_R(prob.A, prob.V, prob.t, prob.degree)
     dt = time.perf_counter() - t0
@@ -262,6 +267,44 @@ def batched_section(ep, torch, workloads, matrix, reps=5):
         torch.cuda.synchronize()
         res["one_shot_ms_per_batch"] = (time.perf_counter() - t0) * 1e3
         out[prec] = res
+    # the oracle on the host, one problem at a time over the whole batch (it takes
+    # a few seconds: the orders are at most 512)
+    t0 = time.perf_counter()
+    for p in probs:
+        matrix.expm_R(p.A, p.V, p.t, 16)
+    wall = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": 512 / wall, "unit": "solves/s", "cores": _host_threads(), "kind": "oracle",
+                           "sample": f"all 512 problems through the oracle (eigendecomposition), {wall:.1f} s"}
+    return out
+
+
+def config1_section(ep, torch, check, reps=20):
+    """The small workload: n = 64, spectrum U[-10, 0], V = I (the full R_16(A)),
+    t = 1, degree 16; one apply per path, median of `reps`."""
+    import numpy as np
+
+    from paper_2306_16778_amd import workloads
+
+    prob = workloads.config1_plain_cpu_sized()
+    n = prob.A.shape[0]
+    Ad = torch.from_numpy(np.asfortranarray(prob.A)).cuda()
+    out = {"workload": "Hermitian n=64, spectrum U[-10,0], V = I, t=1, degree 16"}
+    Y = check.expm_R(prob.A, None, 1.0, 16) if check is not None else None
+    for prec in ("fp64", "mixed"):
+        plan = ep.expm_pfd_plan(n, 16, 1.0, 0, prec)
+        X = ep.expm_pfd_apply(plan, Ad, None)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ep.expm_pfd_apply(plan, Ad, None, X)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = sorted(times)[reps // 2]
+        res = {"ms_per_apply": ms, "solves_per_s": 1e3 / ms}
+        if Y is not None:
+            res["rel_err_vs_oracle"] = check.rel_fro(X.cpu().numpy(), Y)
+        out[prec] = res
     return out
 
 
@@ -305,11 +348,7 @@ def serving_cpu_baseline(reqs, specs, budget_s=20.0):
     M = np.stack([n_s ** 3, np.ones_like(n_s)], axis=1)
     (a, b), *_ = np.linalg.lstsq(M, t_s, rcond=None)
     total = float(np.sum(a * ns.astype(float) ** 3 + b))
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        threads = os.cpu_count()
+    threads = _host_threads()
     return {"value": len(reqs) / total, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "extrapolated": True,
             "sample": "%d requests of the trace (n = %s) timed one by one through the oracle (host-assembled "
@@ -640,6 +679,10 @@ def main():
         from oracle import matrix as rcheck
         real = real_section(ep, torch, args.steps, None if args.no_cpu_baseline else rcheck)
         print("[bench] real-data section done", file=sys.stderr, flush=True)
+    config1 = None
+    if not args.no_config3:
+        from oracle import matrix as c1check
+        config1 = config1_section(ep, torch, None if args.no_cpu_baseline else c1check)
     config3 = None
     if not args.no_config3:
         from oracle import matrix as c3check
@@ -695,6 +738,7 @@ def main():
         "cpu_baseline": cpu,
         "real_symmetric": real,
         "batched": batched,
+        "small_n64": config1,
         "precision_n4096": config3,
         "tridiagonal_route": tri,
         "banded_route": band,

@@ -615,14 +615,21 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
   const int m0 = tm * BM, n0 = tn * BN;
 
   // the products are summed on their own and subtracted from C once, in the
-  // epilogue (MODE 0), so C's magnitude does not enter every rounding step
-  V accR[MI][NJ], accI[MI][NJ];
+  // epilogue (MODE 0), so C's magnitude does not enter every rounding step.
+  // FP32 forms the complex product from three real ones (Gauss: T1 = Re a Re b,
+  // T2 = Im a Im b, T3 = (Re a + Im a)(Re b + Im b); Re = T1 - T2, Im = T3 - T1 - T2),
+  // a quarter fewer matrix-core products than the four of the FP64 form; its
+  // slightly weaker componentwise bound is within what the FP64 refinement corrects.
+  // Every FP32 instantiation does so, so that all tile shapes give the same bits.
+  constexpr bool GAUSS3 = sizeof(R) == 4;
+  V accR[MI][NJ], accI[MI][NJ], accS[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       accR[i][j] = V{0, 0, 0, 0};
       accI[i][j] = V{0, 0, 0, 0};
+      accS[i][j] = V{0, 0, 0, 0};
     }
 
   // one K chunk of A (op applied, conjugated if needed) and B into registers.
@@ -680,6 +687,37 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
   for (int ch = 0; ch < nchunks; ++ch) {
     const int cur = ch & 1;
     if (ch + 1 < nchunks) fetch((ch + 1) * KC);  // in flight during the products below
+    if constexpr (GAUSS3) {
+      // four complex k per matrix-core step: lane (r16, kq) gives A[row r16][k kq]
+      // and B[k kq][column r16]; accR, accI, accS collect T1, T2, T3
+#pragma unroll
+      for (int k4 = 0; k4 < KC / 4; ++k4) {
+        const int kc = 4 * k4 + kq;
+        R a1[MI], a2[MI], a3[MI], b1[NJ], b2[NJ], b3[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const T av = As[cur][wm0 + i * 16 + r16][kc];
+          a1[i] = av.x;
+          a2[i] = av.y;
+          a3[i] = av.x + av.y;
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const T bv = Bs[cur][kc][wn0 + j * 16 + r16];
+          b1[j] = bv.x;
+          b2[j] = bv.y;
+          b3[j] = bv.x + bv.y;
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            accR[i][j] = MF::run(a1[i], b1[j], accR[i][j]);
+            accI[i][j] = MF::run(a2[i], b2[j], accI[i][j]);
+            accS[i][j] = MF::run(a3[i], b3[j], accS[i][j]);
+          }
+      }
+    } else {
 #pragma unroll
     for (int k2 = 0; k2 < KC / 2; ++k2) {
       const int kc = 2 * k2 + (kq >> 1);
@@ -704,8 +742,19 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
           accI[i][j] = MF::run(aI[i], bR[j], accI[i][j]);
         }
     }
+    }
     if (ch + 1 < nchunks) stash(cur ^ 1);
     __syncthreads();
+  }
+  if constexpr (GAUSS3) {
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const V t1 = accR[i][j], t2 = accI[i][j];
+        accR[i][j] = t1 - t2;
+        accI[i][j] = accS[i][j] - t1 - t2;
+      }
   }
   // epilogue: all C loads (clamped in range) first, then the guarded stores
   T cold[MI][NJ][4];
