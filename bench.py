@@ -46,8 +46,8 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 # kernel reads and writes per launch hash to the digest below (the kernel, its
 # device helpers, the launcher and the factorization steps that choose the
 # launch shapes), otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 272.40e6 + 130.02e6,
-                     "sources_sha256": "cf873172b3c8004b140f0105bb38ff344e8fedf83927e4a711530e9bd9bb1e4e"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 273.01e6 + 130.02e6,
+                     "sources_sha256": "7f7ca2c249205379917202390a80083eb4f75ecea0f87683d1e196827acdb579"}}
 
 # (file, first marker, end marker) of each source span in the digest
 TRAFFIC_SPANS = (
