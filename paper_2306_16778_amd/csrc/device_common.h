@@ -129,6 +129,17 @@ template <int CTRL, int ROWMASK>
 __device__ __forceinline__ int dpp_i32(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWMASK, 0xF, false);
 }
+// max (min) of v and the DPP-moved v.  The identity of the operation as the
+// value of lanes whose source is masked off lets the compiler fold the move
+// into the max (min) instruction itself; such lanes keep v.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_max_i32(int v) {
+  return max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, CTRL, ROWMASK, 0xF, false));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_min_i32(int v) {
+  return min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, CTRL, ROWMASK, 0xF, false));
+}
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(dpp_i32<CTRL, ROWMASK>(__float_as_int(v)));
@@ -150,10 +161,10 @@ __device__ __forceinline__ R row16_max(R x) {
   return x;
 }
 __device__ __forceinline__ int row16_min(int x) {
-  x = min(x, dpp_i32<0xB1, 0xF>(x));
-  x = min(x, dpp_i32<0x4E, 0xF>(x));
-  x = min(x, dpp_i32<0x141, 0xF>(x));
-  x = min(x, dpp_i32<0x140, 0xF>(x));
+  x = dpp_min_i32<0xB1, 0xF>(x);
+  x = dpp_min_i32<0x4E, 0xF>(x);
+  x = dpp_min_i32<0x141, 0xF>(x);
+  x = dpp_min_i32<0x140, 0xF>(x);
   return x;
 }
 // maximum over the wave, returned in every lane
@@ -173,8 +184,8 @@ __device__ __forceinline__ R wave_max(R x) {
 }
 __device__ __forceinline__ int wave_min(int x) {
   x = row16_min(x);
-  x = min(x, dpp_i32<0x142, 0xA>(x));
-  x = min(x, dpp_i32<0x143, 0xC>(x));
+  x = dpp_min_i32<0x142, 0xA>(x);
+  x = dpp_min_i32<0x143, 0xC>(x);
   return __builtin_amdgcn_readlane(x, 63);
 }
 
@@ -249,8 +260,11 @@ constexpr int MOVE_STRIDE = 1 + 2 * MOVE_CAP;
 // i = 0..cnt-1 (cnt <= 64, piv[i] >= base+i, applied in order), and writes the
 // net row moves to dst/src.  Returns the number of moves (same on all lanes).
 // piv is read once (one element per lane); every later exchange of values
-// between lanes uses readlane with a wave-uniform lane index.
-__device__ inline int composite_moves(const int* piv, int cnt, int base, int* dst, int* src) {
+// between lanes uses readlane with a wave-uniform lane index.  If slot_of is
+// given, slot_of[i] (i < cnt) is the index of the move that fills row base+i,
+// or -1 if that row keeps its value.
+__device__ inline int composite_moves(const int* piv, int cnt, int base, int* dst, int* src,
+                                      int* slot_of = nullptr) {
   const int lane = threadIdx.x & 63;
   const int mypiv = lane < cnt ? piv[lane] : 0;
   int cur = base + lane;  // original row now at position base+lane
@@ -294,6 +308,7 @@ __device__ inline int composite_moves(const int* piv, int cnt, int base, int* ds
     dst[pos] = key;
     src[pos] = val;
   }
+  if (slot_of != nullptr && lane < cnt) slot_of[lane] = pt ? __popcll(mt & below) : -1;
   return nt + __popcll(mo);
 }
 

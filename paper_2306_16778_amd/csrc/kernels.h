@@ -153,15 +153,19 @@ __global__ __launch_bounds__(256) void k_form(const ProblemDesc* __restrict__ de
 // ---------------------------------------------------------------------------
 // K2: panel factorization with partial pivoting (LAPACK getf2 order) of the
 // IB columns [c0, c0+IB) over rows [c0, npad), one shifted matrix per
-// workgroup.  The panel lives in registers: thread t owns rows
-// c0 + t + PANEL_NT*s.  Per column (one barrier): every wave finds its
-// candidate row (largest |Re|+|Im|, lowest row on ties) with DPP reductions and
-// publishes value, row index and row contents in LDS; after the barrier every
-// wave reduces the PANEL_NT/64 candidates the same way, swaps the pivot row in
-// and applies the rank-1 update in registers.  Every wave repeats the per-column
-// bookkeeping (reductions, pivot reciprocal, swaps), so the workgroup is kept
-// at 8 waves with more rows per thread rather than 16.  The panel is loaded and stored through LDS so that
-// global accesses are coalesced.
+// workgroup.  The panel lives in registers: thread t holds the rows it loaded,
+// c0 + t + PANEL_NT*s, for the whole panel.  A row interchange exchanges
+// positions, not data: pos[s] is the row position the data in a[s] currently
+// stand for, and the rows are written to their final positions when the panel
+// is stored.  Per column (one barrier): every wave finds its candidate row
+// (largest |Re|+|Im|, lowest position on ties) with DPP reductions and
+// publishes value, position and the row's remaining columns in LDS; after the
+// barrier every wave reduces the PANEL_NT/64 candidates the same way, reads
+// the pivot row, exchanges the two positions and applies the rank-1 update in
+// registers.  Every wave repeats the per-column bookkeeping (reductions, pivot
+// reciprocal), so the workgroup is kept at 8 waves with more rows per thread
+// rather than 16.  The panel is loaded and stored through LDS so that global
+// accesses are coalesced.
 // Then, inside the enclosing outer panel [j0, j0+nbo): the IB interchanges are
 // applied to the other outer-panel columns and the IB x (rest) block of U is
 // solved with the unit lower IB x IB factor.  On the last inner step the net
@@ -175,8 +179,7 @@ template <typename R, int IB>
 struct PanelShared {
   R cand_v[2][PANEL_NW];
   int cand_i[2][PANEL_NW];
-  cx<R> cand_row[2][PANEL_NW][IB];  // each wave's candidate row
-  cx<R> crow[2][IB];          // row gc before the interchange
+  cx<R> cand_row[2][PANEL_NW][IB];  // each wave's candidate row (columns C.. of step C)
   int piv[NB_MAX];
 };
 
@@ -184,17 +187,17 @@ struct PanelShared {
 // over each 16-lane row.  For FP32 the values are compared as signed integers:
 // for floats >= 0 the bit patterns order like the values and -1.0f is negative,
 // which saves the NaN canonicalisation a float maximum carries (no search value
-// is NaN: a NaN never compares greater than the running maximum).
+// is NaN).
 template <typename R>
 __device__ __forceinline__ R search_wave_max(R x) {
   if constexpr (sizeof(R) == 4) {
     int v = __float_as_int(x);
-    v = max(v, dpp_i32<0xB1, 0xF>(v));
-    v = max(v, dpp_i32<0x4E, 0xF>(v));
-    v = max(v, dpp_i32<0x141, 0xF>(v));
-    v = max(v, dpp_i32<0x140, 0xF>(v));
-    v = max(v, dpp_i32<0x142, 0xA>(v));
-    v = max(v, dpp_i32<0x143, 0xC>(v));
+    v = dpp_max_i32<0xB1, 0xF>(v);
+    v = dpp_max_i32<0x4E, 0xF>(v);
+    v = dpp_max_i32<0x141, 0xF>(v);
+    v = dpp_max_i32<0x140, 0xF>(v);
+    v = dpp_max_i32<0x142, 0xA>(v);
+    v = dpp_max_i32<0x143, 0xC>(v);
     return __int_as_float(__builtin_amdgcn_readlane(v, 63));
   } else {
     return wave_max(x);
@@ -204,108 +207,13 @@ template <typename R>
 __device__ __forceinline__ R search_row16_max(R x) {
   if constexpr (sizeof(R) == 4) {
     int v = __float_as_int(x);
-    v = max(v, dpp_i32<0xB1, 0xF>(v));
-    v = max(v, dpp_i32<0x4E, 0xF>(v));
-    v = max(v, dpp_i32<0x141, 0xF>(v));
-    v = max(v, dpp_i32<0x140, 0xF>(v));
+    v = dpp_max_i32<0xB1, 0xF>(v);
+    v = dpp_max_i32<0x4E, 0xF>(v);
+    v = dpp_max_i32<0x141, 0xF>(v);
+    v = dpp_max_i32<0x140, 0xF>(v);
     return __int_as_float(v);
   } else {
     return row16_max(x);
-  }
-}
-
-// One column C of the inner panel.  Thread tid holds rows c0 + tid + PANEL_NT*s
-// (s < S) in a[s][.].  Row gc = c0 + C is always lane C of wave 0 in block 0;
-// a row index that is uniform across the wave (the wave's candidate, the pivot)
-// names its block s and wave, so only that block's copy is issued.
-template <typename R, int IB, int S, int C>
-__device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, IB>& sh, int c0, int j0, int npad,
-                                             int tid) {
-  if constexpr (C < IB) {
-    using T = cx<R>;
-    constexpr int NONE = 0x7fffffff;
-    const int lane = tid & 63, wid = tid >> 6;
-    const int gc = c0 + C;
-    constexpr int buf = C & 1;
-    R bv = -1;
-    int bi = NONE;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = c0 + tid + PANEL_NT * s;
-      if (r >= gc && r < npad) {
-        const R v = fabs(a[s][C].x) + fabs(a[s][C].y);
-        if (v > bv) {
-          bv = v;
-          bi = r;
-        }
-      }
-    }
-    // wave candidate: maximum value, then the lowest row among the lanes holding it
-    const R wv = search_wave_max(bv);
-    const unsigned long long m = __ballot(bv == wv);
-    const int wi = (__popcll(m) == 1) ? __builtin_amdgcn_readlane(bi, __ffsll((long long)m) - 1)
-                                       : wave_min(bv == wv ? bi : NONE);
-    if (lane == 0) {
-      sh.cand_v[buf][wid] = wv;
-      sh.cand_i[buf][wid] = wi;
-    }
-    const int wblk = (wi - c0) / PANEL_NT;  // block holding the candidate (none if wi == NONE)
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s == wblk && c0 + tid + PANEL_NT * s == wi) {
-#pragma unroll
-        for (int cc = 0; cc < IB; ++cc) sh.cand_row[buf][wid][cc] = a[s][cc];
-      }
-    }
-    if (wid == 0 && lane == C) {
-#pragma unroll
-      for (int cc = 0; cc < IB; ++cc) sh.crow[buf][cc] = a[0][cc];
-    }
-    __syncthreads();
-    // global pivot: each row of 16 lanes reduces the wave candidates (each
-    // candidate held by 16 / PANEL_NW lanes of the row)
-    const R cv = sh.cand_v[buf][lane % PANEL_NW];
-    const int ci = sh.cand_i[buf][lane % PANEL_NW];
-    const R gv = search_row16_max(cv);
-    const int gi = __builtin_amdgcn_readlane(row16_min(cv == gv ? ci : NONE), 0);
-    // no candidate compared greater (a column of NaNs): keep the diagonal row, so
-    // every later row index stays inside the matrix
-    const bool found = gi >= gc && gi < npad;
-    const int p = found ? gi : gc;
-    const T* prow = found ? sh.cand_row[buf][((p - c0) % PANEL_NT) >> 6] : sh.crow[buf];
-    if (tid == 0) sh.piv[gc - j0] = p;
-    // the part of the pivot row the update uses, read once into registers
-    T pr[IB];
-#pragma unroll
-    for (int cc = C; cc < IB; ++cc) pr[cc] = prow[cc];
-    // interchange rows gc and p
-    if (wid == 0 && lane == C) {
-#pragma unroll
-      for (int cc = 0; cc < IB; ++cc) a[0][cc] = cc < C ? prow[cc] : pr[cc];
-    }
-    const int pblk = (p - c0) / PANEL_NT;
-    if (p != gc && wid == ((p - c0) % PANEL_NT) >> 6) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (s == pblk && c0 + tid + PANEL_NT * s == p) {
-#pragma unroll
-          for (int cc = 0; cc < IB; ++cc) a[s][cc] = sh.crow[buf][cc];
-        }
-      }
-    }
-    const T inv = crecip_fast(pr[C]);
-    // rows at or above gc (lanes 0..C of wave 0, block 0) are rows of U and stay;
-    // rows past npad hold zeros here and are never searched or stored
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s > 0 || tid > C) {
-        const T l = cmul(a[s][C], inv);
-        a[s][C] = l;
-#pragma unroll
-        for (int cc = C + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, pr[cc]);
-      }
-    }
-    panel_column<R, IB, S, C + 1>(a, sh, c0, j0, npad, tid);
   }
 }
 
@@ -314,6 +222,86 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], PanelShared<R, I
 template <int IB>
 __device__ __forceinline__ int stage_slot(int row, int col) {
   return row * IB + (col ^ (row & (IB - 1)));
+}
+
+// One column C of the inner panel.  Positions below gc = c0 + C belong to the
+// earlier pivot rows; padding rows (past npad) carry position -1 and are never
+// searched, updated or stored; every other row is active.  A NaN search value
+// counts as 0, so some active row always wins (the lowest position among
+// equals) and every pivot position stays inside the matrix.
+template <typename R, int IB, int S, int C>
+__device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], int (&pos)[S], PanelShared<R, IB>& sh, int c0,
+                                             int j0, int tid) {
+  if constexpr (C < IB) {
+    using T = cx<R>;
+    constexpr int NONE = 0x7fffffff;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int gc = c0 + C;
+    constexpr int buf = C & 1;
+    R bv = -1;
+    int bi = NONE, bs = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const R v = fmax(fabs(a[s][C].x) + fabs(a[s][C].y), (R)0);
+      if (pos[s] >= gc && (v > bv || (v == bv && pos[s] < bi))) {
+        bv = v;
+        bi = pos[s];
+        bs = s;
+      }
+    }
+    // wave candidate: maximum value, then the lowest position among the lanes
+    // holding it; cl is its lane and ws the block of that lane's row
+    const R wv = search_wave_max(bv);
+    const unsigned long long m = __ballot(bv == wv);
+    int cl = __ffsll((long long)m) - 1;
+    if (__popcll(m) != 1) {
+      const int wmin = wave_min(bv == wv ? bi : NONE);
+      cl = __ffsll((long long)__ballot(bv == wv && bi == wmin)) - 1;
+    }
+    const int wi = __builtin_amdgcn_readlane(bi, cl);
+    const int ws = __builtin_amdgcn_readlane(bs, cl);
+    if (lane == 0) {
+      sh.cand_v[buf][wid] = wv;
+      sh.cand_i[buf][wid] = wi;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s == ws && lane == cl) {
+#pragma unroll
+        for (int cc = C; cc < IB; ++cc) sh.cand_row[buf][wid][cc] = a[s][cc];
+      }
+    }
+    __syncthreads();
+    // global pivot: each row of 16 lanes reduces the wave candidates (each
+    // candidate held by 16 / PANEL_NW lanes of the row); lane l holds the
+    // candidate of wave l % PANEL_NW, so the lowest lane holding the winner
+    // is its wave
+    const R cv = sh.cand_v[buf][lane % PANEL_NW];
+    const int ci = sh.cand_i[buf][lane % PANEL_NW];
+    const R gv = search_row16_max(cv);
+    const int q = __builtin_amdgcn_readlane(row16_min(cv == gv ? ci : NONE), 0);
+    const int pw = __ffsll((long long)__ballot(ci == q)) - 1;
+    if (tid == 0) sh.piv[gc - j0] = q;
+    // the part of the pivot row the update uses, read once into registers
+    T pr[IB];
+#pragma unroll
+    for (int cc = C; cc < IB; ++cc) pr[cc] = sh.cand_row[buf][pw][cc];
+    // interchange positions gc and q
+#pragma unroll
+    for (int s = 0; s < S; ++s) pos[s] = pos[s] == q ? gc : (pos[s] == gc ? q : pos[s]);
+    const T inv = crecip_fast(pr[C]);
+    // the rows below the pivot position
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (pos[s] > gc) {
+        const T l = cmul(a[s][C], inv);
+        a[s][C] = l;
+#pragma unroll
+        for (int cc = C + 1; cc < IB; ++cc) a[s][cc] = cfms(a[s][cc], l, pr[cc]);
+      }
+    }
+    panel_column<R, IB, S, C + 1>(a, pos, sh, c0, j0, tid);
+  }
 }
 
 template <typename R, int IB, int S>
@@ -325,6 +313,7 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
   __shared__ T stage[PANEL_NT * IB];  // panel staging; reused as the row-move buffer
   __shared__ T Lib[IB][IB + 1];
   __shared__ int mv_dst[MOVE_CAP], mv_src[MOVE_CAP];
+  __shared__ int mv_row[IB];
   __shared__ int mv_cnt;
 
   const int b = blockIdx.x;
@@ -368,61 +357,113 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
     for (int c = 0; c < IB; ++c) a[s][c] = tid < nr ? stage[stage_slot<IB>(tid, c)] : czero<T>();
     __syncthreads();
   }
-  panel_column<R, IB, S, 0>(a, sh, c0, j0, npad, tid);
+  int pos[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) pos[s] = c0 + tid + PANEL_NT * s < npad ? c0 + tid + PANEL_NT * s : -1;
+  panel_column<R, IB, S, 0>(a, pos, sh, c0, j0, tid);
 
+  // store: block sb of positions gathers the rows that now stand for them.
+  // Only two kinds of row change blocks: the pivot rows (to positions
+  // [c0, c0+IB) of block 0) and the rows they displaced, which all started at
+  // those positions (block 0 of wave 0, lanes below IB).
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int rbase = c0 + PANEL_NT * s;
+  for (int sb = 0; sb < S; ++sb) {
+    const int rbase = c0 + PANEL_NT * sb;
+    {
+      const int r = pos[sb] - rbase;
+      if (r >= 0 && r < PANEL_NT) {
 #pragma unroll
-    for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(tid, c)] = a[s][c];
+        for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(r, c)] = a[sb][c];
+      }
+    }
+    if (sb == 0) {
+#pragma unroll
+      for (int s = 1; s < S; ++s) {
+        if (pos[s] >= c0 && pos[s] < c0 + IB) {
+#pragma unroll
+          for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(pos[s] - c0, c)] = a[s][c];
+        }
+      }
+    } else if (wid == 0) {
+      const int r = pos[0] - rbase;
+      if (r >= 0 && r < PANEL_NT) {
+#pragma unroll
+        for (int c = 0; c < IB; ++c) stage[stage_slot<IB>(r, c)] = a[0][c];
+      }
+    }
     __syncthreads();
+    if (sb == 0 && tid < IB) {
+#pragma unroll
+      for (int c = 0; c < IB; ++c) Lib[tid][c] = stage[stage_slot<IB>(tid, c)];  // rows c0..c0+IB of the factors
+    }
 #pragma unroll
     for (int q = 0; q < IB; ++q) {
       const int e = tid + PANEL_NT * q;
-      const int rr = PANEL_NT * s + (PANEL_NT / IB) * q;
+      const int rr = PANEL_NT * sb + (PANEL_NT / IB) * q;
       if (c0 + rr + tid / IB < npad)
         *(T*)((char*)pbase + lane_off + (unsigned)rr * pitch) = stage[stage_slot<IB>(e / IB, e % IB)];
     }
     __syncthreads();
   }
-  if (tid < IB) {
-#pragma unroll
-    for (int c = 0; c < IB; ++c) Lib[tid][c] = a[0][c];  // rows c0..c0+IB of the factored panel
-    ipiv[c0 + tid] = sh.piv[c0 - j0 + tid];
-  }
+  if (tid < IB) ipiv[c0 + tid] = sh.piv[c0 - j0 + tid];
   if (wid == 0) {
-    const int cnt = composite_moves(sh.piv + (c0 - j0), IB, c0, mv_dst, mv_src);
+    // mv_row: for each row of the U block, the move that fills it (-1: none)
+    const int cnt = composite_moves(sh.piv + (c0 - j0), IB, c0, mv_dst, mv_src, mv_row);
     if (lane == 0) mv_cnt = cnt;
   }
   __syncthreads();
 
   // ---- interchanges on the other columns of the outer panel, then U block --
+  // The moved values and the U block's rows (as they stand before the
+  // interchanges) are read together; the U block takes the moved value where
+  // a move fills one of its rows and writes all IB of its rows itself, so the
+  // interchanges skip those rows of the right columns.
   T* mvbuf = stage;  // [2*IB][NB_MAX]
   const int nleft = c0 - j0, nright = j0 + nbo - c0 - IB, nother = nleft + nright;
   const int cnt = mv_cnt;
-  for (int e = tid; e < cnt * nother; e += PANEL_NT) {
-    const int i = e / nother, cc = e % nother;
-    const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
-    mvbuf[i * NB_MAX + cc] = W[(int64_t)mv_src[i] * ld + col];
+  // at most 2*IB moves over fewer than NB_MAX columns: MV_IT passes cover them
+  constexpr int MV_IT = (2 * IB * NB_MAX + PANEL_NT - 1) / PANEL_NT;
+  T mvv[MV_IT];
+#pragma unroll
+  for (int it = 0; it < MV_IT; ++it) {
+    const int e = tid + PANEL_NT * it;
+    if (e < cnt * nother) {
+      const int i = e / nother, cc = e % nother;
+      const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
+      mvv[it] = W[(int64_t)mv_src[i] * ld + col];
+    }
+  }
+  T x[IB];
+  if (tid < nright) {
+#pragma unroll
+    for (int i = 0; i < IB; ++i) x[i] = W[(int64_t)(c0 + i) * ld + c0 + IB + tid];
+  }
+#pragma unroll
+  for (int it = 0; it < MV_IT; ++it) {
+    const int e = tid + PANEL_NT * it;
+    if (e < cnt * nother) mvbuf[(e / nother) * NB_MAX + e % nother] = mvv[it];
   }
   __syncthreads();
   for (int e = tid; e < cnt * nother; e += PANEL_NT) {
     const int i = e / nother, cc = e % nother;
     const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
-    W[(int64_t)mv_dst[i] * ld + col] = mvbuf[i * NB_MAX + cc];
+    const int dst = mv_dst[i];
+    if (cc < nleft || dst >= c0 + IB) W[(int64_t)dst * ld + col] = mvbuf[i * NB_MAX + cc];
   }
-  __syncthreads();
   if (tid < nright) {
     const int col = c0 + IB + tid;
-    T x[IB];
 #pragma unroll
-    for (int i = 0; i < IB; ++i) x[i] = W[(int64_t)(c0 + i) * ld + col];
+    for (int i = 0; i < IB; ++i) {
+      const int sl = mv_row[i];
+      const T v = mvbuf[(sl < 0 ? 0 : sl) * NB_MAX + nleft + tid];
+      x[i] = sl >= 0 ? v : x[i];
+    }
 #pragma unroll
     for (int i = 1; i < IB; ++i)
 #pragma unroll
       for (int k = 0; k < i; ++k) x[i] = cfms(x[i], Lib[i][k], x[k]);
 #pragma unroll
-    for (int i = 1; i < IB; ++i) W[(int64_t)(c0 + i) * ld + col] = x[i];
+    for (int i = 0; i < IB; ++i) W[(int64_t)(c0 + i) * ld + col] = x[i];
   }
   if (last && wid == 0) {
     // net row moves of the whole outer step
