@@ -175,8 +175,9 @@ def finish_path(Xh, steps, wall, dom, lat, breakdown, n, m, d, precision, graph)
 
 def stage_rates(breakdown, precision):
     """Per kernel class of one traced apply: algorithmic TFLOP/s and HBM GB/s (the
-    tracer's per-launch counts over the summed launch times), and the fraction of
-    the bound that applies (matrix cores for the products, HBM for the rest)."""
+    tracer's per-launch counts over the summed launch times), the fraction of the
+    bound that applies (matrix cores for the products, HBM for the rest; none for
+    the latency-bound classes) and, for every class, the HBM fraction."""
     mfma = {"lu_trail", "lu_gemm", "lu_trsm", "ir_gemm"}
     latency = {"panel", "moves"}  # one workgroup per matrix / row copies: neither peak applies
     out = {}
@@ -188,7 +189,8 @@ def stage_rates(breakdown, precision):
         peak = 78.6 if (precision == "fp64" or c == "ir_gemm") else 157.3
         bound = "mfma" if c in mfma else "latency" if c in latency else "hbm"
         frac = round(tf / peak, 3) if bound == "mfma" else round(gbs / 8000.0, 3) if bound == "hbm" else None
-        out[c] = {"tflops": round(tf, 2), "gb_per_s": round(gbs, 1), "bound": bound, "frac": frac}
+        out[c] = {"tflops": round(tf, 2), "gb_per_s": round(gbs, 1), "bound": bound, "frac": frac,
+                  "hbm_frac": round(gbs / 8000.0, 4)}
     return out
 
 

@@ -106,7 +106,8 @@ def test_bench_bookkeeping():
 
 def test_stage_rates():
     """Per-stage rates of the bench line: flops and bytes over the summed launch times,
-    matrix-core fraction for the products, HBM fraction (8 TB/s) for the rest."""
+    matrix-core fraction for the products, HBM fraction (8 TB/s) for the rest, and
+    the HBM fraction of every stage, latency-bound ones included."""
     sys.path.insert(0, ROOT)
     import bench
 
@@ -121,7 +122,8 @@ def test_stage_rates():
     assert bench.stage_rates(b, "fp64")["lu_trail"]["frac"] == round(100.0 / 78.6, 3)
     b["panel"] = {"launches": 4, "ms": 1.0, "flops": 1.0e9, "bytes": 1.0e8}
     assert bench.stage_rates(b, "mixed")["panel"] == {"tflops": 1.0, "gb_per_s": 100.0, "bound": "latency",
-                                                      "frac": None}
+                                                      "frac": None, "hbm_frac": 0.0125}
+    assert r["solve_gemm"]["hbm_frac"] == 0.5
 
 
 def test_serving_eigenpairs_rebuild_the_matrix():
