@@ -140,6 +140,40 @@ def test_diagonal_and_zero(ep):
     assert matrix.rel_fro(Z, V) < 1e-13
 
 
+@pytest.mark.parametrize("n", [700, 2048])
+@pytest.mark.parametrize("kind", ["ties", "far"])
+def test_pivoting_ties_and_far_pivots(ep, n, kind):
+    """Two matrices that drive the pivot search of the register panel.
+    ties: A = -(100/n) 1 1^H (spectrum {-100, 0}); below the diagonal every column
+      holds equal magnitudes at every elimination step, so every wave resolves
+      exact ties (largest |Re|+|Im|, then the lowest position).
+    far: A of 2 x 2 blocks [[-1, -50], [-50, -2500]] on rows (i, i + n/2)
+      (spectrum {-2501, 0}); each column of the first half takes its pivot from
+      the row n/2 below, so at n = 2048 rows move between blocks of the register
+      panel at every column of the first half.
+    Both paths against the oracle (a LAPACK pole sum in FP64 reaches 5e-14 and
+    4e-15 on them)."""
+    rng = np.random.default_rng(31 + n)
+    if kind == "ties":
+        A = np.full((n, n), -100.0 / n, np.complex128)
+    else:
+        A = np.zeros((n, n), np.complex128)
+        h = n // 2
+        i = np.arange(h)
+        A[i, i] = -1.0
+        A[i + h, i + h] = -2500.0
+        A[i, i + h] = -50.0
+        A[i + h, i] = -50.0
+    V = wl.complex_gaussian(rng, n, 4)
+    Y = matrix.expm_R(A, V, 1.0, 16)
+    _announce(f"pivot {kind} fp64 n={n} m=4 d=16")
+    X = _run(ep, A, V, 1.0, 16)
+    assert matrix.rel_fro(X, Y) < TOL64
+    _announce(f"pivot {kind} mixed n={n} m=4 d=16")
+    Xm = _run(ep, A, V, 1.0, 16, "mixed")
+    assert matrix.rel_fro(Xm, Y) < TOLMX
+
+
 def test_lower_triangle_only(ep):
     A, V, t = _problem(90, -60, 0, 2, 9)
     B = A.copy()
