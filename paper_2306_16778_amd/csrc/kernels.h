@@ -657,12 +657,15 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
 
   // the products are summed on their own and subtracted from C once, in the
   // epilogue (MODE 0), so C's magnitude does not enter every rounding step.
-  // FP32 forms the complex product from three real ones (Gauss: T1 = Re a Re b,
-  // T2 = Im a Im b, T3 = (Re a + Im a)(Re b + Im b); Re = T1 - T2, Im = T3 - T1 - T2),
-  // a quarter fewer matrix-core products than the four of the FP64 form; its
-  // slightly weaker componentwise bound is within what the FP64 refinement corrects.
-  // Every FP32 instantiation does so, so that all tile shapes give the same bits.
-  constexpr bool GAUSS3 = sizeof(R) == 4;
+  // The LU updates (MODE 0) and every FP32 product form the complex product from
+  // three real ones (Gauss: T1 = Re a Re b, T2 = Im a Im b, T3 = (Re a + Im a)
+  // (Re b + Im b); Re = T1 - T2, Im = T3 - T1 - T2), a quarter fewer matrix-core
+  // products than the four of the plain form.  Its bound is normwise of the same
+  // order, componentwise weaker in Im; in FP32 the FP64 refinement corrects it.
+  // The FP64 products that are not LU updates (U12, the refinement residual, the
+  // block products of wide solves) keep the four-product form.  Every
+  // instantiation of one kind does the same, so all tile shapes give the same bits.
+  constexpr bool GAUSS3 = sizeof(R) == 4 || MODE == 0;
   V accR[MI][NJ], accI[MI][NJ], accS[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
