@@ -657,15 +657,12 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
 
   // the products are summed on their own and subtracted from C once, in the
   // epilogue (MODE 0), so C's magnitude does not enter every rounding step.
-  // The LU updates (MODE 0) and every FP32 product form the complex product from
-  // three real ones (Gauss: T1 = Re a Re b, T2 = Im a Im b, T3 = (Re a + Im a)
-  // (Re b + Im b); Re = T1 - T2, Im = T3 - T1 - T2), a quarter fewer matrix-core
-  // products than the four of the plain form.  Its bound is normwise of the same
-  // order, componentwise weaker in Im; in FP32 the FP64 refinement corrects it.
-  // The FP64 products that are not LU updates (U12, the refinement residual, the
-  // block products of wide solves) keep the four-product form.  Every
-  // instantiation of one kind does the same, so all tile shapes give the same bits.
-  constexpr bool GAUSS3 = sizeof(R) == 4 || MODE == 0;
+  // Each complex product is formed from three real ones (Gauss: T1 = Re a Re b,
+  // T2 = Im a Im b, T3 = (Re a + Im a)(Re b + Im b); Re = T1 - T2, Im = T3 - T1 - T2),
+  // a quarter fewer matrix-core products than the four of the plain form.  Its
+  // bound is normwise of the same order, componentwise weaker in Im; the errors of
+  // the method are set by the cancellation in the pole sum, not by this rounding.
+  // Every instantiation does the same, so all tile shapes give the same bits.
   V accR[MI][NJ], accI[MI][NJ], accS[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -731,7 +728,7 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
   for (int ch = 0; ch < nchunks; ++ch) {
     const int cur = ch & 1;
     if (ch + 1 < nchunks) fetch((ch + 1) * KC);  // in flight during the products below
-    if constexpr (GAUSS3) {
+    {
       // four complex k per matrix-core step: lane (r16, kq) gives A[row r16][k kq]
       // and B[k kq][column r16]; accR, accI, accS collect T1, T2, T3
 #pragma unroll
@@ -761,45 +758,18 @@ __device__ __forceinline__ void gemm_block(int M, int N, int K, GemmOperand<R> a
             accS[i][j] = MF::run(a3[i], b3[j], accS[i][j]);
           }
       }
-    } else {
-#pragma unroll
-    for (int k2 = 0; k2 < KC / 2; ++k2) {
-      const int kc = 2 * k2 + (kq >> 1);
-      const bool odd = kq & 1;
-      R aR[MI], aI[MI], bR[NJ];
-#pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        const T av = As[cur][wm0 + i * 16 + r16][kc];
-        aR[i] = odd ? -av.y : av.x;
-        aI[i] = odd ? av.x : av.y;
-      }
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const T bv = Bs[cur][kc][wn0 + j * 16 + r16];
-        bR[j] = odd ? bv.y : bv.x;
-      }
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          accR[i][j] = MF::run(aR[i], bR[j], accR[i][j]);
-          accI[i][j] = MF::run(aI[i], bR[j], accI[i][j]);
-        }
-    }
     }
     if (ch + 1 < nchunks) stash(cur ^ 1);
     __syncthreads();
   }
-  if constexpr (GAUSS3) {
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const V t1 = accR[i][j], t2 = accI[i][j];
-        accR[i][j] = t1 - t2;
-        accI[i][j] = accS[i][j] - t1 - t2;
-      }
-  }
+    for (int j = 0; j < NJ; ++j) {
+      const V t1 = accR[i][j], t2 = accI[i][j];
+      accR[i][j] = t1 - t2;
+      accI[i][j] = accS[i][j] - t1 - t2;
+    }
   // epilogue: all C loads (clamped in range) first, then the guarded stores
   T cold[MI][NJ][4];
   if constexpr (MODE == 0) {
