@@ -40,6 +40,8 @@ constexpr int TRI_NB = 32;       // reflectors per compact-WY block of the Q for
 constexpr int TRI_KS = 16;       // most K slices of the Q formation's reductions over the rows
 constexpr int TRI_PAD = 256;     // zero rows past the n of Q and of the reflector panel (slice padding)
 constexpr int ROWS_PER_WG = 4;  // rows per workgroup of the reduction kernels (one per wave)
+constexpr int FUSED_ROWS = 8;   // rows per workgroup of the fused reduction step (one per wave)
+constexpr int FUSED_NT = 64 * FUSED_ROWS;
 
 // ---- wave reductions ----------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double x) {
@@ -242,6 +244,208 @@ __global__ __launch_bounds__(256) void k_tri_update(double2* __restrict__ A, int
     } else if (lane == 0) {
       d[n - 1] = A[(int64_t)(n - 1) * ld + (n - 1)].x;
     }
+  }
+}
+
+// Step j's rank-2 update fused with step j+1's product y' = A22' v' (one pass
+// over the trailing matrix per step instead of two).  Every workgroup first
+// forms row j+1 after step j's update (in LDS) and, from it, the reflector v' of
+// step j+1 exactly as householder_from_row does (the same arithmetic and the
+// same reduction order in every workgroup, so all copies have the same bits);
+// workgroup 0 stores v' (below the diagonal of column j+1 and into vnext) and
+// tau, e, d of step j+1.  Each wave then updates its rows j+2 .. n-1 (columns
+// j+2 .. n-1; column j+1 is left as it is, it holds the reflector) and forms
+// y'_k from the values it has just stored.  Row j+1 itself is not stored: no
+// later step reads it.  The workgroups' sums of conj(y'_k) v'_k go to part[],
+// and the last workgroup to finish adds them in a fixed order into *yvnext and
+// clears *done.
+// grid ceil((L - 1) / FUSED_ROWS) with L = n - j - 1 >= 2, block FUSED_NT (one
+// row per wave), dynamic LDS L x 16 bytes
+__global__ __launch_bounds__(FUSED_NT) void k_tri_step(double2* __restrict__ A, int64_t ld, int n, int j,
+                                                       const double2* __restrict__ v, double2* __restrict__ vnext,
+                                                       const double2* __restrict__ y, double2* __restrict__ ynext,
+                                                       const double2* __restrict__ yv, double2* __restrict__ yvnext,
+                                                       double2* __restrict__ tau, double* __restrict__ e,
+                                                       double* __restrict__ d, double2* __restrict__ part,
+                                                       unsigned* __restrict__ done) {
+  extern __shared__ double2 rowb[];  // row j+1 after the update, then v' (entry c: column j+1+c)
+  __shared__ double red[FUSED_ROWS];
+  __shared__ double2 red2[FUSED_NT];
+  __shared__ bool last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int L = n - j - 1;
+  const double2 t = tau[j];
+  const double cc = 0.5 * (t.x * t.x + t.y * t.y) * yv->x;
+  // w_c = tau y_c - cc v_c, as in k_tri_update
+  auto wof = [&](int c, double2 vc) {
+    double2 w = cmul(t, y[c]);
+    w.x -= cc * vc.x;
+    w.y -= cc * vc.y;
+    return w;
+  };
+  {
+    // four columns per pass, their loads issued together
+    const double2 v0 = v[0], w0 = wof(0, v0);
+    const double2* row1 = A + (int64_t)(j + 1) * ld + (j + 1);
+    for (int c0 = tid; c0 < L; c0 += 4 * FUSED_NT) {
+      double2 av[4], vv[4], yy[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + FUSED_NT * u < L ? c0 + FUSED_NT * u : c0;
+        av[u] = row1[c];
+        vv[u] = v[c];
+        yy[u] = y[c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + FUSED_NT * u;
+        if (c < L) {
+          const double2 vc = vv[u];
+          double2 wc = cmul(t, yy[u]);
+          wc.x -= cc * vc.x;
+          wc.y -= cc * vc.y;
+          double2 a = av[u];
+          a.x -= v0.x * wc.x + v0.y * wc.y + w0.x * vc.x + w0.y * vc.y;
+          a.y -= v0.y * wc.x - v0.x * wc.y + w0.y * vc.x - w0.x * vc.y;
+          rowb[c] = a;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // the reflector of step j+1 from x_c = conj(rowb[c]), c = 1 .. L-1
+  double sig = 0.0;
+  for (int c = 2 + tid; c < L; c += FUSED_NT) {
+    const double2 x = rowb[c];
+    sig += x.x * x.x + x.y * x.y;
+  }
+  sig = wave_sum(sig);
+  if (lane == 0) red[wave] = sig;
+  __syncthreads();
+  sig = 0.0;
+#pragma unroll
+  for (int w = 0; w < FUSED_ROWS; ++w) sig += red[w];
+  const double2 alpha = cconj(rowb[1]);
+  const double dnext = rowb[0].x;
+  double2 tn, sc;
+  double beta;
+  if (sig == 0.0 && alpha.y == 0.0) {
+    tn = czero<double2>();
+    beta = alpha.x;
+    sc = czero<double2>();
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    tn.x = (beta - alpha.x) / beta;
+    tn.y = -alpha.y / beta;
+    double2 am;  // alpha - beta
+    am.x = alpha.x - beta;
+    am.y = alpha.y;
+    sc = crecip(am);
+  }
+  __syncthreads();  // rowb[0] and rowb[1] have been read everywhere
+  for (int c = 1 + tid; c < L; c += FUSED_NT) {
+    double2 vv;
+    if (c == 1) {
+      vv.x = 1.0;
+      vv.y = 0.0;
+    } else {
+      vv = cmul(cconj(rowb[c]), sc);
+    }
+    rowb[c] = vv;
+    if (blockIdx.x == 0) {
+      A[(int64_t)(j + 1 + c) * ld + (j + 1)] = vv;
+      vnext[c - 1] = vv;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    tau[j + 1] = tn;
+    e[j + 1] = beta;
+    d[j + 1] = dnext;
+  }
+  __syncthreads();
+  // rows j+2 .. n-1: row j+1+i with i = k + 1, k = blockIdx.x * FUSED_ROWS + wave
+  double2 acc = czero<double2>();
+  {
+    const int k = blockIdx.x * FUSED_ROWS + wave;
+    if (k < L - 1) {
+      const int i = k + 1;
+      double2* row = A + (int64_t)(j + 1 + i) * ld + (j + 1);
+      const double2 vi = v[i], wi = wof(i, vi);
+      // four columns per pass (their loads issued together), four partial sums
+      double2 s4[4] = {czero<double2>(), czero<double2>(), czero<double2>(), czero<double2>()};
+      for (int c0 = 1 + lane; c0 < L; c0 += 256) {
+        double2 av[4], vv[4], yy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + 64 * u < L ? c0 + 64 * u : c0;
+          av[u] = row[c];
+          vv[u] = v[c];
+          yy[u] = y[c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + 64 * u;
+          if (c < L) {
+            const double2 vc = vv[u];
+            double2 wc = cmul(t, yy[u]);
+            wc.x -= cc * vc.x;
+            wc.y -= cc * vc.y;
+            double2 a = av[u];
+            a.x -= vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
+            a.y -= vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
+            row[c] = a;
+            const double2 vn = rowb[c];  // v'_{c-1}
+            s4[u].x += a.x * vn.x - a.y * vn.y;
+            s4[u].y += a.x * vn.y + a.y * vn.x;
+          }
+        }
+      }
+      double2 sum;
+      sum.x = (s4[0].x + s4[1].x) + (s4[2].x + s4[3].x);
+      sum.y = (s4[0].y + s4[1].y) + (s4[2].y + s4[3].y);
+      sum = wave_sum2(sum);
+      if (lane == 0) {
+        ynext[k] = sum;
+        const double2 vk = rowb[k + 1];  // v'_k
+        acc.x += sum.x * vk.x + sum.y * vk.y;  // conj(y'_k) v'_k
+        acc.y += sum.x * vk.y - sum.y * vk.x;
+      }
+    }
+  }
+  if (lane == 0) red2[wave] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double2 w = red2[0];
+    for (int k = 1; k < FUSED_ROWS; ++k) {
+      w.x += red2[k].x;
+      w.y += red2[k].y;
+    }
+    part[blockIdx.x] = w;
+    __threadfence();
+    last = atomicAdd(done, 1u) == gridDim.x - 1u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double2 q = czero<double2>();
+  for (unsigned b = tid; b < gridDim.x; b += FUSED_NT) {
+    const double2 pb = load_coherent(part + b);
+    q.x += pb.x;
+    q.y += pb.y;
+  }
+  red2[tid] = q;
+  __syncthreads();
+  for (int h = FUSED_NT / 2; h >= 1; h >>= 1) {
+    if (tid < h) {
+      red2[tid].x += red2[tid + h].x;
+      red2[tid].y += red2[tid + h].y;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *yvnext = red2[0];
+    *done = 0u;
   }
 }
 
@@ -540,9 +744,9 @@ struct expm_pfd_tri_s {
   double* e = nullptr;      // subdiagonal of T (n)
   double2* tau = nullptr;   // reflector scalars (n)
   double2* vbuf = nullptr;  // 2 x n: current and next reflector
-  double2* y = nullptr;     // n
+  double2* y = nullptr;     // 2 x n: the products of two consecutive steps
   double2* part = nullptr;  // partial sums of the reduction's products
-  double2* yv = nullptr;
+  double2* yv = nullptr;    // 2: their sums conj(y)^T v
   unsigned* done = nullptr;
   double2* Vp = nullptr;    // n x TRI_NB reflector panel
   double2* Tf = nullptr;    // TRI_NB x TRI_NB
@@ -578,7 +782,7 @@ std::vector<size_t> tri_sizes(int64_t n, int degree, int64_t m_max) {
   const int64_t np = round_up(n, 64), P = degree / 2, nt = P * 2 * m_max;
   const int64_t nwg = (n + ROWS_PER_WG - 1) / ROWS_PER_WG;
   return {(size_t)np * np * 16, (size_t)(np + TRI_PAD) * np * 16, (size_t)n * 8, (size_t)n * 8, (size_t)n * 16,
-          (size_t)2 * n * 16, (size_t)n * 16, (size_t)nwg * 16, 16, 16, (size_t)(n + TRI_PAD) * TRI_NB * 16,
+          (size_t)2 * n * 16, (size_t)2 * n * 16, (size_t)nwg * 16, 32, 16, (size_t)(n + TRI_PAD) * TRI_NB * 16,
           (size_t)TRI_NB * TRI_NB * 16, (size_t)TRI_NB * n * 16, (size_t)TRI_NB * n * 16,
           (size_t)TRI_KS * TRI_NB * n * 16, (size_t)P * 16, (size_t)P * 16, (size_t)np * m_max * 16,
           (size_t)np * m_max * 16, (size_t)n * nt * 16, (size_t)TRI_KS * n * m_max * 16, (size_t)n * nt * 16,
@@ -705,15 +909,26 @@ extern "C" int expm_pfd_tridiag_factor(expm_pfd_tri_t p, const void* A, int64_t 
                        n);
     hipLaunchKernelGGL(k_tri_order1, dim3(1), dim3(1), 0, st, p->Aw, p->d);
   } else {
+    // step 0's product, then one fused launch per step (its update and the next
+    // step's reflector and product), then the last step's update
     hipLaunchKernelGGL(k_tri_house0, dim3(1), dim3(64), 0, st, p->Aw, ld, n, p->vbuf, p->tau, p->e, p->d);
-    for (int j = 0; j + 1 < n; ++j) {
+    {
+      const unsigned g = (unsigned)((n - 1 + ROWS_PER_WG - 1) / ROWS_PER_WG);
+      hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(256), 0, st, p->Aw, ld, n, 0, p->vbuf, p->y, p->part, p->yv,
+                         p->done);
+    }
+    for (int j = 0; j + 2 < n; ++j) {
       const int L = n - j - 1;
-      const unsigned g = (unsigned)((L + ROWS_PER_WG - 1) / ROWS_PER_WG);
-      const double2* v = p->vbuf + (j & 1) * n;
-      double2* vn = p->vbuf + ((j + 1) & 1) * n;
-      hipLaunchKernelGGL(k_tri_gemv, dim3(g), dim3(256), 0, st, p->Aw, ld, n, j, v, p->y, p->part, p->yv, p->done);
-      hipLaunchKernelGGL(k_tri_update, dim3(g), dim3(256), 0, st, p->Aw, ld, n, j, v, vn, p->y, p->yv, p->tau, p->e,
-                         p->d);
+      const unsigned g = (unsigned)((L - 1 + FUSED_ROWS - 1) / FUSED_ROWS);
+      const int b = j & 1, bn = (j + 1) & 1;
+      hipLaunchKernelGGL(k_tri_step, dim3(g), dim3(FUSED_NT), (size_t)L * sizeof(double2), st, p->Aw, ld, n, j,
+                         p->vbuf + b * n, p->vbuf + bn * n, p->y + b * n, p->y + bn * n, p->yv + b, p->yv + bn,
+                         p->tau, p->e, p->d, p->part, p->done);
+    }
+    {
+      const int j = n - 2, b = j & 1;
+      hipLaunchKernelGGL(k_tri_update, dim3(1), dim3(256), 0, st, p->Aw, ld, n, j, p->vbuf + b * n,
+                         p->vbuf + ((j + 1) & 1) * n, p->y + b * n, p->yv + b, p->tau, p->e, p->d);
     }
     // Q = H_0 H_1 ... H_{n-2}, accumulated backwards in blocks of TRI_NB reflectors
     hipLaunchKernelGGL(k_tri_eye, dim3(grid_for((ld + TRI_PAD) * ld)), dim3(256), 0, st, p->Q, ld, (int)ld + TRI_PAD,

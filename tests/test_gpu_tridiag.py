@@ -76,6 +76,32 @@ def test_tridiag_parity_several_t(ep, n, spec, m, d, ts):
         assert _gate(err, A, V, t, d, eig), err
 
 
+def test_tridiag_large_order_known_eigenpairs(ep):
+    """n = 4500 (reflector rows of up to 72 KB held in LDS by the fused reduction
+    step): A of the serving workload's construction (spectrum U[-200, 0], unitary
+    from three Householder reflections and a phase diagonal), checked against the
+    oracle given those eigenpairs, with the spectrum of the computed T."""
+    import torch
+    spec = (4500, 7)
+    n = spec[0]
+    lam, U = wl.config5_eigenpairs(spec)
+    A = wl.config5_matrix(spec)
+    V = wl.complex_gaussian(np.random.default_rng(85), n, 2)
+    _announce(f"tridiag n={n} m=2 d=16 (known eigenpairs)")
+    tri = ep.expm_pfd_tridiag_plan(n, 16, 2)
+    ep.expm_pfd_tridiag_factor(tri, _dev(A))
+    dd, ee = ep.expm_pfd_tridiag_diagonals(tri)
+    mu = sl.eigvalsh_tridiagonal(dd, ee)
+    assert np.max(np.abs(np.sort(mu) - np.sort(lam))) < 1e-12 * np.max(np.abs(lam))
+    Vd = _dev(V)
+    for t in (1.0, 0.2):
+        X = ep.expm_pfd_tridiag_apply(tri, t, Vd)
+        torch.cuda.synchronize()
+        err = matrix.rel_fro(X.cpu().numpy(), matrix.expm_R(A, V, t, 16, eig=(lam, U)))
+        print(f"  t={t}: rel_fro={err:.3e}", file=sys.stderr, flush=True)
+        assert _gate(err, A, V, t, 16, (lam, U)), err
+
+
 def test_tridiag_config2_shape_and_reuse(ep):
     """The benchmarked shape (n = 2048, spectrum U[-100, 0], V 2048 x 16, degree 24):
     one reduction, then t = 1 (the LU path's workload) and two more t, each against
