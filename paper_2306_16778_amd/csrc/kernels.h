@@ -238,15 +238,28 @@ __device__ __forceinline__ void panel_column(cx<R> (&a)[S][IB], int (&pos)[S], P
     const int lane = tid & 63, wid = tid >> 6;
     const int gc = c0 + C;
     constexpr int buf = C & 1;
+    // An active row of block s >= 1 still stands for the position it was loaded
+    // at (only pivots leave, and they become inactive), so those rows are in
+    // increasing position order and a strict comparison keeps the lowest
+    // position among equal values; the row of block 0 may stand for a
+    // position past them (a row displaced by a pivot) and takes the full rule.
     R bv = -1;
     int bi = NONE, bs = 0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 1; s < S; ++s) {
       const R v = fmax(fabs(a[s][C].x) + fabs(a[s][C].y), (R)0);
-      if (pos[s] >= gc && (v > bv || (v == bv && pos[s] < bi))) {
+      if (pos[s] >= gc && v > bv) {
         bv = v;
         bi = pos[s];
         bs = s;
+      }
+    }
+    {
+      const R v = fmax(fabs(a[0][C].x) + fabs(a[0][C].y), (R)0);
+      if (pos[0] >= gc && (v > bv || (v == bv && pos[0] < bi))) {
+        bv = v;
+        bi = pos[0];
+        bs = 0;
       }
     }
     // wave candidate: maximum value, then the lowest position among the lanes
