@@ -118,6 +118,9 @@ int inner_width(int64_t npad, bool fp64) {
   if (fp64) return npad <= 2048 ? 8 : npad <= 4096 ? 4 : 2;
   return npad <= 2048 ? 16 : npad <= 4096 ? 8 : 4;
 }
+// inner width of the panels of one outer step: FP64 panels of at most 1024 rows
+// take 16 columns (two rows per thread), the others the plan's width
+int inner_width_at(int ib, int rows, bool fp64) { return fp64 && ib == 8 && rows <= 1024 ? 16 : ib; }
 
 // ---- launch helpers ---------------------------------------------------------
 
@@ -132,8 +135,8 @@ template <typename R, int IB, int S>
 void panel_launch(hipStream_t st, const PanelArgs& g, cx<R>* W) {
   const int P = g.P;
   constexpr int LIMIT = sizeof(R) == 8 ? 32 : 64;
-  // widths inner_width can choose: FP32 16/8/4, FP64 8/4/2
-  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 ? IB >= 4 : IB <= 8)) {
+  // widths inner_width and inner_width_at can choose: FP32 16/8/4, FP64 16/8/4/2
+  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 ? IB >= 4 : true)) {
     const double rows = g.npad - g.c0;
     trace::Scope ts(st, EXPM_PFD_K_PANEL, (double)P * 4.0 * rows * IB * IB,
                     (double)P * 2.0 * rows * IB * sizeof(cx<R>));
@@ -651,11 +654,12 @@ int configure_plan(expm_pfd_plan_t pl, const expm_pfd_opts* o) {
 // panels and the updates inside the outer panel.
 template <typename R>
 void panel_phase(expm_pfd_plan_t pl, int step, hipStream_t st) {
-  const int PB = pl->PB, npad = (int)pl->npad, IB = pl->IB;
+  const int PB = pl->PB, npad = (int)pl->npad;
   const int64_t ld = npad, ws = (int64_t)npad * npad;
   const int64_t mstride = (int64_t)pl->nsteps * MOVE_STRIDE;
   cx<R>* W = (cx<R>*)pl->W;
   const int j0 = step * NB, nbo = std::min(NB, npad - j0);
+  const int IB = inner_width_at(pl->IB, npad - j0, sizeof(R) == 8);
   for (int c0 = j0; c0 < j0 + nbo; c0 += IB) {
     PanelArgs g;
     g.ws = ws;

@@ -436,11 +436,18 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
   const int cnt = mv_cnt;
   // at most 2*IB moves over fewer than NB_MAX columns: MV_IT passes cover them
   constexpr int MV_IT = (2 * IB * NB_MAX + PANEL_NT - 1) / PANEL_NT;
+  // (FP64: unconditional loads, the unused ones of the matrix's first element;
+  // guarded ones put the values in scratch memory there and serialize them)
   T mvv[MV_IT];
 #pragma unroll
   for (int it = 0; it < MV_IT; ++it) {
     const int e = tid + PANEL_NT * it;
-    if (e < cnt * nother) {
+    const bool ok = e < cnt * nother;
+    if constexpr (sizeof(R) == 8) {
+      const int i = ok ? e / nother : 0, cc = ok ? e % nother : 0;
+      const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
+      mvv[it] = W[ok ? (int64_t)mv_src[i] * ld + col : 0];
+    } else if (ok) {
       const int i = e / nother, cc = e % nother;
       const int col = cc < nleft ? j0 + cc : c0 + IB + (cc - nleft);
       mvv[it] = W[(int64_t)mv_src[i] * ld + col];
@@ -467,9 +474,16 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
     const int col = c0 + IB + tid;
 #pragma unroll
     for (int i = 0; i < IB; ++i) {
-      const int sl = mv_row[i];
-      const T v = mvbuf[(sl < 0 ? 0 : sl) * NB_MAX + nleft + tid];
-      x[i] = sl >= 0 ? v : x[i];
+      if constexpr (sizeof(R) == 8) {
+        // (these threads are all in wave 0, so the move index is wave-uniform;
+        // a select of the two values puts x in scratch memory in FP64)
+        const int sl = __builtin_amdgcn_readfirstlane(mv_row[i]);
+        if (sl >= 0) x[i] = mvbuf[sl * NB_MAX + nleft + tid];
+      } else {
+        const int sl = mv_row[i];
+        const T v = mvbuf[(sl < 0 ? 0 : sl) * NB_MAX + nleft + tid];
+        x[i] = sl >= 0 ? v : x[i];
+      }
     }
 #pragma unroll
     for (int i = 1; i < IB; ++i)
