@@ -136,7 +136,7 @@ void panel_launch(hipStream_t st, const PanelArgs& g, cx<R>* W) {
   const int P = g.P;
   constexpr int LIMIT = sizeof(R) == 8 ? 32 : 64;
   // widths inner_width and inner_width_at can choose: FP32 16/8/4, FP64 16/8/4/2
-  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 ? IB >= 4 : true)) {
+  if constexpr (IB * S <= LIMIT && (sizeof(R) == 4 ? IB >= 4 && IB <= 16 : IB <= 16)) {
     const double rows = g.npad - g.c0;
     trace::Scope ts(st, EXPM_PFD_K_PANEL, (double)P * 4.0 * rows * IB * IB,
                     (double)P * 2.0 * rows * IB * sizeof(cx<R>));
