@@ -46,8 +46,8 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 # kernel reads and writes per launch hash to the digest below (the kernel, its
 # device helpers, the launcher and the factorization steps that choose the
 # launch shapes), otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 273.11e6 + 130.02e6,
-                     "sources_sha256": "e2a32e5f31302d5e151791d834f5f7118bc39891e8484fc3f6070643716c9251"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 272.98e6 + 130.02e6,
+                     "sources_sha256": "149cf986204d72e371687f4ce5d37595cceb17282f87d23bfbf08ad28c3ceee8"}}
 
 # (file, first marker, end marker) of each source span in the digest
 TRAFFIC_SPANS = (
