@@ -331,6 +331,25 @@ void block_inverse(hipStream_t st, int batch, const cx<R>* W, int64_t ws, int64_
                        which, dinv, ds);
 }
 
+// One factorization step's interchanges on the columns outside its panel, then
+// (with linv) the inverse of its L11.  Where the inverse runs as four 4-wave
+// workgroups per matrix, both go into one launch (k_moves_inverse): they touch
+// disjoint data, and the two short launches cost more apart than together.
+template <typename R>
+void moves_and_linv(hipStream_t st, int batch, cx<R>* W, int64_t ws, int64_t ld, int ncols, int gap_at, int gap_len,
+                    const int* mv, int64_t smv, int step, bool linv, cx<R>* dinv, int64_t ds) {
+  if (!linv || ncols <= 0 || batch >= 256) {
+    moves_apply<R>(st, batch, W, ws, ld, ncols, gap_at, gap_len, mv, smv, 0, 1, 0);
+    if (linv) block_inverse<R>(st, batch, W, ws, ld, step, 1, 0, dinv, ds);
+    return;
+  }
+  constexpr int CW = 32;
+  const int gm = (ncols + CW - 1) / CW;
+  trace::Scope ts(st, EXPM_PFD_K_PANEL, 8.0 * batch * NB * NB * NB / 6.0, sizeof(cx<R>) * 2.0 * batch * NB * NB);
+  hipLaunchKernelGGL((k_moves_inverse<R, CW>), dim3(gm + 4, batch), dim3(256), 0, st, W, ws, ld, ncols, gap_at,
+                     gap_len, mv, smv, gm, step, dinv, ds);
+}
+
 inline int grid_for(int64_t count) {
   int64_t g = (count + 255) / 256;
   return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
@@ -698,10 +717,9 @@ void step_update(expm_pfd_plan_t pl, int step, hipStream_t st) {
   const int j0 = step * NB, nbo = std::min(NB, npad - j0);
   const int* mv = pl->moves + (int64_t)step * MOVE_STRIDE;
   const int ntr = npad - j0 - nbo;
-  moves_apply<R>(st, PB, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, 0, 1, 0);
+  moves_and_linv<R>(st, PB, W, ws, ld, j0 + ntr, j0, nbo, mv, mstride, step, ntr > 0, dinv, ds);
   if (ntr <= 0) return;
   const int64_t c1 = j0 + nbo;
-  block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
   const cx<R>* Linv = dinv + (int64_t)step * 2 * NB * NB;
   gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, nbo, ntr, nbo, opnd<R>(Linv, ds, NB, false), opnd<R>(nullptr, 0, 0, false),
              PB, W + (int64_t)j0 * ld + c1, ws, ld, W + (int64_t)j0 * ld + c1, ws, ld);
@@ -733,9 +751,8 @@ void step_pair(expm_pfd_plan_t pl, int step, hipStream_t st) {
   const int ntr1 = npad - (int)c1, ntr2 = npad - (int)c2;
   // step j: panel, its interchanges elsewhere, L11^{-1}, U12 over every right column
   panel_phase<R>(pl, step, st);
-  moves_apply<R>(st, PB, W, ws, ld, (int)j0 + ntr1, (int)j0, NB, pl->moves + (int64_t)step * MOVE_STRIDE, mstride,
-                 0, 1, 0);
-  block_inverse<R>(st, PB, W, ws, ld, step, 1, 0, dinv, ds);
+  moves_and_linv<R>(st, PB, W, ws, ld, (int)j0 + ntr1, (int)j0, NB, pl->moves + (int64_t)step * MOVE_STRIDE, mstride,
+                    step, true, dinv, ds);
   gemm<R, 1>(st, EXPM_PFD_K_LU_TRSM, PB, NB, ntr1, NB, opnd<R>(dinv + (int64_t)step * 2 * NB * NB, ds, NB, false),
              opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c1, ws, ld, W + j0 * ld + c1, ws, ld);
   // step j's update of the columns of panel j+1
@@ -743,10 +760,9 @@ void step_pair(expm_pfd_plan_t pl, int step, hipStream_t st) {
              opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c1, ws, ld, W + c1 * ld + c1, ws, ld);
   // step j+1: panel and its interchanges on the columns left and right of it
   panel_phase<R>(pl, step + 1, st);
-  moves_apply<R>(st, PB, W, ws, ld, (int)c1 + ntr2, (int)c1, nb2,
-                 pl->moves + (int64_t)(step + 1) * MOVE_STRIDE, mstride, 0, 1, 0);
+  moves_and_linv<R>(st, PB, W, ws, ld, (int)c1 + ntr2, (int)c1, nb2, pl->moves + (int64_t)(step + 1) * MOVE_STRIDE,
+                    mstride, step + 1, ntr2 > 0, dinv, ds);
   if (ntr2 <= 0) return;
-  block_inverse<R>(st, PB, W, ws, ld, step + 1, 1, 0, dinv, ds);
   // step j's update of the rows of U12_j+1, then U12_j+1 = L11^{-1} A12
   gemm<R, 0>(st, EXPM_PFD_K_LU_GEMM, PB, nb2, ntr2, NB, opnd<R>(W + c1 * ld + j0, ws, ld, false),
              opnd<R>(nullptr, 0, 0, false), PB, W + j0 * ld + c2, ws, ld, W + c1 * ld + c2, ws, ld);

@@ -516,21 +516,17 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(cx<R>* __restrict__ Wb, int6
 // blockIdx.x encodes (step, L or U, group of 4*BIW columns).
 // ---------------------------------------------------------------------------
 template <typename R, int BIW>
-__global__ __launch_bounds__(64 * BIW) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride,
-                                                                 int64_t ld, int step0, int which,
-                                                                 cx<R>* __restrict__ dinvb, int64_t dstride) {
+__device__ __forceinline__ void block_inverse_body(int g, int b, const cx<R>* __restrict__ Wb, int64_t wstride,
+                                                   int64_t ld, int step0, int which, cx<R>* __restrict__ dinvb,
+                                                   int64_t dstride, cx<R> (*D)[NB_MAX + 1], cx<R>* rdiag) {
   using T = cx<R>;
   constexpr int NB = NB_MAX, NT = 64 * BIW, GROUPS = 16 / BIW;
   static_assert(16 % BIW == 0, "whole column groups");
-  __shared__ T D[NB][NB + 1];
-  __shared__ T rdiag[NB];
   const int nmat = which == 2 ? 2 : 1;  // which: 0 = L only, 1 = U only, 2 = both
-  const int g = blockIdx.x;
   const int wg = g % GROUPS;
   const int mat = (g / GROUPS) % nmat;
   const int step = step0 + g / (GROUPS * nmat);
   const bool upper = which == 1 || (which == 2 && mat == 1);
-  const int b = blockIdx.y;
   const T* W = Wb + b * wstride;
   const int j0 = step * NB;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -600,6 +596,15 @@ __global__ __launch_bounds__(64 * BIW) void k_block_inverse(const cx<R>* __restr
     const int r = e / CW, c = wg * CW + e % CW;
     out[r * NB + c] = D[r][c];
   }
+}
+
+template <typename R, int BIW>
+__global__ __launch_bounds__(64 * BIW) void k_block_inverse(const cx<R>* __restrict__ Wb, int64_t wstride,
+                                                                 int64_t ld, int step0, int which,
+                                                                 cx<R>* __restrict__ dinvb, int64_t dstride) {
+  __shared__ cx<R> D[NB_MAX][NB_MAX + 1];
+  __shared__ cx<R> rdiag[NB_MAX];
+  block_inverse_body<R, BIW>(blockIdx.x, blockIdx.y, Wb, wstride, ld, step0, which, dinvb, dstride, D, rdiag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1264,43 +1269,72 @@ __global__ void k_sweep_status(const int* __restrict__ ctl, int* __restrict__ in
 // moved by one launch.  grid (ceil(ncols/CW), batch)
 // ---------------------------------------------------------------------------
 template <typename R, int CW>
-__global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols, int gap_at,
-                                               int gap_len, const int* __restrict__ moves, int64_t smv, int s_begin,
-                                               int s_end, int inverse, const int* __restrict__ gate) {
+__device__ __forceinline__ void moves_body(int bx, int bb, cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols,
+                                           int gap_at, int gap_len, const int* __restrict__ moves, int64_t smv,
+                                           int s_begin, int s_end, int inverse) {
   using T = cx<R>;
-  __shared__ T Mv[MOVE_CAP][CW];
-  if (gate != nullptr && *gate == 0) return;
-  __shared__ int from_s[MOVE_CAP], to_s[MOVE_CAP];
-  __shared__ int cnt_s;
-  const int bb = blockIdx.y;
+  // each thread holds its (move, column) elements of one step in registers
+  // between the reads and the writes: the workgroup's columns are its own, so
+  // one barrier orders every read of a step before any of its writes
+  constexpr int PER = MOVE_CAP * CW / 256;
+  static_assert(MOVE_CAP * CW % 256 == 0, "whole elements per thread");
   Bm += bb * sB;
   const int* mvb = moves + bb * smv;
   const int tid = threadIdx.x;
-  const int cb = blockIdx.x * CW;
+  const int cb = bx * CW;
   const int ns = s_end - s_begin;
   for (int q = 0; q < ns; ++q) {
     const int step = inverse ? s_end - 1 - q : s_begin + q;
     const int* mv = mvb + (int64_t)step * MOVE_STRIDE;
-    if (tid == 0) cnt_s = mv[0];
-    if (tid < MOVE_CAP) {
-      from_s[tid] = inverse ? mv[1 + tid] : mv[1 + MOVE_CAP + tid];
-      to_s[tid] = inverse ? mv[1 + MOVE_CAP + tid] : mv[1 + tid];
+    const int cnt = mv[0];
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, i = e / CW, lc = cb + e % CW;
+      v[u] = czero<T>();
+      if (i < cnt && lc < ncols) {
+        const int from = inverse ? mv[1 + i] : mv[1 + MOVE_CAP + i];
+        v[u] = Bm[(int64_t)from * ldb + (lc < gap_at ? lc : lc + gap_len)];
+      }
     }
     __syncthreads();
-    const int cnt = cnt_s;
-    for (int e = tid; e < cnt * CW; e += 256) {
-      const int i = e / CW, c = e % CW;
-      const int lc = cb + c;
-      if (lc < ncols) Mv[i][c] = Bm[(int64_t)from_s[i] * ldb + (lc < gap_at ? lc : lc + gap_len)];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, i = e / CW, lc = cb + e % CW;
+      if (i < cnt && lc < ncols) {
+        const int to = inverse ? mv[1 + MOVE_CAP + i] : mv[1 + i];
+        Bm[(int64_t)to * ldb + (lc < gap_at ? lc : lc + gap_len)] = v[u];
+      }
     }
-    __syncthreads();
-    for (int e = tid; e < cnt * CW; e += 256) {
-      const int i = e / CW, c = e % CW;
-      const int lc = cb + c;
-      if (lc < ncols) Bm[(int64_t)to_s[i] * ldb + (lc < gap_at ? lc : lc + gap_len)] = Mv[i][c];
-    }
-    __syncthreads();
+    __syncthreads();  // the next step reads what this one wrote
   }
+}
+
+template <typename R, int CW>
+__global__ __launch_bounds__(256) void k_moves(cx<R>* __restrict__ Bm, int64_t sB, int64_t ldb, int ncols, int gap_at,
+                                               int gap_len, const int* __restrict__ moves, int64_t smv, int s_begin,
+                                               int s_end, int inverse, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  moves_body<R, CW>(blockIdx.x, blockIdx.y, Bm, sB, ldb, ncols, gap_at, gap_len, moves, smv, s_begin, s_end, inverse);
+}
+
+// One factorization step's interchanges on the columns outside its panel
+// (workgroups x < gmoves, CW columns each, as k_moves with one step) and the
+// inverse of its L11 (the other 4 workgroups per matrix, as k_block_inverse
+// with 4 waves and which = 0) in one launch: the two touch disjoint data (the
+// moves skip the panel's columns, the inverse reads only the panel's diagonal
+// block).  grid (gmoves + 4, batch), block 256
+template <typename R, int CW>
+__global__ __launch_bounds__(256) void k_moves_inverse(cx<R>* __restrict__ Wb, int64_t wstride, int64_t ld, int ncols,
+                                                       int gap_at, int gap_len, const int* __restrict__ moves,
+                                                       int64_t smv, int gmoves, int step,
+                                                       cx<R>* __restrict__ dinvb, int64_t dstride) {
+  __shared__ cx<R> D[NB_MAX][NB_MAX + 1];
+  __shared__ cx<R> rdiag[NB_MAX];
+  if ((int)blockIdx.x < gmoves)
+    moves_body<R, CW>(blockIdx.x, blockIdx.y, Wb, wstride, ld, ncols, gap_at, gap_len, moves, smv, 0, 1, 0);
+  else
+    block_inverse_body<R, 4>(blockIdx.x - gmoves, blockIdx.y, Wb, wstride, ld, step, 0, dinvb, dstride, D, rdiag);
 }
 
 // ---------------------------------------------------------------------------
