@@ -46,8 +46,8 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA TFLOP/s, MI355X: FP64, FP32
 # kernel reads and writes per launch hash to the digest below (the kernel, its
 # device helpers, the launcher and the factorization steps that choose the
 # launch shapes), otherwise reported null
-TRAFFIC = {"mixed": {"bytes_per_launch": 272.98e6 + 130.02e6,
-                     "sources_sha256": "149cf986204d72e371687f4ce5d37595cceb17282f87d23bfbf08ad28c3ceee8"}}
+TRAFFIC = {"mixed": {"bytes_per_launch": 272.82e6 + 130.02e6,
+                     "sources_sha256": "94c22b296649bc7387828773a3526a746f60287cbad8d6597945c93c90ac2ecd"}}
 
 # (file, first marker, end marker) of each source span in the digest
 TRAFFIC_SPANS = (
