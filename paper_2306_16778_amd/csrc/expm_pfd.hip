@@ -343,7 +343,9 @@ void moves_and_linv(hipStream_t st, int batch, cx<R>* W, int64_t ws, int64_t ld,
     if (linv) block_inverse<R>(st, batch, W, ws, ld, step, 1, 0, dinv, ds);
     return;
   }
-  constexpr int CW = 32;
+  // FP64: the inverse's LDS leaves two workgroups per CU, so wider column groups
+  // keep the moves to one round of workgroups
+  constexpr int CW = sizeof(R) == 8 ? 64 : 32;
   const int gm = (ncols + CW - 1) / CW;
   trace::Scope ts(st, EXPM_PFD_K_PANEL, 8.0 * batch * NB * NB * NB / 6.0, sizeof(cx<R>) * 2.0 * batch * NB * NB);
   hipLaunchKernelGGL((k_moves_inverse<R, CW>), dim3(gm + 4, batch), dim3(256), 0, st, W, ws, ld, ncols, gap_at,
