@@ -78,13 +78,16 @@ def test_batched_equals_alone(ep, precision):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-10)])
 def test_many_chains_sweep_equals_alone(ep, precision, tol):
-    """24 problems of one padded order: 384 sixteen-column chains per sweep, so the
+    """36 problems of one padded order: 576 sixteen-column chains per sweep, so the
     sweeps run one workgroup per chain; alone, a problem has 16 chains and runs
-    the ticketed one-launch sweep.  Both give the same bits and match the oracle."""
+    the ticketed one-launch sweep.  The batch's 288 shifted matrices also take a
+    step's row moves and its L11 inverse (16-wave workgroups) as two launches,
+    where a problem alone takes them as one (k_moves_inverse).  Both give the
+    same bits and match the oracle."""
     import torch
     rng = np.random.default_rng(9)
     probs = []
-    for k in range(24):
+    for k in range(36):
         n = 130 + 5 * (k % 12)
         A = wl.hermitian_with_spectrum(rng, rng.uniform(-50.0, 0.0, n))
         probs.append((A, wl.complex_gaussian(rng, n, 4), float(rng.uniform(0.1, 1.0))))
